@@ -1,0 +1,240 @@
+/*
+ * miloc.h -- C ABI of the MI355X ALI line radiative-transfer library (libmiloc.so).
+ *
+ * The library solves the non-LTE level populations of one molecular species
+ * in a 1D spherical cloud (nested shells) or a 3D regular Cartesian grid by
+ * alternating a deterministic ray march (radiative transfer) with per-cell
+ * statistical-equilibrium solves, as in Juvela (2020), "LOC program for line
+ * radiative transfer":
+ *   - problem statement: a model, a molecule and a fixed ray set; radiation
+ *     field and level populations iterated until converged; the final
+ *     populations kept and spectra made by a last line-of-sight integration
+ *     (Sect. 2);
+ *   - per-step radiative update and absorbed-photon counting (Sect. 2,
+ *     Eqs. (2)-(3)); the diagonal accelerated lambda iteration, A_ul scaled by
+ *     the escape probability (Sect. 2);
+ *   - 1D impact-parameter rays through shells (Sect. 2.1), 3D HEALPix ray
+ *     directions with one ray per upstream surface element and side
+ *     re-entry (Sect. 2.2).
+ *
+ * Conventions (all calls):
+ *   - Units are CGS and Kelvin.  Host arrays are row-major.
+ *   - Every call returns miloc_status: MILOC_OK (0) or a negative error code.
+ *     On error nothing is written to caller buffers and miloc_last_error()
+ *     describes the failure.  No C++ exception crosses this boundary.
+ *   - Inputs are copied before the call returns; the caller keeps ownership
+ *     of every buffer it passes.  Outputs go to caller-allocated host buffers
+ *     sized from miloc_get_sizes().  The library owns all device memory.
+ *   - A context is not thread-safe; use one context per host thread.  All
+ *     device work of a context is issued on one HIP stream (its own, or one
+ *     the caller lends at creation and keeps alive until miloc_destroy).
+ *   - Calls in the wrong order (run before a model, molecule and spectral
+ *     grid are loaded; spectra before populations exist) return MILOC_ESTATE.
+ */
+#ifndef MILOC_H
+#define MILOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MILOC_OK = 0,
+    MILOC_EINVAL = -1,   /* bad argument: NULL, size, NaN, negative physical value, band too narrow */
+    MILOC_ENOMEM = -2,   /* device or host allocation failed                                        */
+    MILOC_EDEVICE = -3,  /* HIP runtime error, or no usable gfx950 device                            */
+    MILOC_ESTATE = -4,   /* call out of order                                                        */
+    MILOC_ENOTCONV = -5, /* miloc_run reached max_iter without meeting tol (results still valid)     */
+    MILOC_ENUMERIC = -6, /* non-finite or negative populations, or a maser optical depth below -40   */
+    MILOC_EBUSY = -7     /* resource exhausted (serving: no slot / budget)                           */
+} miloc_status;
+
+typedef struct miloc_ctx miloc_ctx;
+
+/* Library version string, e.g. "miloc 0.1 gfx950". Static storage. */
+const char* miloc_version(void);
+
+/* Create a context on HIP device `hip_device`.  `hip_stream` (a hipStream_t)
+ * may be NULL: the context then creates and owns a stream of default
+ * priority.  *out receives the context.  Fails with MILOC_EDEVICE when the
+ * device does not exist or is not gfx950. */
+miloc_status miloc_create(int hip_device, void* hip_stream, miloc_ctx** out);
+
+/* Release every device and host resource of the context.  NULL is allowed. */
+void miloc_destroy(miloc_ctx* ctx);
+
+/* Text of the last error on this context (static "" when none); valid until
+ * the next call on the same context. */
+const char* miloc_last_error(const miloc_ctx* ctx);
+
+/* ---------------------------------------------------------------- molecule */
+/* Level and transition tables of the species (Sect. 2: Einstein A, B and
+ * collision coefficients; one collision partner, H2).
+ *   n_levels        number of energy levels (2..32)
+ *   E_K[n_levels]   level energy / k_B [K]
+ *   g[n_levels]     statistical weights (> 0)
+ *   n_trans         number of radiative transitions (1..n_levels*(n_levels-1)/2)
+ *   up, lo[n_trans] level indices, up > lo, distinct pairs
+ *   A[n_trans]      Einstein A_ul [s^-1] (> 0)
+ *   nu_Hz[n_trans]  rest frequency [Hz] (> 0)
+ *   gamma_down[n_levels*n_levels] downward collision rate coefficient
+ *                   [cm^3 s^-1], entry [u*n_levels + l] for u > l (other
+ *                   entries ignored); temperature independent.  Upward rates
+ *                   follow from detailed balance at the local T_kin.
+ *   mass_amu        molecular mass for the thermal line width.
+ * Loading a molecule discards populations computed with a previous one. */
+typedef struct {
+    int n_levels;
+    const double* E_K;
+    const double* g;
+    int n_trans;
+    const int* up;
+    const int* lo;
+    const double* A;
+    const double* nu_Hz;
+    const double* gamma_down;
+    double mass_amu;
+} miloc_molecule;
+
+miloc_status miloc_load_molecule(miloc_ctx* ctx, const miloc_molecule* mol);
+
+/* ------------------------------------------------------------------ models */
+/* 1D spherical model (Sect. 2.1): shell k spans (r_out[k-1], r_out[k]]
+ * (r_out[-1] = 0), with values constant inside it.
+ *   n_shells (1..65536); r_out strictly increasing, > 0 [cm];
+ *   n_H2 [cm^-3] >= 0, T_kin [K] > 0, b_turb [cm/s] >= 0 (microturbulent
+ *   Doppler parameter, added in quadrature to the thermal one),
+ *   v_r [cm/s] radial velocity (positive outwards), abundance >= 0;
+ *   n_rays (1..65536) impact-parameter rays; impact_cm NULL => equidistant
+ *   b_j = (j + 1/2) R/n_rays, else n_rays strictly increasing values in (0, R).
+ * Each ray's weight is the annulus between the mid-points of neighbouring
+ * impact parameters. */
+typedef struct {
+    int n_shells;
+    const double* r_out_cm;
+    const double* n_H2;
+    const double* T_kin;
+    const double* b_turb_cms;
+    const double* v_r_cms;
+    const double* abundance;
+    int n_rays;
+    const double* impact_cm;
+} miloc_model1d;
+
+/* 3D regular model (Sect. 2.2 with the grid unrefined): n0[0] = n0[1] =
+ * n0[2] = N (2..1024) cubic cells of side root_cell_cm.  Cell (x, y, z) is
+ * stored at index (z*N + y)*N + x.  n_oct_levels must be 0 (octrees are not
+ * accepted by this version: MILOC_EINVAL); n_cells_per_level and first_child
+ * are then ignored.  Per-cell float fields as in miloc_model1d plus the
+ * velocity vector (vx, vy, vz) [cm/s]. */
+typedef struct {
+    int n0[3];
+    int n_oct_levels;
+    double root_cell_cm;
+    const int64_t* n_cells_per_level;
+    const int32_t* const* first_child;
+    const float* n_H2;
+    const float* T_kin;
+    const float* b_turb_cms;
+    const float* vx;
+    const float* vy;
+    const float* vz;
+    const float* abundance;
+} miloc_model3d;
+
+/* Loading a model replaces the previous one (1D or 3D) and its populations. */
+miloc_status miloc_load_model_1d(miloc_ctx* ctx, const miloc_model1d* model);
+miloc_status miloc_load_model_3d(miloc_ctx* ctx, const miloc_model3d* model);
+
+/* Velocity channels (Sect. 2: a regular velocity grid per ray):
+ * centres v_c = v_min + (c + 1/2) dv, c = 0..n_channels-1 (8..4096).  The
+ * band must contain every cell's line out to 5 Doppler widths at any
+ * projected velocity (checked at miloc_run: MILOC_EINVAL). */
+miloc_status miloc_set_spectral(miloc_ctx* ctx, int n_channels, double v_min_cms, double dv_cms);
+
+/* Isotropic background B_nu(T_bg) entering at every ray start (Sect. 2,
+ * Eq. (1)).  Default 2.73 K.  T_bg >= 0 (0 => no background). */
+miloc_status miloc_set_background(miloc_ctx* ctx, double T_bg_K);
+
+/* 3D ray directions: the 12*nside^2 HEALPix pixel centres (Sect. 2.2; 48 for
+ * nside = 2, the default).  nside 1..8. */
+miloc_status miloc_set_directions_healpix(miloc_ctx* ctx, int nside);
+
+/* 3D ray directions given explicitly: n_dir (1..1024) vectors, dirs[3*n_dir],
+ * normalised by the library (zero vectors: MILOC_EINVAL).  Each direction
+ * stands for a solid angle 4 pi / n_dir. */
+miloc_status miloc_set_directions(miloc_ctx* ctx, int n_dir, const double* dirs);
+
+/* Arithmetic of the ray march: MILOC_MARCH_FP32 (default; FP32 intensities,
+ * FP64 accumulation) or MILOC_MARCH_FP64 (everything in FP64). */
+typedef enum { MILOC_MARCH_FP32 = 0, MILOC_MARCH_FP64 = 1 } miloc_march_precision;
+miloc_status miloc_set_march_precision(miloc_ctx* ctx, int precision);
+
+/* ------------------------------------------------------------- iteration */
+/* Populations = Boltzmann distribution at T_kin in every cell (LTE start,
+ * Sect. 3.3.2).  Needs a model and a molecule. */
+miloc_status miloc_init_lte(miloc_ctx* ctx);
+
+/* Populations from the caller: x[n_cells*n_levels], cell-major; each row is
+ * renormalised to sum 1; negative or non-finite entries => MILOC_EINVAL.
+ * Together with miloc_get_populations this is the checkpoint/resume pair. */
+miloc_status miloc_set_populations(miloc_ctx* ctx, const double* x);
+
+/* Run up to max_iter (>= 1) iterations.  One iteration = for every
+ * transition, march all rays with the current populations and accumulate
+ * the absorbed counts and the diagonal operator per cell; then solve the
+ * statistical equilibrium of every cell (FP64); then the convergence test
+ * delta = max |x_new - x_old| / x_new over x_new >= 1e-10 (FP64, on the
+ * device).  use_ali != 0 selects the ALI form (Sect. 2), 0 the plain lambda
+ * iteration.  Stops early when delta < tol (tol <= 0: never).  Populations
+ * are initialised to LTE if none are set.  iters_done / last_delta may be
+ * NULL.  Returns MILOC_ENOTCONV when tol > 0 was not met (state is valid). */
+miloc_status miloc_run(miloc_ctx* ctx, int max_iter, double tol, int use_ali,
+                       int* iters_done, double* last_delta);
+
+/* Sizes of the loaded problem (any pointer may be NULL). */
+miloc_status miloc_get_sizes(const miloc_ctx* ctx, int64_t* n_cells, int* n_levels,
+                             int* n_trans, int* n_channels);
+
+/* Current populations x[n_cells*n_levels] (cell-major). */
+miloc_status miloc_get_populations(miloc_ctx* ctx, double* x_out);
+
+/* Radiation terms of the last iteration, each [n_trans*n_cells]
+ * (transition-major): J = mean intensity of the external field weighted by
+ * the line profile [erg s^-1 cm^-2 Hz^-1 sr^-1] (with the plain lambda
+ * iteration: the full field), lambda = diagonal operator (1 - escape
+ * probability).  Either pointer may be NULL. */
+miloc_status miloc_get_radiation(miloc_ctx* ctx, double* J_out, double* lambda_out);
+
+/* Spectra of transition `trans` from the current populations by a final
+ * line-of-sight march (Sect. 2), dI = I - I_bg per channel
+ * [erg s^-1 cm^-2 Hz^-1 sr^-1], dI_out[n_los*n_channels].
+ *   1D: n_los rays at impact parameters impact_cm[n_los] (in [0, R)), or the
+ *       model's own ray set when impact_cm is NULL (n_los must then equal
+ *       n_rays).
+ *   3D: a map towards +z, one line of sight per (x, y) cell column through
+ *       the cell centres; n_los must be N*N, index y*N + x; impact_cm NULL. */
+miloc_status miloc_get_spectra(miloc_ctx* ctx, int trans, int n_los, const double* impact_cm,
+                               double* dI_out);
+
+/* Counters since the last reset (miloc_reset_counters). */
+typedef struct {
+    int64_t iterations;          /* ALI/LI iterations run                                    */
+    int64_t march_launches;      /* launches of the ray-march kernel                          */
+    double march_ms;             /* summed device time of those launches (HIP events)        */
+    double prepare_ms;           /* populations -> opacity/emissivity kernels                */
+    double solve_ms;             /* statistical equilibrium + convergence kernels            */
+    double ray_steps;            /* ray-cell steps per transition, summed over launches      */
+    double channel_updates;      /* ray_steps x n_channels (nominal, window not subtracted)  */
+} miloc_counters;
+
+miloc_status miloc_get_counters(const miloc_ctx* ctx, miloc_counters* out);
+miloc_status miloc_reset_counters(miloc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MILOC_H */

@@ -1,0 +1,30 @@
+// geometry.h -- host-side ray geometry (see geometry.cpp).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace miloc {
+
+// 12*nside^2 unit vectors (x, y, z interleaved), HEALPix RING order.
+std::vector<double> healpix_directions(int nside);
+
+// Axis (0, 1, 2) of the largest |component|; near-ties -> lowest index.
+int main_axis(const double* d);
+
+// Step list of the representative ray of one regular-grid direction.
+struct DirPattern {
+    int m = 2, a = 0, b = 1;          // main and transverse axes (a < b)
+    double aw = 1.0;                  // |d_m|
+    std::vector<double> len;          // step lengths (cell units)
+    std::vector<int> flags;           // moves before each step: 1 m, 2 a, 4 b
+    std::vector<double> layer_len;    // path length per layer (from the upstream face)
+};
+DirPattern regular_pattern(const double* d, int N);
+
+// 1D ray-sampled volumes W_k = sum_j area_j * (path of ray j in shell k).
+void shell_weights(int n, const double* R, int nrays, const double* b, const double* area,
+                   double* W, int64_t* nsteps_total);
+
+}  // namespace miloc

@@ -1,0 +1,533 @@
+// kernels.hip -- gfx950 kernels of the ALI line ray march.
+//
+//   prepare   populations -> per (transition, cell) opacity/emissivity (khat, ehat)
+//   lte       Boltzmann populations at T_kin
+//   march3d   3D regular grid: HEALPix directions, one ray per upstream surface
+//             cell, side re-entry with background; per step and channel the
+//             radiative update and the absorbed-count / diagonal-operator sums
+//   march1d   1D shells: impact-parameter rays, geometry on the fly (FP64)
+//   se        per-cell statistical equilibrium (FP64 partial-pivot elimination)
+//             and the maximum relative population change
+//
+// Lane mapping of the marches: a ray owns a group of LANES (32 or 64) lanes of
+// one wavefront; the lanes cover the channel window of the current step,
+// |v_c + w| <= K b, so only channels where the local profile is significantly
+// non-zero are touched (App. A.2).  The ray's full channel vector lives in LDS.
+// Per step the group reduces its two partial sums in registers and one lane
+// issues two FP64 atomic adds.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "miloc_internal.h"
+
+namespace miloc {
+
+namespace {
+
+constexpr float kLog2eF = 1.4426950408889634f;
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double fast_exp2(double x) { return exp2(x); }
+
+// 1 - beta and e^{-tau}, beta = (1 - e^{-tau})/tau (Sect. 2, Eqs. (2)-(3)).
+// Small |tau|: Taylor series of 1 - beta (no cancellation); else direct.
+__device__ __forceinline__ void escape_terms(float tau, float& omb, float& e)
+{
+    if (fabsf(tau) < 0.2f) {
+        float h = (1.0f / 720.0f) - tau * (1.0f / 5040.0f);
+        h = (1.0f / 120.0f) - tau * h;
+        h = (1.0f / 24.0f) - tau * h;
+        h = (1.0f / 6.0f) - tau * h;
+        h = 0.5f - tau * h;
+        omb = tau * h;
+        e = (1.0f - tau) + tau * omb;
+    } else {
+        e = fast_exp2(-tau * kLog2eF);
+        const float beta = (1.0f - e) * __builtin_amdgcn_rcpf(tau);
+        omb = 1.0f - beta;
+    }
+}
+
+__device__ __forceinline__ void escape_terms(double tau, double& omb, double& e)
+{
+    if (fabs(tau) < 1.0e-3) {
+        double h = (1.0 / 120.0) - tau * (1.0 / 720.0);
+        h = (1.0 / 24.0) - tau * h;
+        h = (1.0 / 6.0) - tau * h;
+        h = 0.5 - tau * h;
+        omb = tau * h;
+        e = (1.0 - tau) + tau * omb;
+    } else {
+        e = exp(-tau);
+        omb = 1.0 + expm1(-tau) / tau;
+    }
+}
+
+template <int LANES, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LANES);
+    return v;
+}
+
+// Radiative update of one step over the channel window.  Lanes take channels
+// clo + lane, clo + lane + LANES, ...  Returns the partial sums
+// sum e_c I_c beta_c and sum e_c (1 - beta_c) of this lane.
+template <int LANES, typename T>
+__device__ __forceinline__ void step_channels(T* __restrict__ I, int lane, int clo, int chi,
+                                              T frac, T ibs, T kl, T el, T& sj, T& sl)
+{
+    for (int c = clo + lane; c <= chi; c += LANES) {
+        const T xs = ((T)(c - clo) + frac) * ibs;
+        const T ec = fast_exp2(-xs * xs);
+        const T tau = kl * ec;
+        T omb, e;
+        escape_terms(tau, omb, e);
+        const T Iin = I[c];
+        const T u = ec - ec * omb;          // e_c beta_c
+        sj += Iin * u;
+        sl += ec * omb;
+        I[c] = Iin * e + el * u;
+    }
+}
+
+// Channel window [clo, chi] of a step: channels with |c - c*| <= Kw/ibs,
+// c* = -(chalf + w), clipped to the band.  frac = clo - c*.
+template <typename T>
+__device__ __forceinline__ void window(double w, double chalf, T Kw, T ibs, int nch,
+                                       int& clo, int& chi, T& frac)
+{
+    const double cstar = -(chalf + w);
+    const double hw = (double)(Kw / ibs);
+    int lo = (int)ceil(cstar - hw);
+    int hi = (int)floor(cstar + hw);
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > nch - 1 ? nch - 1 : hi;
+    clo = lo;
+    chi = hi;
+    frac = (T)((double)lo - cstar);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- prepare
+// With ibg_sub (spectra) the emission term becomes ehat - I_bg khat, so that the
+// march carries I - I_bg directly: I_out - I_bg = (I_in - I_bg) e^-tau
+// + (ehat - I_bg khat) len e_c beta, without cancellation where I ~ I_bg.
+template <typename T>
+__global__ void prepare_kernel(int nc, const MolDev* __restrict__ mol, int ntr,
+                               const double* __restrict__ x, const double* __restrict__ nmolLb,
+                               const double* __restrict__ ibg_sub,
+                               typename V2<T>::type* __restrict__ ke)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const int L = mol->L;
+    const double* xk = x + (size_t)k * L;
+    const double base = nmolLb[k];
+    for (int t = 0; t < ntr; ++t) {
+        const double xu = xk[mol->up[t]];
+        const double xl = xk[mol->lo[t]];
+        const double f = base * mol->Ct[t];
+        const double kap = f * (xl * mol->gratio[t] - xu);   // kappa term
+        double eta = f * xu;                                   // eta term (occupation units)
+        if (ibg_sub) eta -= ibg_sub[t] * kap;
+        typename V2<T>::type v;
+        v.x = (T)kap;
+        v.y = (T)eta;
+        ke[(size_t)t * nc + k] = v;
+    }
+}
+
+__global__ void lte_kernel(int nc, const MolDev* __restrict__ mol, const double* __restrict__ Tkin,
+                           double* __restrict__ x)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const int L = mol->L;
+    const double T = Tkin[k];
+    double s = 0.0;
+    for (int i = 0; i < L; ++i) s += mol->g[i] * exp(-mol->E[i] / T);
+    const double inv = 1.0 / s;
+    for (int i = 0; i < L; ++i) x[(size_t)k * L + i] = mol->g[i] * exp(-mol->E[i] / T) * inv;
+}
+
+// ---------------------------------------------------------------- 3D march
+template <typename T, int LANES, bool ACCUM>
+__global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
+{
+    using T2 = typename V2<T>::type;
+    using T4 = typename V4<T>::type;
+    const int rpb = blockDim.x / LANES;
+    const int lane = threadIdx.x % LANES;
+    const int rib = threadIdx.x / LANES;
+    // Consecutive workgroups are dealt round-robin to the 8 XCDs; remap so that
+    // each XCD walks a contiguous range of rays (neighbouring rays of one
+    // direction share cells and hence L2 lines).
+    int bid = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+    const int q = bid / p.blocks_per_dir;
+    const int r = (bid - q * p.blocks_per_dir) * rpb + rib;
+    const int t = p.trans_offset + blockIdx.y;
+    extern __shared__ unsigned char smem_raw[];
+    T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)rib * p.nch;
+    if (r >= p.rays_per_dir) return;
+
+    const DirDev D = p.dirs[q];
+    const int N = p.N;
+    const int i0 = r % N, j0 = r / N;
+    int ca = i0, cb = j0;
+    int idx = D.start_off + i0 * D.sta + j0 * D.stb;
+    const T Ibg = p.Ibg[t];
+    const size_t tb = (size_t)t * p.nc;
+    const StepRec<T>* __restrict__ st = p.steps + D.step0;
+    const T aw = (T)D.aw;
+
+    for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+
+    for (int s = 0; s < D.nsteps; ++s) {
+        const StepRec<T> rec = st[s];
+        bool restart = false;
+        if (rec.flags & 1) idx += D.stride_m;
+        if (rec.flags & 2) {
+            if (D.sa > 0) {
+                if (ca == N - 1) { ca = 0; idx -= (N - 1) * D.sta; restart = true; }
+                else { ++ca; idx += D.sta; }
+            } else {
+                if (ca == 0) { ca = N - 1; idx += (N - 1) * D.sta; restart = true; }
+                else { --ca; idx -= D.sta; }
+            }
+        }
+        if (rec.flags & 4) {
+            if (D.sb > 0) {
+                if (cb == N - 1) { cb = 0; idx -= (N - 1) * D.stb; restart = true; }
+                else { ++cb; idx += D.stb; }
+            } else {
+                if (cb == 0) { cb = N - 1; idx += (N - 1) * D.stb; restart = true; }
+                else { --cb; idx -= D.stb; }
+            }
+        }
+        if (restart) {
+            // Side exit: the ray re-enters on the opposite face carrying the
+            // background again (Sect. 2.2).
+            for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+        }
+        const T4 cv = p.cellv[idx];
+        const T2 kev = p.ke[tb + idx];
+        const double w = (double)cv.x * D.d[0] + (double)cv.y * D.d[1] + (double)cv.z * D.d[2];
+        int clo, chi;
+        T frac;
+        window<T>(w, p.chalf, p.Kw, cv.w, p.nch, clo, chi, frac);
+        T sj = 0, sl = 0;
+        step_channels<LANES, T>(I, lane, clo, chi, frac, cv.w, kev.x * rec.len,
+                                kev.y * rec.len, sj, sl);
+        if (ACCUM) {
+            sj = group_sum<LANES>(sj);
+            sl = group_sum<LANES>(sl);
+            if (lane == 0) {
+                const double wgt = (double)(aw * rec.len);
+                unsafeAtomicAdd(&p.acc[tb + idx].x, wgt * (double)sj);
+                unsafeAtomicAdd(&p.acc[tb + idx].y, wgt * (double)sl);
+            }
+        }
+    }
+    if (!ACCUM && p.Iout) {
+        T* out = p.Iout + ((size_t)q * p.rays_per_dir + r) * p.nch;
+        for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
+    }
+}
+
+// ---------------------------------------------------------------- 1D march
+template <typename T, int LANES, bool ACCUM>
+__global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
+{
+    using T2 = typename V2<T>::type;
+    const int rpb = blockDim.x / LANES;
+    const int lane = threadIdx.x % LANES;
+    const int rib = threadIdx.x / LANES;
+    const int j = blockIdx.x * rpb + rib;
+    const int t = p.trans_offset + blockIdx.y;
+    extern __shared__ unsigned char smem_raw[];
+    T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)rib * p.nch;
+    if (j >= p.nrays) return;
+
+    const int n = p.n;
+    const double* __restrict__ R = p.R;
+    const double b = p.bimp[j];
+    const double a = p.area[j];
+    // innermost shell reached: first k with R[k] > b
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (R[mid] > b) hi = mid; else lo = mid + 1;
+    }
+    const int kmin = lo;
+    const int nin = n - 1 - kmin;
+    const int nsteps = 2 * nin + 2;
+    const T Ibg = p.Ibg[t];
+    const size_t tb = (size_t)t * n;
+    for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+
+    double zprev = sqrt((R[n - 1] - b) * (R[n - 1] + b));
+    for (int s = 0; s < nsteps; ++s) {
+        int k;
+        double len, mu;
+        if (s < nin) {                       // inwards through shell k
+            k = n - 1 - s;
+            const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
+            len = zprev - zi;
+            mu = -zprev / R[k];
+            zprev = zi;
+        } else if (s == nin) {               // tangent shell, first half
+            k = kmin;
+            len = zprev;
+            mu = -zprev / R[k];
+        } else if (s == nin + 1) {           // tangent shell, second half
+            k = kmin;
+            len = zprev;
+            mu = 0.0;
+        } else {                             // outwards through shell k
+            k = kmin + (s - nin - 1);
+            const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
+            const double zo = sqrt((R[k] - b) * (R[k] + b));
+            len = zo - zi;
+            mu = zi / R[k - 1];
+        }
+        const T2 sv = p.shellv[k];
+        const T2 kev = p.ke[tb + k];
+        const double w = (double)sv.x * mu;
+        int clo, chi;
+        T frac;
+        window<T>(w, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
+        const T tl = (T)len;
+        T sj = 0, sl = 0;
+        step_channels<LANES, T>(I, lane, clo, chi, frac, sv.y, kev.x * tl, kev.y * tl, sj, sl);
+        if (ACCUM) {
+            sj = group_sum<LANES>(sj);
+            sl = group_sum<LANES>(sl);
+            if (lane == 0) {
+                const double wgt = a * len;
+                unsafeAtomicAdd(&p.acc[tb + k].x, wgt * (double)sj);
+                unsafeAtomicAdd(&p.acc[tb + k].y, wgt * (double)sl);
+            }
+        }
+    }
+    if (!ACCUM && p.Iout) {
+        T* out = p.Iout + (size_t)j * p.nch;
+        for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
+    }
+}
+
+// ---------------------------------------------------------------- SE solve
+// One thread per cell.  The (L+1) x L augmented matrix lives in LDS with the
+// thread index fastest, M[(row*(L+1) + col)*bs + tid].
+__global__ void se_kernel(SEArgs p)
+{
+    extern __shared__ double sm[];
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x * blockDim.x + tid;
+    const int bs = p.bs;
+    const MolDev* __restrict__ mol = p.mol;
+    const int L = p.L;
+    const int W = L + 1;
+    double* M = sm;                                    // L*W*bs
+    double* bz = sm + (size_t)L * W * bs;              // L*bs Boltzmann factors
+#define MM(i, j) M[((i) * W + (j)) * bs + tid]
+#define BZ(i) bz[(i) * bs + tid]
+    double dmax = 0.0;
+    if (k < p.nc) {
+        const double* xo = p.x_old + (size_t)k * L;
+        const double nH2 = p.nH2[k];
+        const double T = p.Tkin[k];
+        const double q = p.q[k];
+
+        for (int i = 0; i < L; ++i) {
+            for (int j = 0; j < W; ++j) MM(i, j) = 0.0;
+            BZ(i) = mol->g[i] * exp(-mol->E[i] / T);
+        }
+        // collisions, every pair u > l; upward rate by detailed balance
+        for (int u = 1; u < L; ++u) {
+            for (int l = 0; l < u; ++l) {
+                const double gam = mol->gamma[u * L + l];
+                if (gam == 0.0) continue;
+                const double Cul = nH2 * gam;
+                const double Clu = Cul * BZ(u) / BZ(l);
+                MM(l, u) += Cul;  MM(u, u) -= Cul;
+                MM(u, l) += Clu;  MM(l, l) -= Clu;
+            }
+        }
+        // radiative rates with the absorbed counts in place of B I (Sect. 2);
+        // ALI: A scaled by the escape probability 1 - Lambda
+        for (int t = 0; t < p.ntr; ++t) {
+            const int u = mol->up[t], l = mol->lo[t];
+            const double A = mol->A[t];
+            const double2 a = p.acc[(size_t)t * p.nc + k];
+            double J = a.x * q;
+            const double Lam = a.y * q;
+            double Rul;
+            if (p.use_ali) {
+                Rul = A * (1.0 - Lam) + A * J;
+            } else {
+                const double den = xo[l] * mol->gratio[t] - xo[u];
+                const double S = den != 0.0 ? xo[u] / den : 0.0;
+                J += S * Lam;
+                Rul = A + A * J;
+            }
+            const double Rlu = mol->gratio[t] * A * J;
+            MM(l, u) += Rul;  MM(u, u) -= Rul;
+            MM(u, l) += Rlu;  MM(l, l) -= Rlu;
+        }
+        // replace the equation of the most populated level by sum x = 1
+        int r = 0;
+        for (int i = 1; i < L; ++i) if (xo[i] > xo[r]) r = i;
+        for (int j = 0; j < L; ++j) MM(r, j) = 1.0;
+        MM(r, L) = 1.0;
+        // Gaussian elimination with partial pivoting
+        for (int c = 0; c < L; ++c) {
+            int piv = c;
+            double best = fabs(MM(c, c));
+            for (int i = c + 1; i < L; ++i) {
+                const double v = fabs(MM(i, c));
+                if (v > best) { best = v; piv = i; }
+            }
+            if (piv != c)
+                for (int j = c; j < W; ++j) {
+                    const double tmp = MM(c, j); MM(c, j) = MM(piv, j); MM(piv, j) = tmp;
+                }
+            const double inv = 1.0 / MM(c, c);
+            for (int i = c + 1; i < L; ++i) {
+                const double f = MM(i, c) * inv;
+                if (f == 0.0) continue;
+                for (int j = c + 1; j < W; ++j) MM(i, j) -= f * MM(c, j);
+            }
+        }
+        for (int i = L - 1; i >= 0; --i) {
+            double s = MM(i, L);
+            for (int j = i + 1; j < L; ++j) s -= MM(i, j) * MM(j, L);
+            MM(i, L) = s / MM(i, i);
+        }
+        bool bad = false;
+        for (int i = 0; i < L; ++i) {
+            const double xi = MM(i, L);
+            p.x_new[(size_t)k * L + i] = xi;
+            if (!(xi == xi) || xi < -1.0e-12 || fabs(xi) > 2.0) bad = true;
+            if (xi >= 1.0e-10) {
+                const double d = fabs(xi - xo[i]) / xi;
+                dmax = d > dmax ? d : dmax;
+            }
+        }
+        if (bad) atomicAdd(p.bad, 1u);
+    }
+#undef MM
+#undef BZ
+    // positive doubles order like their bit patterns
+    const int width = bs < 64 ? bs : 64;
+    unsigned long long bits = (unsigned long long)__double_as_longlong(dmax);
+    for (int o = width >> 1; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(bits, o, width);
+        bits = other > bits ? other : bits;
+    }
+    if ((tid % width) == 0 && bits != 0ull) atomicMax(p.delta_bits, bits);
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_prepare(hipStream_t s, int nc, const MolDev* mol, int ntr, const double* x,
+                          const double* nmolLb, const double* ibg_sub, void* ke, bool fp64)
+{
+    const int bs = 256;
+    const int nb = (nc + bs - 1) / bs;
+    if (fp64)
+        hipLaunchKernelGGL(prepare_kernel<double>, dim3(nb), dim3(bs), 0, s, nc, mol, ntr, x, nmolLb,
+                           ibg_sub, reinterpret_cast<double2*>(ke));
+    else
+        hipLaunchKernelGGL(prepare_kernel<float>, dim3(nb), dim3(bs), 0, s, nc, mol, ntr, x, nmolLb,
+                           ibg_sub, reinterpret_cast<float2*>(ke));
+    return hipGetLastError();
+}
+
+hipError_t launch_lte(hipStream_t s, int nc, const MolDev* mol, const double* Tkin, double* x)
+{
+    const int bs = 256;
+    hipLaunchKernelGGL(lte_kernel, dim3((nc + bs - 1) / bs), dim3(bs), 0, s, nc, mol, Tkin, x);
+    return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+int rays_per_block(int lanes, int nch)
+{
+    int rpb = 256 / lanes;
+    while (rpb > 1 && (size_t)rpb * nch * sizeof(T) > 65536) rpb >>= 1;
+    return rpb;
+}
+
+template <typename T, int LANES, bool ACCUM>
+hipError_t do_march3d(hipStream_t s, March3DArgs<T> a)
+{
+    const int rpb = rays_per_block<T>(LANES, a.nch);
+    a.blocks_per_dir = (a.rays_per_dir + rpb - 1) / rpb;
+    const dim3 grid(a.blocks_per_dir * a.n_dir, a.ntr);
+    const size_t shm = (size_t)rpb * a.nch * sizeof(T);
+    hipLaunchKernelGGL((march3d_kernel<T, LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int LANES, bool ACCUM>
+hipError_t do_march1d(hipStream_t s, const March1DArgs<T>& a)
+{
+    const int rpb = rays_per_block<T>(LANES, a.nch);
+    const dim3 grid((a.nrays + rpb - 1) / rpb, a.ntr);
+    const size_t shm = (size_t)rpb * a.nch * sizeof(T);
+    hipLaunchKernelGGL((march1d_kernel<T, LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch3d(hipStream_t s, const March3DArgs<T>& a, int lanes, bool accum)
+{
+    if (lanes == 32) return accum ? do_march3d<T, 32, true>(s, a) : do_march3d<T, 32, false>(s, a);
+    return accum ? do_march3d<T, 64, true>(s, a) : do_march3d<T, 64, false>(s, a);
+}
+
+template <typename T>
+hipError_t dispatch1d(hipStream_t s, const March1DArgs<T>& a, int lanes, bool accum)
+{
+    if (lanes == 32) return accum ? do_march1d<T, 32, true>(s, a) : do_march1d<T, 32, false>(s, a);
+    return accum ? do_march1d<T, 64, true>(s, a) : do_march1d<T, 64, false>(s, a);
+}
+}  // namespace
+
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum)
+{
+    return dispatch3d<float>(s, a, lanes, accum);
+}
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum)
+{
+    return dispatch3d<double>(s, a, lanes, accum);
+}
+hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum)
+{
+    return dispatch1d<float>(s, a, lanes, accum);
+}
+hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes, bool accum)
+{
+    return dispatch1d<double>(s, a, lanes, accum);
+}
+
+hipError_t launch_se(hipStream_t s, const SEArgs& a0)
+{
+    SEArgs a = a0;
+    // LDS per thread: (L*(L+1) + L) doubles; block size = the largest power
+    // of two (<= 256) that keeps the block within 64 KB.
+    const size_t per = (size_t)(a.L * (a.L + 1) + a.L) * sizeof(double);
+    int bs = 256;
+    while (bs > 1 && per * bs > 65536) bs >>= 1;
+    a.bs = bs;
+    const size_t shm = per * bs;
+    hipLaunchKernelGGL(se_kernel, dim3((a.nc + bs - 1) / bs), dim3(bs), shm, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace miloc

@@ -1,0 +1,118 @@
+// miloc_internal.h -- shared definitions of the host runtime and the gfx950 kernels.
+//
+// Internal units (chosen so that every FP32 quantity of the march is O(1)):
+//   * intensities are photon occupation numbers, I' = I / (2 h nu^3 / c^2), so
+//     B_ul J = A J' and B_lu J = (g_u/g_l) A J' in the equilibrium equations;
+//   * lengths are in "march units": the cell size for 3D grids, the outer
+//     radius for 1D models;
+//   * velocities are in channel units (v / dv), and the line-profile argument is
+//     carried as x * sqrt(log2 e) so that exp(-x^2) = exp2(-xs^2).
+// With these, a step of length len in cell k contributes
+//   tau_c = khat * len * e_c,  emission = ehat * len * e_c * beta_c,
+//   e_c = exp(-((v_c + w)/b)^2),
+// where khat, ehat carry kappa/(b sqrt(pi)) and eta/(b sqrt(pi)) times the
+// length unit (Sect. 2, Eq. (3) in intensity form).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace miloc {
+
+constexpr int kMaxLevels = 32;
+constexpr int kMaxTrans = kMaxLevels * (kMaxLevels - 1) / 2;
+
+// Molecule constants on the device (read through uniform loads).
+struct MolDev {
+    int L, T;
+    double E[kMaxLevels];        // E_i / k_B - min E  [K]
+    double g[kMaxLevels];
+    double gamma[kMaxLevels * kMaxLevels];   // [u*L + l], u > l
+    int up[kMaxTrans], lo[kMaxTrans];
+    double A[kMaxTrans];
+    double gratio[kMaxTrans];    // g_u / g_l
+    double Ct[kMaxTrans];        // c^3 A / (8 pi nu^3) [cm^3 s^-1 ... per unit n_mol]
+};
+
+// One 3D ray direction of the regular-grid march.  All N*N rays of a
+// direction share one crossing pattern (same fractional transverse offset),
+// stored as a list of steps of the representative ray.
+struct DirDev {
+    double d[3];          // unit propagation vector
+    double aw;            // |d_m|: ray cross-section per unit face area
+    int sa, sb;           // move direction (+1/-1) along the transverse axes a, b
+    int sta, stb;         // memory stride of one cell along a, b (positive)
+    int stride_m;         // signed memory offset of one move along the main axis
+    int start_off;        // memory offset of the start cell of ray (0, 0)
+    int step0, nsteps;    // slice of the step table
+};
+
+template <typename T>
+struct StepRec {
+    T len;                // path length in cell units
+    int flags;            // moves before this step: 1 = main axis, 2 = axis a, 4 = axis b
+};
+
+template <typename T> struct V2;
+template <> struct V2<float> { using type = float2; };
+template <> struct V2<double> { using type = double2; };
+template <typename T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+
+template <typename T>
+struct March3DArgs {
+    int N, nc, nch, ntr;
+    int rays_per_dir, blocks_per_dir, n_dir;
+    const DirDev* dirs;
+    const StepRec<T>* steps;
+    const typename V4<T>::type* cellv;   // {Ux, Uy, Uz, ibs} per cell
+    const typename V2<T>::type* ke;      // [ntr][nc] {khat, ehat}
+    const T* Ibg;                        // [ntr], occupation units
+    double2* acc;                        // [ntr][nc] raw {J, Lambda} sums
+    double chalf;                        // 1/2 + v_min/dv
+    T Kw;                                // window half width * ibs (channels * ibs)
+    T* Iout;                             // spectra: [n_dir*rays][nch] or null
+    int trans_offset;                    // first transition of this launch
+};
+
+template <typename T>
+struct March1DArgs {
+    int n, nrays, nch, ntr;
+    const double* R;                     // outer radii / R_out
+    const double* bimp;                  // impact parameters / R_out
+    const double* area;                  // ray weights / R_out^2
+    const typename V2<T>::type* shellv;  // {Ur, ibs} per shell
+    const typename V2<T>::type* ke;      // [ntr][n]
+    const T* Ibg;                        // [ntr]
+    double2* acc;                        // [ntr][n]
+    double chalf;
+    T Kw;
+    T* Iout;                             // spectra: [nrays][nch] or null
+    int trans_offset;
+};
+
+struct SEArgs {
+    int nc, L, ntr, use_ali, bs;
+    const MolDev* mol;
+    const double* x_old;                 // [nc][L]
+    double* x_new;                       // [nc][L]
+    const double* nH2;                   // [nc]
+    const double* Tkin;                  // [nc]
+    const double* q;                     // [nc] dv / (b sqrt(pi) W)
+    const double2* acc;                  // [ntr][nc]
+    unsigned long long* delta_bits;      // max relative change (as double bits)
+    unsigned int* bad;                   // numeric-failure counter
+};
+
+// Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_prepare(hipStream_t s, int nc, const MolDev* mol, int ntr, const double* x,
+                          const double* nmolLb, const double* ibg_sub, void* ke, bool fp64);
+hipError_t launch_lte(hipStream_t s, int nc, const MolDev* mol, const double* Tkin, double* x);
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum);
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum);
+hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum);
+hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes, bool accum);
+hipError_t launch_se(hipStream_t s, const SEArgs& a);
+
+}  // namespace miloc

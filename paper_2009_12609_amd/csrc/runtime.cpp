@@ -1,0 +1,972 @@
+// runtime.cpp -- the C ABI of libmiloc (include/miloc.h): context state, input
+// validation, device buffers and the iteration driver (Sect. 2: alternate the
+// ray march and the equilibrium solve until the populations converge).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "geometry.h"
+#include "miloc.h"
+#include "miloc_internal.h"
+
+using namespace miloc;
+
+namespace {
+
+// CODATA-2018 exact h, k_B, c (CGS); atomic mass unit.
+constexpr double kH = 6.62607015e-27;
+constexpr double kK = 1.380649e-16;
+constexpr double kC = 2.99792458e10;
+constexpr double kAmu = 1.66053906660e-24;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtLog2e = 1.2011224087864498;   // sqrt(log2(e))
+// Channel window half-widths in Doppler widths: the profile beyond is below
+// e^-25 (FP32) / e^-42 (FP64) of its peak, i.e. far below the arithmetic's
+// rounding level.
+constexpr double kWindowK32 = 5.0;
+constexpr double kWindowK64 = 6.5;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n == 0) n = 8;
+        if (p && bytes == n) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) { p = nullptr; return e; }
+        bytes = n;
+        return hipSuccess;
+    }
+    template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct Status {
+    miloc_status code;
+};
+
+}  // namespace
+
+struct miloc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    hipEvent_t ev[6] = {};
+
+    // molecule
+    bool has_mol = false;
+    int L = 0, T = 0;
+    std::vector<double> E, g, A, nu, gamma;
+    std::vector<int> up, lo;
+    double mass_amu = 0;
+
+    // model
+    int kind = 0;   // 1: 1D shells, 3: 3D regular grid
+    int64_t nc = 0;
+    std::vector<double> R, nH2, Tk, bt, vr, X, impact;   // 1D (FP64)
+    int nrays = 0;
+    int N = 0;
+    double delta = 0;
+    std::vector<float> f_nH2, f_T, f_bt, f_vx, f_vy, f_vz, f_X;   // 3D
+
+    // settings
+    bool has_spec = false;
+    int nch = 0;
+    double vmin = 0, dv = 0;
+    double Tbg = 2.73;
+    std::vector<double> dirs;
+    int precision = MILOC_MARCH_FP32;
+
+    // device state
+    bool dirty = true;        // static buffers need a rebuild
+    bool base_ready = false;  // molecule + per-cell base arrays uploaded
+    bool has_pops = false;
+    bool has_rad = false;
+    DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
+        d_zero, d_dirs, d_steps, d_flags, d_R, d_bimp, d_area;
+    std::vector<double> Iscale, Ibg;   // per transition: 2 h nu^3 / c^2, background (occupation)
+    std::vector<double> q_host;
+    int lanes = 32;
+    double steps_per_trans = 0;
+    double chalf = 0;
+    double Kw = 0;
+    int n_dir_dev = 0;
+    std::vector<DirDev> dir_host;
+
+    miloc_counters ctr{};
+};
+
+namespace {
+
+miloc_status fail(miloc_ctx* c, miloc_status code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return fail((ctx), _e == hipErrorOutOfMemory ? MILOC_ENOMEM : MILOC_EDEVICE,     \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));                 \
+    } while (0)
+
+bool finite_all(const double* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+bool finite_all(const float* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+template <typename T>
+bool nonneg_all(const T* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!(a[i] >= 0)) return false;
+    return true;
+}
+template <typename T>
+bool positive_all(const T* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!(a[i] > 0)) return false;
+    return true;
+}
+
+double doppler_b(double T, double bturb, double mass_amu)
+{
+    return std::sqrt(2.0 * kK * T / (mass_amu * kAmu) + bturb * bturb);
+}
+
+// Per-cell fields as FP64 regardless of model type.
+struct CellView {
+    const miloc_ctx* c;
+    double nH2(int64_t k) const { return c->kind == 1 ? c->nH2[k] : (double)c->f_nH2[k]; }
+    double T(int64_t k) const { return c->kind == 1 ? c->Tk[k] : (double)c->f_T[k]; }
+    double bt(int64_t k) const { return c->kind == 1 ? c->bt[k] : (double)c->f_bt[k]; }
+    double X(int64_t k) const { return c->kind == 1 ? c->X[k] : (double)c->f_X[k]; }
+};
+
+// Molecule and per-cell base arrays (needs molecule + model).
+miloc_status ensure_base(miloc_ctx* c)
+{
+    if (!c->has_mol || c->kind == 0) return fail(c, MILOC_ESTATE, "molecule and model must be loaded first");
+    if (c->base_ready) return MILOC_OK;
+    MolDev m;
+    std::memset(&m, 0, sizeof(m));
+    m.L = c->L;
+    m.T = c->T;
+    const double Emin = *std::min_element(c->E.begin(), c->E.end());
+    for (int i = 0; i < c->L; ++i) {
+        m.E[i] = c->E[i] - Emin;
+        m.g[i] = c->g[i];
+    }
+    for (int u = 0; u < c->L; ++u)
+        for (int l = 0; l < u; ++l) m.gamma[u * c->L + l] = c->gamma[(size_t)u * c->L + l];
+    for (int t = 0; t < c->T; ++t) {
+        m.up[t] = c->up[t];
+        m.lo[t] = c->lo[t];
+        m.A[t] = c->A[t];
+        m.gratio[t] = c->g[c->up[t]] / c->g[c->lo[t]];
+        m.Ct[t] = kC * kC * kC * c->A[t] / (8.0 * kPi * c->nu[t] * c->nu[t] * c->nu[t]);
+    }
+    HIPCHK(c, c->d_mol.ensure(sizeof(MolDev)));
+    HIPCHK(c, hipMemcpy(c->d_mol.p, &m, sizeof(MolDev), hipMemcpyHostToDevice));
+    const int64_t nc = c->nc;
+    std::vector<double> a(nc), b(nc);
+    CellView cv{c};
+    for (int64_t k = 0; k < nc; ++k) { a[k] = cv.nH2(k); b[k] = cv.T(k); }
+    HIPCHK(c, c->d_nH2.ensure(nc * sizeof(double)));
+    HIPCHK(c, c->d_T.ensure(nc * sizeof(double)));
+    HIPCHK(c, hipMemcpy(c->d_nH2.p, a.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_T.p, b.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, c->d_x.ensure((size_t)nc * c->L * sizeof(double)));
+    HIPCHK(c, c->d_xnew.ensure((size_t)nc * c->L * sizeof(double)));
+    HIPCHK(c, c->d_flags.ensure(16));
+    c->Iscale.resize(c->T);
+    for (int t = 0; t < c->T; ++t) c->Iscale[t] = 2.0 * kH * std::pow(c->nu[t], 3) / (kC * kC);
+    c->base_ready = true;
+    return MILOC_OK;
+}
+
+template <typename TT>
+void pack_cell_static(miloc_ctx* c, const std::vector<double>& b, std::vector<char>& out)
+{
+    const int64_t nc = c->nc;
+    const double ibs_f = c->dv * kSqrtLog2e;
+    if (c->kind == 3) {
+        using T4 = typename V4<TT>::type;
+        out.resize(nc * sizeof(T4));
+        T4* v = reinterpret_cast<T4*>(out.data());
+        for (int64_t k = 0; k < nc; ++k) {
+            v[k].x = (TT)((double)c->f_vx[k] / c->dv);
+            v[k].y = (TT)((double)c->f_vy[k] / c->dv);
+            v[k].z = (TT)((double)c->f_vz[k] / c->dv);
+            v[k].w = (TT)(ibs_f / b[k]);
+        }
+    } else {
+        using T2 = typename V2<TT>::type;
+        out.resize(nc * sizeof(T2));
+        T2* v = reinterpret_cast<T2*>(out.data());
+        for (int64_t k = 0; k < nc; ++k) {
+            v[k].x = (TT)(c->vr[k] / c->dv);
+            v[k].y = (TT)(ibs_f / b[k]);
+        }
+    }
+}
+
+template <typename TT>
+miloc_status upload_steps(miloc_ctx* c, const std::vector<double>& len, const std::vector<int>& fl)
+{
+    std::vector<StepRec<TT>> st(len.size());
+    for (size_t i = 0; i < len.size(); ++i) {
+        st[i].len = (TT)len[i];
+        st[i].flags = fl[i];
+    }
+    HIPCHK(c, c->d_steps.ensure(std::max<size_t>(1, st.size()) * sizeof(StepRec<TT>)));
+    HIPCHK(c, hipMemcpy(c->d_steps.p, st.data(), st.size() * sizeof(StepRec<TT>),
+                        hipMemcpyHostToDevice));
+    return MILOC_OK;
+}
+
+// Build the direction table and step patterns for a list of directions.
+void build_patterns(int N, const std::vector<double>& dirs, std::vector<DirDev>& dd,
+                    std::vector<double>& len, std::vector<int>& fl, std::vector<DirPattern>* keep)
+{
+    const int nd = (int)dirs.size() / 3;
+    const int64_t stride[3] = {1, N, (int64_t)N * N};
+    dd.assign(nd, DirDev{});
+    len.clear();
+    fl.clear();
+    for (int q = 0; q < nd; ++q) {
+        const double* d = &dirs[3 * q];
+        DirPattern P = regular_pattern(d, N);
+        DirDev& D = dd[q];
+        D.d[0] = d[0]; D.d[1] = d[1]; D.d[2] = d[2];
+        D.aw = P.aw;
+        D.sa = d[P.a] >= 0 ? 1 : -1;
+        D.sb = d[P.b] >= 0 ? 1 : -1;
+        D.sta = (int)stride[P.a];
+        D.stb = (int)stride[P.b];
+        const bool fwd = d[P.m] > 0;
+        D.stride_m = fwd ? (int)stride[P.m] : -(int)stride[P.m];
+        D.start_off = fwd ? 0 : (int)((N - 1) * stride[P.m]);
+        D.step0 = (int)len.size();
+        D.nsteps = (int)P.len.size();
+        len.insert(len.end(), P.len.begin(), P.len.end());
+        fl.insert(fl.end(), P.flags.begin(), P.flags.end());
+        if (keep) keep->push_back(std::move(P));
+    }
+}
+
+// Everything the march needs beyond the base arrays (needs the spectral grid).
+miloc_status ensure_static(miloc_ctx* c)
+{
+    miloc_status st = ensure_base(c);
+    if (st != MILOC_OK) return st;
+    if (!c->has_spec) return fail(c, MILOC_ESTATE, "spectral grid not set");
+    if (!c->dirty) return MILOC_OK;
+    const bool fp64 = c->precision == MILOC_MARCH_FP64;
+    const int64_t nc = c->nc;
+    CellView cv{c};
+    std::vector<double> b(nc);
+    double maxu = 0, maxb = 0;
+    for (int64_t k = 0; k < nc; ++k) {
+        b[k] = doppler_b(cv.T(k), cv.bt(k), c->mass_amu);
+        maxb = std::max(maxb, b[k]);
+        double u;
+        if (c->kind == 3) {
+            const double ux = c->f_vx[k], uy = c->f_vy[k], uz = c->f_vz[k];
+            u = std::sqrt(ux * ux + uy * uy + uz * uz);
+        } else {
+            u = std::fabs(c->vr[k]);
+        }
+        maxu = std::max(maxu, u + 5.0 * b[k]);
+    }
+    const double vmax = c->vmin + c->nch * c->dv;
+    if (-maxu < c->vmin || maxu > vmax) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf,
+                      "velocity band [%g, %g] cm/s does not contain |v| + 5 b = %g cm/s",
+                      c->vmin, vmax, maxu);
+        return fail(c, MILOC_EINVAL, buf);
+    }
+    const double Kd = fp64 ? kWindowK64 : kWindowK32;
+    c->Kw = Kd * kSqrtLog2e;
+    c->chalf = 0.5 + c->vmin / c->dv;
+    // widest window over the cells decides lanes per ray
+    double minb = b[0];
+    for (int64_t k = 0; k < nc; ++k) minb = std::min(minb, b[k]);
+    (void)minb;
+    const double wmax = 2.0 * Kd * maxb / c->dv + 2.0;
+    c->lanes = wmax <= 32.0 ? 32 : 64;
+
+    // geometry, weights W (in march length units) and q = dv/(b sqrt(pi) W)
+    std::vector<double> W(nc, 0.0);
+    double Lunit;
+    if (c->kind == 3) {
+        const int N = c->N;
+        Lunit = c->delta;
+        std::vector<DirDev> dd;
+        std::vector<double> len;
+        std::vector<int> fl;
+        std::vector<DirPattern> pats;
+        build_patterns(N, c->dirs, dd, len, fl, &pats);
+        // W(cell) = sum over directions of aw * (path per ray in the cell's layer)
+        std::vector<double> Wax[3];
+        for (int a = 0; a < 3; ++a) Wax[a].assign(N, 0.0);
+        double steps = 0;
+        for (size_t q = 0; q < pats.size(); ++q) {
+            const DirPattern& P = pats[q];
+            const bool fwd = c->dirs[3 * q + P.m] > 0;
+            for (int l = 0; l < N; ++l) Wax[P.m][fwd ? l : N - 1 - l] += P.aw * P.layer_len[l];
+            steps += (double)P.len.size() * N * N;
+        }
+        for (int z = 0; z < N; ++z)
+            for (int y = 0; y < N; ++y)
+                for (int x = 0; x < N; ++x)
+                    W[((int64_t)z * N + y) * N + x] = Wax[0][x] + Wax[1][y] + Wax[2][z];
+        c->steps_per_trans = steps;
+        c->dir_host = dd;
+        c->n_dir_dev = (int)dd.size();
+        HIPCHK(c, c->d_dirs.ensure(dd.size() * sizeof(DirDev)));
+        HIPCHK(c, hipMemcpy(c->d_dirs.p, dd.data(), dd.size() * sizeof(DirDev), hipMemcpyHostToDevice));
+        st = fp64 ? upload_steps<double>(c, len, fl) : upload_steps<float>(c, len, fl);
+        if (st != MILOC_OK) return st;
+    } else {
+        const int n = (int)c->nc;
+        Lunit = c->R[n - 1];
+        std::vector<double> Rn(n), bn(c->nrays), an(c->nrays);
+        for (int k = 0; k < n; ++k) Rn[k] = c->R[k] / Lunit;
+        Rn[n - 1] = 1.0;
+        for (int j = 0; j < c->nrays; ++j) bn[j] = c->impact[j] / Lunit;
+        // ray weights: annulus between the mid-points of neighbouring impact parameters
+        for (int j = 0; j < c->nrays; ++j) {
+            const double e0 = j == 0 ? 0.0 : 0.5 * (bn[j] + bn[j - 1]);
+            const double e1 = j == c->nrays - 1 ? 1.0 : 0.5 * (bn[j] + bn[j + 1]);
+            an[j] = kPi * (e1 * e1 - e0 * e0);
+        }
+        int64_t steps = 0;
+        shell_weights(n, Rn.data(), c->nrays, bn.data(), an.data(), W.data(), &steps);
+        c->steps_per_trans = (double)steps;
+        HIPCHK(c, c->d_R.ensure(n * sizeof(double)));
+        HIPCHK(c, c->d_bimp.ensure(c->nrays * sizeof(double)));
+        HIPCHK(c, c->d_area.ensure(c->nrays * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->d_R.p, Rn.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->d_bimp.p, bn.data(), c->nrays * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->d_area.p, an.data(), c->nrays * sizeof(double), hipMemcpyHostToDevice));
+    }
+    std::vector<double> q(nc), nmolLb(nc);
+    for (int64_t k = 0; k < nc; ++k) {
+        const double bs = b[k] * std::sqrt(kPi);
+        q[k] = W[k] > 0 ? c->dv / (bs * W[k]) : 0.0;
+        nmolLb[k] = cv.nH2(k) * cv.X(k) * Lunit / bs;
+    }
+    c->q_host = q;
+    HIPCHK(c, c->d_q.ensure(nc * sizeof(double)));
+    HIPCHK(c, c->d_nmolLb.ensure(nc * sizeof(double)));
+    HIPCHK(c, hipMemcpy(c->d_q.p, q.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_nmolLb.p, nmolLb.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<char> cvb;
+    if (fp64) pack_cell_static<double>(c, b, cvb); else pack_cell_static<float>(c, b, cvb);
+    HIPCHK(c, c->d_cellv.ensure(cvb.size()));
+    HIPCHK(c, hipMemcpy(c->d_cellv.p, cvb.data(), cvb.size(), hipMemcpyHostToDevice));
+    const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+    HIPCHK(c, c->d_ke.ensure((size_t)c->T * nc * 2 * tsz));
+    HIPCHK(c, c->d_acc.ensure((size_t)c->T * nc * sizeof(double2)));
+    c->Ibg.resize(c->T);
+    std::vector<char> ib(c->T * tsz);
+    for (int t = 0; t < c->T; ++t) {
+        const double xx = c->Tbg > 0 ? kH * c->nu[t] / (kK * c->Tbg) : INFINITY;
+        c->Ibg[t] = std::isfinite(xx) ? 1.0 / std::expm1(xx) : 0.0;
+        if (fp64) reinterpret_cast<double*>(ib.data())[t] = c->Ibg[t];
+        else reinterpret_cast<float*>(ib.data())[t] = (float)c->Ibg[t];
+    }
+    HIPCHK(c, c->d_Ibg.ensure(ib.size()));
+    HIPCHK(c, hipMemcpy(c->d_Ibg.p, ib.data(), ib.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, c->d_Ibg64.ensure(c->T * sizeof(double)));
+    HIPCHK(c, hipMemcpy(c->d_Ibg64.p, c->Ibg.data(), c->T * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, c->d_zero.ensure(c->T * sizeof(double)));
+    HIPCHK(c, hipMemset(c->d_zero.p, 0, c->T * sizeof(double)));
+    c->dirty = false;
+    return MILOC_OK;
+}
+
+void invalidate_model(miloc_ctx* c)
+{
+    c->base_ready = false;
+    c->dirty = true;
+    c->has_pops = false;
+    c->has_rad = false;
+}
+
+template <typename TT>
+miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, bool zdir,
+                          const DirDev* d_dirs_override, const void* steps_override, int nd_override,
+                          const double* bimp_override, int nrays_override)
+{
+    hipError_t e;
+    if (c->kind == 3) {
+        March3DArgs<TT> a{};
+        a.N = c->N;
+        a.nc = (int)c->nc;
+        a.nch = c->nch;
+        a.ntr = ntr;
+        a.trans_offset = toff;
+        a.rays_per_dir = c->N * c->N;
+        a.n_dir = zdir ? nd_override : c->n_dir_dev;
+        a.dirs = zdir ? d_dirs_override : c->d_dirs.as<DirDev>();
+        a.steps = zdir ? reinterpret_cast<const StepRec<TT>*>(steps_override) : c->d_steps.as<StepRec<TT>>();
+        a.cellv = c->d_cellv.as<typename V4<TT>::type>();
+        a.ke = c->d_ke.as<typename V2<TT>::type>();
+        a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
+        a.acc = c->d_acc.as<double2>();
+        a.chalf = c->chalf;
+        a.Kw = (TT)c->Kw;
+        a.Iout = Iout;
+        e = launch_march3d(c->stream, a, c->lanes, accum);
+    } else {
+        March1DArgs<TT> a{};
+        a.n = (int)c->nc;
+        a.nrays = bimp_override ? nrays_override : c->nrays;
+        a.nch = c->nch;
+        a.ntr = ntr;
+        a.trans_offset = toff;
+        a.R = c->d_R.as<double>();
+        a.bimp = bimp_override ? bimp_override : c->d_bimp.as<double>();
+        a.area = bimp_override ? bimp_override : c->d_area.as<double>();
+        a.shellv = c->d_cellv.as<typename V2<TT>::type>();
+        a.ke = c->d_ke.as<typename V2<TT>::type>();
+        a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
+        a.acc = c->d_acc.as<double2>();
+        a.chalf = c->chalf;
+        a.Kw = (TT)c->Kw;
+        a.Iout = Iout;
+        e = launch_march1d(c->stream, a, c->lanes, accum);
+    }
+    HIPCHK(c, e);
+    return MILOC_OK;
+}
+
+miloc_status check_ctx(miloc_ctx* c)
+{
+    if (!c) return MILOC_EINVAL;
+    c->err.clear();
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return fail(c, MILOC_EDEVICE, hipGetErrorString(e));
+    return MILOC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* miloc_version(void) { return "miloc 0.1 gfx950"; }
+
+miloc_status miloc_create(int hip_device, void* hip_stream, miloc_ctx** out)
+{
+    if (!out) return MILOC_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MILOC_EDEVICE;
+    if (hip_device < 0 || hip_device >= n) return MILOC_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return MILOC_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MILOC_EDEVICE;
+    if (hipSetDevice(hip_device) != hipSuccess) return MILOC_EDEVICE;
+    miloc_ctx* c = new (std::nothrow) miloc_ctx();
+    if (!c) return MILOC_ENOMEM;
+    c->device = hip_device;
+    if (hip_stream) {
+        c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return MILOC_EDEVICE; }
+        c->own_stream = true;
+    }
+    for (auto& ev : c->ev)
+        if (hipEventCreate(&ev) != hipSuccess) { miloc_destroy(c); return MILOC_EDEVICE; }
+    c->dirs = healpix_directions(2);
+    *out = c;
+    return MILOC_OK;
+}
+
+void miloc_destroy(miloc_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* miloc_last_error(const miloc_ctx* c)
+{
+    return c ? c->err.c_str() : "";
+}
+
+miloc_status miloc_load_molecule(miloc_ctx* c, const miloc_molecule* m)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!m || !m->E_K || !m->g || !m->up || !m->lo || !m->A || !m->nu_Hz || !m->gamma_down)
+        return fail(c, MILOC_EINVAL, "NULL molecule field");
+    const int L = m->n_levels, T = m->n_trans;
+    if (L < 2 || L > kMaxLevels) return fail(c, MILOC_EINVAL, "n_levels out of range 2..32");
+    if (T < 1 || T > L * (L - 1) / 2) return fail(c, MILOC_EINVAL, "n_trans out of range");
+    if (!finite_all(m->E_K, L) || !positive_all(m->g, L) || !finite_all(m->g, L))
+        return fail(c, MILOC_EINVAL, "bad level energies or weights");
+    if (!positive_all(m->A, T) || !positive_all(m->nu_Hz, T) || !finite_all(m->A, T) ||
+        !finite_all(m->nu_Hz, T))
+        return fail(c, MILOC_EINVAL, "A and nu must be positive and finite");
+    if (!(m->mass_amu > 0) || !std::isfinite(m->mass_amu)) return fail(c, MILOC_EINVAL, "bad mass");
+    std::vector<char> seen((size_t)L * L, 0);
+    for (int t = 0; t < T; ++t) {
+        const int u = m->up[t], l = m->lo[t];
+        if (u < 0 || u >= L || l < 0 || l >= u) return fail(c, MILOC_EINVAL, "transition needs 0 <= lo < up < n_levels");
+        if (seen[(size_t)u * L + l]) return fail(c, MILOC_EINVAL, "duplicate transition");
+        seen[(size_t)u * L + l] = 1;
+    }
+    for (int u = 0; u < L; ++u)
+        for (int l = 0; l < u; ++l) {
+            const double gm = m->gamma_down[(size_t)u * L + l];
+            if (!(gm >= 0) || !std::isfinite(gm)) return fail(c, MILOC_EINVAL, "bad collision coefficient");
+        }
+    c->L = L;
+    c->T = T;
+    c->E.assign(m->E_K, m->E_K + L);
+    c->g.assign(m->g, m->g + L);
+    c->up.assign(m->up, m->up + T);
+    c->lo.assign(m->lo, m->lo + T);
+    c->A.assign(m->A, m->A + T);
+    c->nu.assign(m->nu_Hz, m->nu_Hz + T);
+    c->gamma.assign(m->gamma_down, m->gamma_down + (size_t)L * L);
+    c->mass_amu = m->mass_amu;
+    c->has_mol = true;
+    invalidate_model(c);
+    return MILOC_OK;
+}
+
+miloc_status miloc_load_model_1d(miloc_ctx* c, const miloc_model1d* m)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!m || !m->r_out_cm || !m->n_H2 || !m->T_kin || !m->b_turb_cms || !m->v_r_cms || !m->abundance)
+        return fail(c, MILOC_EINVAL, "NULL model field");
+    const int n = m->n_shells;
+    if (n < 1 || n > 65536) return fail(c, MILOC_EINVAL, "n_shells out of range 1..65536");
+    if (m->n_rays < 1 || m->n_rays > 65536) return fail(c, MILOC_EINVAL, "n_rays out of range 1..65536");
+    if (!positive_all(m->r_out_cm, n) || !finite_all(m->r_out_cm, n))
+        return fail(c, MILOC_EINVAL, "radii must be positive and finite");
+    for (int k = 1; k < n; ++k)
+        if (!(m->r_out_cm[k] > m->r_out_cm[k - 1])) return fail(c, MILOC_EINVAL, "radii must increase");
+    if (!nonneg_all(m->n_H2, n) || !finite_all(m->n_H2, n) || !positive_all(m->T_kin, n) ||
+        !finite_all(m->T_kin, n) || !nonneg_all(m->b_turb_cms, n) || !finite_all(m->b_turb_cms, n) ||
+        !finite_all(m->v_r_cms, n) || !nonneg_all(m->abundance, n) || !finite_all(m->abundance, n))
+        return fail(c, MILOC_EINVAL, "negative or non-finite shell values");
+    const double Rout = m->r_out_cm[n - 1];
+    std::vector<double> imp(m->n_rays);
+    if (m->impact_cm) {
+        for (int j = 0; j < m->n_rays; ++j) {
+            imp[j] = m->impact_cm[j];
+            if (!(imp[j] > 0 && imp[j] < Rout) || (j > 0 && !(imp[j] > imp[j - 1])))
+                return fail(c, MILOC_EINVAL, "impact parameters must increase inside (0, R)");
+        }
+    } else {
+        for (int j = 0; j < m->n_rays; ++j) imp[j] = (j + 0.5) * Rout / m->n_rays;
+    }
+    c->kind = 1;
+    c->nc = n;
+    c->R.assign(m->r_out_cm, m->r_out_cm + n);
+    c->nH2.assign(m->n_H2, m->n_H2 + n);
+    c->Tk.assign(m->T_kin, m->T_kin + n);
+    c->bt.assign(m->b_turb_cms, m->b_turb_cms + n);
+    c->vr.assign(m->v_r_cms, m->v_r_cms + n);
+    c->X.assign(m->abundance, m->abundance + n);
+    c->nrays = m->n_rays;
+    c->impact = imp;
+    c->f_nH2.clear(); c->f_T.clear(); c->f_bt.clear(); c->f_vx.clear(); c->f_vy.clear();
+    c->f_vz.clear(); c->f_X.clear();
+    invalidate_model(c);
+    return MILOC_OK;
+}
+
+miloc_status miloc_load_model_3d(miloc_ctx* c, const miloc_model3d* m)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!m || !m->n_H2 || !m->T_kin || !m->b_turb_cms || !m->vx || !m->vy || !m->vz || !m->abundance)
+        return fail(c, MILOC_EINVAL, "NULL model field");
+    if (m->n_oct_levels != 0) return fail(c, MILOC_EINVAL, "octree models are not supported by this version");
+    const int N = m->n0[0];
+    if (N < 2 || N > 1024 || m->n0[1] != N || m->n0[2] != N)
+        return fail(c, MILOC_EINVAL, "grid must be N^3 with 2 <= N <= 1024");
+    if (!(m->root_cell_cm > 0) || !std::isfinite(m->root_cell_cm)) return fail(c, MILOC_EINVAL, "bad cell size");
+    const int64_t nc = (int64_t)N * N * N;
+    if (!nonneg_all(m->n_H2, nc) || !finite_all(m->n_H2, nc) || !positive_all(m->T_kin, nc) ||
+        !finite_all(m->T_kin, nc) || !nonneg_all(m->b_turb_cms, nc) || !finite_all(m->b_turb_cms, nc) ||
+        !finite_all(m->vx, nc) || !finite_all(m->vy, nc) || !finite_all(m->vz, nc) ||
+        !nonneg_all(m->abundance, nc) || !finite_all(m->abundance, nc))
+        return fail(c, MILOC_EINVAL, "negative or non-finite cell values");
+    c->kind = 3;
+    c->nc = nc;
+    c->N = N;
+    c->delta = m->root_cell_cm;
+    c->f_nH2.assign(m->n_H2, m->n_H2 + nc);
+    c->f_T.assign(m->T_kin, m->T_kin + nc);
+    c->f_bt.assign(m->b_turb_cms, m->b_turb_cms + nc);
+    c->f_vx.assign(m->vx, m->vx + nc);
+    c->f_vy.assign(m->vy, m->vy + nc);
+    c->f_vz.assign(m->vz, m->vz + nc);
+    c->f_X.assign(m->abundance, m->abundance + nc);
+    c->R.clear(); c->nH2.clear(); c->Tk.clear(); c->bt.clear(); c->vr.clear(); c->X.clear();
+    invalidate_model(c);
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_spectral(miloc_ctx* c, int n_channels, double v_min_cms, double dv_cms)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (n_channels < 8 || n_channels > 4096) return fail(c, MILOC_EINVAL, "n_channels out of range 8..4096");
+    if (!std::isfinite(v_min_cms) || !(dv_cms > 0) || !std::isfinite(dv_cms))
+        return fail(c, MILOC_EINVAL, "bad channel grid");
+    c->nch = n_channels;
+    c->vmin = v_min_cms;
+    c->dv = dv_cms;
+    c->has_spec = true;
+    c->dirty = true;
+    c->has_rad = false;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_background(miloc_ctx* c, double T_bg_K)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!(T_bg_K >= 0) || !std::isfinite(T_bg_K)) return fail(c, MILOC_EINVAL, "T_bg must be >= 0");
+    c->Tbg = T_bg_K;
+    c->dirty = true;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_directions_healpix(miloc_ctx* c, int nside)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (nside < 1 || nside > 8) return fail(c, MILOC_EINVAL, "nside out of range 1..8");
+    c->dirs = healpix_directions(nside);
+    c->dirty = true;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_directions(miloc_ctx* c, int n_dir, const double* dirs)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (n_dir < 1 || n_dir > 1024 || !dirs) return fail(c, MILOC_EINVAL, "n_dir out of range 1..1024");
+    std::vector<double> d(3 * (size_t)n_dir);
+    for (int q = 0; q < n_dir; ++q) {
+        const double x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
+        const double nrm = std::sqrt(x * x + y * y + z * z);
+        if (!(nrm > 0) || !std::isfinite(nrm)) return fail(c, MILOC_EINVAL, "zero or non-finite direction");
+        d[3 * q] = x / nrm; d[3 * q + 1] = y / nrm; d[3 * q + 2] = z / nrm;
+    }
+    c->dirs = d;
+    c->dirty = true;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_march_precision(miloc_ctx* c, int precision)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (precision != MILOC_MARCH_FP32 && precision != MILOC_MARCH_FP64)
+        return fail(c, MILOC_EINVAL, "precision must be MILOC_MARCH_FP32 or MILOC_MARCH_FP64");
+    if (precision != c->precision) {
+        c->precision = precision;
+        c->dirty = true;
+    }
+    return MILOC_OK;
+}
+
+miloc_status miloc_init_lte(miloc_ctx* c)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    s = ensure_base(c);
+    if (s) return s;
+    HIPCHK(c, launch_lte(c->stream, (int)c->nc, c->d_mol.as<MolDev>(), c->d_T.as<double>(), c->d_x.as<double>()));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_pops = true;
+    c->has_rad = false;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_populations(miloc_ctx* c, const double* x)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!x) return fail(c, MILOC_EINVAL, "NULL populations");
+    s = ensure_base(c);
+    if (s) return s;
+    const size_t n = (size_t)c->nc * c->L;
+    std::vector<double> h(x, x + n);
+    for (int64_t k = 0; k < c->nc; ++k) {
+        double sum = 0;
+        for (int i = 0; i < c->L; ++i) {
+            const double v = h[(size_t)k * c->L + i];
+            if (!(v >= 0) || !std::isfinite(v)) return fail(c, MILOC_EINVAL, "populations must be finite and >= 0");
+            sum += v;
+        }
+        if (!(sum > 0)) return fail(c, MILOC_EINVAL, "a cell has all-zero populations");
+        for (int i = 0; i < c->L; ++i) h[(size_t)k * c->L + i] /= sum;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_x.p, h.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_pops = true;
+    c->has_rad = false;
+    return MILOC_OK;
+}
+
+miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int* iters_done,
+                       double* last_delta)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (max_iter < 1) return fail(c, MILOC_EINVAL, "max_iter must be >= 1");
+    if (!std::isfinite(tol)) return fail(c, MILOC_EINVAL, "tol must be finite");
+    s = ensure_static(c);
+    if (s) return s;
+    if (!c->has_pops) {
+        s = miloc_init_lte(c);
+        if (s) return s;
+    }
+    const bool fp64 = c->precision == MILOC_MARCH_FP64;
+    const int64_t nc = c->nc;
+    double delta = INFINITY;
+    int it = 0;
+    bool converged = false;
+    for (; it < max_iter; ++it) {
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        HIPCHK(c, launch_prepare(c->stream, (int)nc, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
+                                 c->d_nmolLb.as<double>(), nullptr, c->d_ke.p, fp64));
+        HIPCHK(c, hipMemsetAsync(c->d_acc.p, 0, c->d_acc.bytes, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+        s = fp64 ? launch_march<double>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
+                 : launch_march<float>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
+        if (s) return s;
+        HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+        HIPCHK(c, hipMemsetAsync(c->d_flags.p, 0, 16, c->stream));
+        SEArgs a{};
+        a.nc = (int)nc;
+        a.L = c->L;
+        a.ntr = c->T;
+        a.use_ali = use_ali ? 1 : 0;
+        a.mol = c->d_mol.as<MolDev>();
+        a.x_old = c->d_x.as<double>();
+        a.x_new = c->d_xnew.as<double>();
+        a.nH2 = c->d_nH2.as<double>();
+        a.Tkin = c->d_T.as<double>();
+        a.q = c->d_q.as<double>();
+        a.acc = c->d_acc.as<double2>();
+        a.delta_bits = c->d_flags.as<unsigned long long>();
+        a.bad = reinterpret_cast<unsigned int*>(c->d_flags.as<char>() + 8);
+        HIPCHK(c, launch_se(c->stream, a));
+        HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+        unsigned long long flags[2] = {0, 0};
+        HIPCHK(c, hipMemcpyAsync(flags, c->d_flags.p, 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        float t01 = 0, t12 = 0, t23 = 0;
+        HIPCHK(c, hipEventElapsedTime(&t01, c->ev[0], c->ev[1]));
+        HIPCHK(c, hipEventElapsedTime(&t12, c->ev[1], c->ev[2]));
+        HIPCHK(c, hipEventElapsedTime(&t23, c->ev[2], c->ev[3]));
+        c->ctr.prepare_ms += t01;
+        c->ctr.march_ms += t12;
+        c->ctr.solve_ms += t23;
+        c->ctr.march_launches += 1;
+        c->ctr.ray_steps += c->steps_per_trans * c->T;
+        c->ctr.channel_updates += c->steps_per_trans * c->T * c->nch;
+        c->ctr.iterations += 1;
+        c->has_rad = true;
+        const unsigned int bad = (unsigned int)(flags[1] & 0xffffffffu);
+        if (bad) {
+            if (iters_done) *iters_done = it;
+            return fail(c, MILOC_ENUMERIC, "non-finite or negative populations from the equilibrium solve");
+        }
+        std::memcpy(&delta, &flags[0], sizeof(double));
+        std::swap(c->d_x.p, c->d_xnew.p);
+        if (tol > 0 && delta < tol) {
+            converged = true;
+            ++it;
+            break;
+        }
+    }
+    if (iters_done) *iters_done = it;
+    if (last_delta) *last_delta = delta;
+    if (tol > 0 && !converged) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "not converged after %d iterations (delta %.3e)", it, delta);
+        return fail(c, MILOC_ENOTCONV, buf);
+    }
+    return MILOC_OK;
+}
+
+miloc_status miloc_get_sizes(const miloc_ctx* c, int64_t* n_cells, int* n_levels, int* n_trans,
+                             int* n_channels)
+{
+    if (!c) return MILOC_EINVAL;
+    if (n_cells) *n_cells = c->nc;
+    if (n_levels) *n_levels = c->has_mol ? c->L : 0;
+    if (n_trans) *n_trans = c->has_mol ? c->T : 0;
+    if (n_channels) *n_channels = c->has_spec ? c->nch : 0;
+    return MILOC_OK;
+}
+
+miloc_status miloc_get_populations(miloc_ctx* c, double* x_out)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!x_out) return fail(c, MILOC_EINVAL, "NULL output");
+    if (!c->has_pops) return fail(c, MILOC_ESTATE, "no populations yet");
+    const size_t n = (size_t)c->nc * c->L;
+    std::vector<double> h(n);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->d_x.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(x_out, h.data(), n * sizeof(double));
+    return MILOC_OK;
+}
+
+miloc_status miloc_get_radiation(miloc_ctx* c, double* J_out, double* lambda_out)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!c->has_rad) return fail(c, MILOC_ESTATE, "no iteration has run since the last change");
+    const size_t n = (size_t)c->T * c->nc;
+    std::vector<double2> h(n);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->d_acc.p, n * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int t = 0; t < c->T; ++t)
+        for (int64_t k = 0; k < c->nc; ++k) {
+            const size_t i = (size_t)t * c->nc + k;
+            if (J_out) J_out[i] = h[i].x * c->q_host[k] * c->Iscale[t];
+            if (lambda_out) lambda_out[i] = h[i].y * c->q_host[k];
+        }
+    return MILOC_OK;
+}
+
+miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double* impact_cm, double* dI_out)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!dI_out) return fail(c, MILOC_EINVAL, "NULL output");
+    if (!c->has_mol || c->kind == 0) return fail(c, MILOC_ESTATE, "no model");
+    if (trans < 0 || trans >= c->T) return fail(c, MILOC_EINVAL, "transition index out of range");
+    if (!c->has_pops) return fail(c, MILOC_ESTATE, "no populations yet");
+    s = ensure_static(c);
+    if (s) return s;
+    const bool fp64 = c->precision == MILOC_MARCH_FP64;
+    const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+    DevBuf out, extra, extra2;
+    // march I - I_bg from zero (see prepare_kernel)
+    HIPCHK(c, launch_prepare(c->stream, (int)c->nc, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
+                             c->d_nmolLb.as<double>(), c->d_Ibg64.as<double>(), c->d_ke.p, fp64));
+    if (c->kind == 3) {
+        if (impact_cm) return fail(c, MILOC_EINVAL, "3D spectra take no impact parameters");
+        if (n_los != c->N * c->N) return fail(c, MILOC_EINVAL, "3D spectra need n_los = N*N");
+        std::vector<double> zd = {0.0, 0.0, 1.0};
+        std::vector<DirDev> dd;
+        std::vector<double> len;
+        std::vector<int> fl;
+        build_patterns(c->N, zd, dd, len, fl, nullptr);
+        HIPCHK(c, extra.ensure(sizeof(DirDev)));
+        HIPCHK(c, hipMemcpy(extra.p, dd.data(), sizeof(DirDev), hipMemcpyHostToDevice));
+        if (fp64) {
+            std::vector<StepRec<double>> st(len.size());
+            for (size_t i = 0; i < len.size(); ++i) { st[i].len = len[i]; st[i].flags = fl[i]; }
+            HIPCHK(c, extra2.ensure(st.size() * sizeof(st[0])));
+            HIPCHK(c, hipMemcpy(extra2.p, st.data(), st.size() * sizeof(st[0]), hipMemcpyHostToDevice));
+        } else {
+            std::vector<StepRec<float>> st(len.size());
+            for (size_t i = 0; i < len.size(); ++i) { st[i].len = (float)len[i]; st[i].flags = fl[i]; }
+            HIPCHK(c, extra2.ensure(st.size() * sizeof(st[0])));
+            HIPCHK(c, hipMemcpy(extra2.p, st.data(), st.size() * sizeof(st[0]), hipMemcpyHostToDevice));
+        }
+        HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
+        s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0)
+                 : launch_march<float>(c, 1, trans, false, out.as<float>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0);
+        if (s) return s;
+    } else {
+        const double Rout = c->R[c->nc - 1];
+        std::vector<double> bn;
+        if (impact_cm) {
+            if (n_los < 1) return fail(c, MILOC_EINVAL, "n_los must be >= 1");
+            bn.resize(n_los);
+            for (int j = 0; j < n_los; ++j) {
+                if (!(impact_cm[j] >= 0 && impact_cm[j] < Rout)) return fail(c, MILOC_EINVAL, "impact parameter outside [0, R)");
+                bn[j] = impact_cm[j] / Rout;
+            }
+        } else {
+            if (n_los != c->nrays) return fail(c, MILOC_EINVAL, "n_los must equal n_rays when impact_cm is NULL");
+            bn.resize(n_los);
+            for (int j = 0; j < n_los; ++j) bn[j] = c->impact[j] / Rout;
+        }
+        HIPCHK(c, extra.ensure(bn.size() * sizeof(double)));
+        HIPCHK(c, hipMemcpy(extra.p, bn.data(), bn.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
+        s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los)
+                 : launch_march<float>(c, 1, trans, false, out.as<float>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los);
+        if (s) return s;
+    }
+    const size_t n = (size_t)n_los * c->nch;
+    std::vector<char> h(n * tsz);
+    HIPCHK(c, hipMemcpyAsync(h.data(), out.p, n * tsz, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double sc = c->Iscale[trans];
+    for (size_t i = 0; i < n; ++i) {
+        const double v = fp64 ? reinterpret_cast<double*>(h.data())[i] : (double)reinterpret_cast<float*>(h.data())[i];
+        dI_out[i] = v * sc;
+    }
+    return MILOC_OK;
+}
+
+miloc_status miloc_get_counters(const miloc_ctx* c, miloc_counters* out)
+{
+    if (!c || !out) return MILOC_EINVAL;
+    *out = c->ctr;
+    return MILOC_OK;
+}
+
+miloc_status miloc_reset_counters(miloc_ctx* c)
+{
+    if (!c) return MILOC_EINVAL;
+    c->ctr = miloc_counters{};
+    return MILOC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (populations): relative 1e-5 for x >= 1e-12 with the FP32 march, 1e-10
+with the FP64 march; entries below 1e-12 compared with an absolute 1e-17
+floor.  Spectra: max_c |dI_gpu - dI_ref| <= 1e-4 max_c |dI_ref| per line of
+sight (FP32), 1e-9 (FP64).  Inputs are the seeded synthetic workloads.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+miloc = pytest.importorskip("paper_2009_12609_amd")
+
+pytestmark = pytest.mark.gpu
+
+KMS = 1.0e5
+
+
+def make_ctx(w, fp64=False, dirs=None):
+    ctx = miloc.Context()
+    ctx.load_molecule(w.mol)
+    if isinstance(w.model, synth.Model1D):
+        ctx.load_model_1d(w.model)
+    else:
+        ctx.load_model_3d(w.model)
+    ctx.set_spectral(w.spec.n_channels, w.spec.v_min, w.spec.dv)
+    ctx.set_background(w.T_bg)
+    ctx.set_march_precision(fp64)
+    if dirs is not None:
+        ctx.set_directions(dirs)
+    return ctx
+
+
+def pop_err(x, ref):
+    big = ref >= 1e-12
+    rel = float(np.max(np.abs(x[big] - ref[big]) / ref[big]))
+    absd = float(np.max(np.abs(x[~big] - ref[~big]))) if np.any(~big) else 0.0
+    return rel, absd
+
+
+def assert_pops(x, ref, rtol, label=""):
+    rel, absd = pop_err(x, ref)
+    print(f"[parity] {label} populations: max rel {rel:.3e}, small-entry abs {absd:.3e}", flush=True)
+    assert rel <= rtol, (label, rel)
+    assert absd <= 1e-17, (label, absd)
+
+
+def assert_spectra(sp, ref, tol, label=""):
+    scale = np.max(np.abs(ref), axis=1)
+    err = np.max(np.abs(sp - ref), axis=1)
+    ok = scale > 0
+    worst = float(np.max(err[ok] / scale[ok])) if np.any(ok) else 0.0
+    print(f"[parity] {label} spectra: max err / peak {worst:.3e}", flush=True)
+    assert worst <= tol, (label, worst)
+    assert np.all(err[~ok] <= 1e-30)
+
+
+def workload_1d_plummer(n_shells, abundance=1e-9, n_levels=10):
+    w = synth.workload_1d_plummer(n_shells=n_shells, abundance=abundance)
+    if n_levels != 10:
+        w.mol = synth.rotor_molecule(n_levels)
+    return w
+
+
+def workload_3d(N, seed=3001, abundance=1e-9, n_levels=10, box_pc=1.0, nch=256, half=4.0):
+    cube = synth.turbulent_cube(N=N, seed=seed, abundance=abundance, box_pc=box_pc)
+    return synth.Workload(f"3d-{N}", synth.rotor_molecule(n_levels), synth.Spectral.symmetric(nch, half),
+                          2.73, cube, 2)
+
+
+# ---------------------------------------------------------------------------
+# 1D
+# ---------------------------------------------------------------------------
+
+def test_1d_small_fp64_iteration_by_iteration():
+    """100 log shells, two-level species, 128 channels, FP64 march: every one
+    of 20 ALI iterations matches the oracle."""
+    w = synth.workload_1d_small()
+    print("[case] 1d-small fp64 20 it", flush=True)
+    ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, 20)
+    ctx = make_ctx(w, fp64=True)
+    ctx.init_lte()
+    worst = 0.0
+    for it in range(20):
+        ctx.run(1)
+        x = ctx.populations()
+        rel, _ = pop_err(x, ref.history[it]["x"])
+        worst = max(worst, rel)
+        if it in (0, 19):
+            J, Lam = ctx.radiation()
+            h = ref.history[it]
+            assert np.allclose(J, h["J"], rtol=1e-10, atol=0)
+            assert np.allclose(Lam, h["Lam"], rtol=1e-9, atol=1e-20)
+    print(f"[parity] 1d-small fp64 worst over iterations {worst:.3e}", flush=True)
+    assert worst < 1e-10
+    sp = ctx.spectra(0, n_los=w.model.n_rays)
+    ref_sp = oracle.spectra_1d(w.mol, w.model, w.spec, w.T_bg, ref.x, 0)
+    assert_spectra(sp, ref_sp, 1e-9, "1d-small fp64")
+
+
+def test_1d_small_fp32():
+    w = synth.workload_1d_small()
+    ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, 20)
+    ctx = make_ctx(w, fp64=False)
+    it, delta = ctx.run(20)
+    assert it == 20
+    assert_pops(ctx.populations(), ref.x, 1e-5, "1d-small fp32")
+    sp = ctx.spectra(0, n_los=w.model.n_rays)
+    ref_sp = oracle.spectra_1d(w.mol, w.model, w.spec, w.T_bg, ref.x, 0)
+    assert_spectra(sp, ref_sp, 1e-4, "1d-small fp32")
+
+
+@pytest.mark.parametrize("n_shells,abundance,n_iter", [(157, 1e-9, 20), (61, 1e-6, 12)])
+def test_1d_plummer_reduced(n_shells, abundance, n_iter):
+    """Plummer infall cloud with the 10-level rotor (thin and thick variants)."""
+    w = workload_1d_plummer(n_shells, abundance)
+    print(f"[case] 1d-plummer {n_shells} X={abundance}", flush=True)
+    ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, n_iter)
+    ctx = make_ctx(w)
+    ctx.run(n_iter)
+    assert_pops(ctx.populations(), ref.x, 1e-5, f"1d-plummer-{n_shells}")
+    J, Lam = ctx.radiation()
+    h = ref.history[-1]
+    assert np.allclose(J, h["J"], rtol=2e-5, atol=0)
+    assert np.allclose(Lam, h["Lam"], rtol=2e-5, atol=1e-9)
+    imp = np.array([0.0, 0.003, 0.2, 0.77]) * w.model.r_out[-1]
+    for t in (0, 3):
+        sp = ctx.spectra(t, impact=imp)
+        ref_sp = oracle.spectra_1d(w.mol, w.model, w.spec, w.T_bg, ref.x, t, impact=imp)
+        assert_spectra(sp, ref_sp, 1e-4, f"1d-plummer-{n_shells} t={t}")
+
+
+def test_1d_plummer_full_size_two_iterations():
+    """The full 1000-shell / 1000-ray / 256-channel workload, two iterations."""
+    w = workload_1d_plummer(1000)
+    print("[case] 1d-plummer-1000 full size", flush=True)
+    ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, 2)
+    ctx = make_ctx(w)
+    ctx.run(2)
+    assert_pops(ctx.populations(), ref.x, 1e-5, "1d-plummer-1000")
+    J, Lam = ctx.radiation()
+    assert np.allclose(J, ref.history[-1]["J"], rtol=2e-5, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# 3D regular grid
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,abundance,n_iter", [(12, 1e-9, 4), (13, 1e-9, 2), (9, 3e-7, 4)])
+def test_3d_small_grid(N, abundance, n_iter):
+    """Turbulent cube, 48 HEALPix directions, rotor, 256 channels.  N = 13
+    leaves a ragged last block of rays; X = 3e-7 makes the lines thick."""
+    w = workload_3d(N, seed=100 + N, abundance=abundance, box_pc=0.1 * N / 12)
+    print(f"[case] 3d N={N} X={abundance}", flush=True)
+    ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, n_iter)
+    ctx = make_ctx(w)
+    ctx.run(n_iter)
+    assert_pops(ctx.populations(), ref.x, 1e-5, f"3d-{N}")
+    J, Lam = ctx.radiation()
+    h = ref.history[-1]
+    assert np.allclose(J, h["J"], rtol=2e-5, atol=0)
+    assert np.allclose(Lam, h["Lam"], rtol=2e-5, atol=1e-9)
+    sp = ctx.spectra(0, n_los=N * N)
+    ref_sp = oracle.spectra_3d(w.mol, w.model, w.spec, w.T_bg, ref.x, 0)
+    assert_spectra(sp, ref_sp, 1e-4, f"3d-{N}")
+
+
+def test_3d_fp64_march():
+    w = workload_3d(8, seed=7, abundance=1e-7, n_levels=5, box_pc=0.05, nch=128)
+    ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, 3)
+    ctx = make_ctx(w, fp64=True)
+    ctx.run(3)
+    assert_pops(ctx.populations(), ref.x, 1e-10, "3d-8 fp64")
+
+
+def test_3d_full_size_sampled_directions():
+    """128^3 at full size in the benchmark's launch configuration, with the ray
+    set reduced to two directions (one with a |d_x| = |d_y| tie, one polar) so
+    the oracle can follow every ray; J and Lambda of the first and last
+    transition after one iteration."""
+    w = synth.workload_3d_regular()
+    hp = oracle.healpix_nside2()
+    absd = np.abs(hp)
+    tie = [i for i, v in enumerate(absd) if abs(v[0] - v[1]) < 1e-12 and v[0] >= v.max() - 1e-12][0]
+    dirs = hp[[tie, 2]]
+    print("[case] 3d 128^3 two directions", flush=True)
+    ctx = make_ctx(w, dirs=dirs)
+    ctx.run(1)
+    J, Lam = ctx.radiation()
+    m = w.model
+    prob = oracle._Problem(w.mol, m.n_H2, m.T_kin, m.b_turb, m.abundance, w.spec, w.T_bg)
+    x0 = oracle.lte_populations(w.mol, prob.T)
+    kap, eta = oracle.prepare(w.mol, x0, prob.n_mol)
+    for t in (0, w.mol.n_trans - 1):
+        r = oracle.march_3d(128, m.root_cell_cm, m.vx.astype(float), m.vy.astype(float),
+                            m.vz.astype(float), prob.bD, kap[t], eta[t], dirs, w.spec, prob.I_bg[t])
+        Jr = r.Jraw / r.W
+        Lr = r.Lraw / r.W
+        relJ = np.max(np.abs(J[t] - Jr) / Jr)
+        print(f"[parity] 3d-128 t={t} J max rel {relJ:.3e}", flush=True)
+        assert relJ < 2e-5
+        assert np.allclose(Lam[t], Lr, rtol=2e-5, atol=1e-10)
+
+
+def test_3d_full_size_detailed_balance():
+    """128^3, 48 directions: with T_bg = T_kin the Boltzmann populations are
+    the fixed point at any optical depth (exact in the method)."""
+    w = synth.workload_3d_regular()
+    w.T_bg = 15.0
+    ctx = make_ctx(w)
+    ctx.init_lte()
+    x0 = ctx.populations()
+    ctx.run(1)
+    x1 = ctx.populations()
+    rel, absd = pop_err(x1, x0)
+    print(f"[parity] 3d-128 detailed balance drift {rel:.3e}", flush=True)
+    assert rel < 1e-5
+
+
+def test_3d_full_size_uniform_field():
+    """128^3, 48 directions: populations with source function B(T_bg) in every
+    transition leave every ray at I_bg, so J + S Lambda = I_bg (sum_c f_c = 1)."""
+    w = synth.workload_3d_regular()
+    ctx = make_ctx(w)
+    nc = w.model.n_cells
+    xbg = oracle.lte_populations(w.mol, np.array([w.T_bg]))[0]
+    ctx.set_populations(np.tile(xbg, (nc, 1)))
+    ctx.run(1)
+    J, Lam = ctx.radiation()
+    Ibg = oracle.planck(w.mol.nu, w.T_bg)
+    g = w.mol.g
+    for t in range(w.mol.n_trans):
+        u, l = w.mol.up[t], w.mol.lo[t]
+        S = (2 * oracle.H * w.mol.nu[t] ** 3 / oracle.C ** 2) / (xbg[l] * g[u] / (xbg[u] * g[l]) - 1)
+        tot = J[t] + S * Lam[t]
+        err = np.max(np.abs(tot / Ibg[t] - 1))
+        print(f"[parity] 3d-128 uniform field t={t} {err:.3e}", flush=True)
+        assert err < 2e-6
+
+
+# ---------------------------------------------------------------------------
+# ABI behaviour on the device
+# ---------------------------------------------------------------------------
+
+def test_abi_state_and_argument_errors():
+    ctx = miloc.Context()
+    with pytest.raises(miloc.MilocError) as e:
+        ctx.run(1)
+    assert e.value.code == miloc.ESTATE
+    w = synth.workload_1d_small()
+    ctx.load_molecule(w.mol)
+    ctx.load_model_1d(w.model)
+    with pytest.raises(miloc.MilocError) as e:
+        ctx.run(1)                       # no spectral grid yet
+    assert e.value.code == miloc.ESTATE
+    with pytest.raises(miloc.MilocError) as e:
+        ctx.set_spectral(4, -1e5, 1e3)
+    assert e.value.code == miloc.EINVAL
+    # band narrower than the lines
+    ctx.set_spectral(16, -0.2 * KMS, 0.025 * KMS)
+    with pytest.raises(miloc.MilocError) as e:
+        ctx.run(1)
+    assert e.value.code == miloc.EINVAL
+    bad = synth.workload_1d_small().model
+    bad.T_kin[3] = -1.0
+    with pytest.raises(miloc.MilocError) as e:
+        ctx.load_model_1d(bad)
+    assert e.value.code == miloc.EINVAL
+    with pytest.raises(miloc.MilocError) as e:
+        ctx.set_directions(np.zeros((2, 3)))
+    assert e.value.code == miloc.EINVAL
+
+
+def test_not_converged_and_checkpoint_resume():
+    w = workload_1d_plummer(80, abundance=1e-7, n_levels=5)
+    a = make_ctx(w)
+    it, d = a.run(3, tol=1e-14)
+    assert it == 3
+    with pytest.raises(miloc.MilocError) as e:
+        a.run(1, tol=1e-14, allow_notconv=False)
+    assert e.value.code == miloc.ENOTCONV
+    # run(4) + save + resume in a fresh context + run(3) == run(7)
+    b = make_ctx(w)
+    b.run(4)
+    saved = b.populations()
+    c = make_ctx(w)
+    c.set_populations(saved)
+    c.run(3)
+    d7 = make_ctx(w)
+    d7.run(7)
+    rel, _ = pop_err(c.populations(), d7.populations())
+    assert rel < 1e-6
