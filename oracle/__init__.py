@@ -64,6 +64,8 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_max_threads.restype = ctypes.c_int
+        L.orc_max_threads.argtypes = []
         L.orc1d_ray_steps.restype = ctypes.c_int
         L.orc1d_ray_steps.argtypes = [ctypes.c_int, dp, ctypes.c_double, ip, dp, dp]
         L.orc1d_march.restype = None
@@ -84,6 +86,11 @@ def lib():
                                   dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
+
+
+def max_threads() -> int:
+    """Threads the oracle's marches use with n_threads = 0."""
+    return int(lib().orc_max_threads())
 
 
 def _dp(a: Optional[np.ndarray]):

@@ -103,6 +103,16 @@ typedef struct {
     double cons;
 } accum_t;
 
+/* Number of threads the marches use when asked for 0 (all available). */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static int nthreads_of(int req)
 {
 #ifdef _OPENMP

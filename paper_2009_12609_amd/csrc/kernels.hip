@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "miloc_internal.h"
 
 namespace miloc {
@@ -28,6 +30,8 @@ constexpr float kLog2eF = 1.4426950408889634f;
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double fast_exp2(double x) { return exp2(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
 // 1 - beta and e^{-tau}, beta = (1 - e^{-tau})/tau (Sect. 2, Eqs. (2)-(3)).
 // Small |tau|: Taylor series of 1 - beta (no cancellation); else direct.
@@ -63,8 +67,32 @@ __device__ __forceinline__ void escape_terms(double tau, double& omb, double& e)
     }
 }
 
-template <int LANES, typename T>
-__device__ __forceinline__ T group_sum(T v)
+// Sum over a group of LANES (32 or 64) consecutive lanes; the total is valid
+// in the group's last lane.  FP32 uses DPP row operations (no LDS traffic):
+// quad swaps, half-row and row mirrors give every lane its 16-lane row sum,
+// row_bcast15 / row_bcast31 then fold rows 0->1, 2->3 and (64) 1->3.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    const int src = __builtin_bit_cast(int, v);
+    const int got = __builtin_amdgcn_update_dpp(0, src, CTRL, ROW_MASK, 0xF, false);
+    return v + __builtin_bit_cast(float, got);
+}
+
+template <int LANES>
+__device__ __forceinline__ float group_sum(float v)
+{
+    v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    if (LANES >= 8) v = dpp_add<0x141, 0xF>(v);    // row_half_mirror
+    if (LANES >= 16) v = dpp_add<0x140, 0xF>(v);   // row_mirror
+    if (LANES >= 32) v = dpp_add<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
+    if (LANES == 64) v = dpp_add<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
+    return v;
+}
+
+template <int LANES>
+__device__ __forceinline__ double group_sum(double v)
 {
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LANES);
@@ -99,7 +127,7 @@ __device__ __forceinline__ void window(double w, double chalf, T Kw, T ibs, int 
                                        int& clo, int& chi, T& frac)
 {
     const double cstar = -(chalf + w);
-    const double hw = (double)(Kw / ibs);
+    const double hw = (double)(Kw * fast_rcp(ibs));
     int lo = (int)ceil(cstar - hw);
     int hi = (int)floor(cstar + hw);
     lo = lo < 0 ? 0 : lo;
@@ -154,6 +182,88 @@ __global__ void lte_kernel(int nc, const MolDev* __restrict__ mol, const double*
 }
 
 // ---------------------------------------------------------------- 3D march
+// Per workgroup: rays of one direction (a block never straddles directions).
+// The direction's step list is staged in LDS once and read as a broadcast.
+// Several rays share a wavefront (16 lanes each for narrow lines), so each
+// step issues the cell loads of several independent rays at once.
+namespace {
+
+// One move of the ray along a transverse axis with periodic re-entry.
+__device__ __forceinline__ void move_transverse(int& c, int& idx, int s, int st, int N, bool& restart)
+{
+    c += s;
+    const bool wrap = (unsigned)c >= (unsigned)N;
+    c = wrap ? c - s * N : c;
+    idx += wrap ? -s * (N - 1) * st : s * st;
+    restart |= wrap;
+}
+
+}  // namespace
+
+// Window table of one direction: for every cell the first channel of its
+// window, the number of window channels and the profile argument of the first
+// channel, all from the FP64 line-of-sight velocity (Sect. 3.1: Doppler shift
+// per step; App. A.2: only channels where the profile is significant).
+template <typename T>
+__global__ void window_table_kernel(int nc, int n_dir, const DirDev* __restrict__ dirs,
+                                    const float4* __restrict__ vel, const double* __restrict__ bD,
+                                    double dv, double chalf, double K, int nch,
+                                    typename V4<T>::type* __restrict__ win)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (k >= nc || q >= n_dir) return;
+    const DirDev& D = dirs[q];
+    const float4 u = vel[k];
+    const double w = ((double)u.x * D.d[0] + (double)u.y * D.d[1] + (double)u.z * D.d[2]) / dv;
+    const double cstar = -(chalf + w);
+    const double bc = bD[k] / dv;                 // Doppler width in channels
+    const double hw = K * bc;
+    int lo = (int)ceil(cstar - hw);
+    int hi = (int)floor(cstar + hw);
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > nch - 1 ? nch - 1 : hi;
+    const int n = hi >= lo ? hi - lo + 1 : 0;
+    const double ibs = 1.2011224087864498 / bc;   // sqrt(log2 e) / (b/dv)
+    typename V4<T>::type r;
+    r.x = (T)(((double)lo - cstar) * ibs);
+    r.y = (T)ibs;
+    r.z = __builtin_bit_cast(T, (typename std::conditional<sizeof(T) == 4, int, long long>::type)lo);
+    r.w = __builtin_bit_cast(T, (typename std::conditional<sizeof(T) == 4, int, long long>::type)n);
+    win[(size_t)q * nc + k] = r;
+}
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ int as_int(T v)
+{
+    return (int)__builtin_bit_cast(typename std::conditional<sizeof(T) == 4, int, long long>::type, v);
+}
+
+// 1 - beta for |tau| < 0.01 (3 terms; relative truncation error < 2e-8).
+__device__ __forceinline__ float omb_thin(float tau)
+{
+    const float h = 0.5f - tau * ((1.0f / 6.0f) - tau * (1.0f / 24.0f));
+    return tau * h;
+}
+__device__ __forceinline__ double omb_thin(double tau)
+{
+    double omb, e;
+    escape_terms(tau, omb, e);
+    return omb;
+}
+// 1 - beta for any tau.
+template <typename T>
+__device__ __forceinline__ T omb_any(T tau)
+{
+    T omb, e;
+    escape_terms(tau, omb, e);
+    return omb;
+}
+
+}  // namespace
+
 template <typename T, int LANES, bool ACCUM>
 __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
 {
@@ -172,64 +282,93 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
     const int r = (bid - q * p.blocks_per_dir) * rpb + rib;
     const int t = p.trans_offset + blockIdx.y;
     extern __shared__ unsigned char smem_raw[];
-    T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)rib * p.nch;
-    if (r >= p.rays_per_dir) return;
+    StepRec<T>* __restrict__ sst = reinterpret_cast<StepRec<T>*>(smem_raw);
+    T* __restrict__ I = reinterpret_cast<T*>(smem_raw + p.step_lds_bytes) + (size_t)rib * p.ich;
 
     const DirDev D = p.dirs[q];
+    for (int i = threadIdx.x; i < D.nsteps; i += blockDim.x) sst[i] = p.steps[D.step0 + i];
+    __syncthreads();
+    if (r >= p.rays_per_dir) return;
+
     const int N = p.N;
     const int i0 = r % N, j0 = r / N;
     int ca = i0, cb = j0;
     int idx = D.start_off + i0 * D.sta + j0 * D.stb;
     const T Ibg = p.Ibg[t];
     const size_t tb = (size_t)t * p.nc;
-    const StepRec<T>* __restrict__ st = p.steps + D.step0;
+    const T4* __restrict__ win = p.win + (size_t)q * p.nc;
+    const T2* __restrict__ ke = p.ke + tb;
+    double2* __restrict__ acc = p.acc + tb;
     const T aw = (T)D.aw;
+    const int ns = D.nsteps;
+    const T lanef = (T)lane;
+    // Invalid channel slots read and write a private dummy word in the
+    // ray's padding so that no lane touches another ray's channels.
+    T* __restrict__ dummy = I + p.nch + lane;
 
     for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
 
-    for (int s = 0; s < D.nsteps; ++s) {
-        const StepRec<T> rec = st[s];
+    // Per-ray queue of pending accumulations {weighted J sum, weighted Lambda
+    // sum, cell}.  Global atomics without return share the load counter on
+    // this architecture, so an atomic issued every step would make the next
+    // step's load wait for it; instead the group flushes LANES queued steps at
+    // once, one entry per lane.
+    T* __restrict__ qj = reinterpret_cast<T*>(smem_raw + p.queue_lds_offset) + (size_t)rib * 3 * LANES;
+    T* __restrict__ ql = qj + LANES;
+    int* __restrict__ qi = reinterpret_cast<int*>(ql + LANES);
+    int qn = 0;
+
+    for (int s = 0; s < ns; ++s) {
+        const StepRec<T> rec = sst[s];
         bool restart = false;
         if (rec.flags & 1) idx += D.stride_m;
-        if (rec.flags & 2) {
-            if (D.sa > 0) {
-                if (ca == N - 1) { ca = 0; idx -= (N - 1) * D.sta; restart = true; }
-                else { ++ca; idx += D.sta; }
-            } else {
-                if (ca == 0) { ca = N - 1; idx += (N - 1) * D.sta; restart = true; }
-                else { --ca; idx -= D.sta; }
-            }
-        }
-        if (rec.flags & 4) {
-            if (D.sb > 0) {
-                if (cb == N - 1) { cb = 0; idx -= (N - 1) * D.stb; restart = true; }
-                else { ++cb; idx += D.stb; }
-            } else {
-                if (cb == 0) { cb = N - 1; idx += (N - 1) * D.stb; restart = true; }
-                else { --cb; idx -= D.stb; }
-            }
-        }
+        if (rec.flags & 2) move_transverse(ca, idx, D.sa, D.sta, N, restart);
+        if (rec.flags & 4) move_transverse(cb, idx, D.sb, D.stb, N, restart);
+        const T4 wv = win[idx];
+        const T2 kv = ke[idx];
         if (restart) {
             // Side exit: the ray re-enters on the opposite face carrying the
             // background again (Sect. 2.2).
             for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
         }
-        const T4 cv = p.cellv[idx];
-        const T2 kev = p.ke[tb + idx];
-        const double w = (double)cv.x * D.d[0] + (double)cv.y * D.d[1] + (double)cv.z * D.d[2];
-        int clo, chi;
-        T frac;
-        window<T>(w, p.chalf, p.Kw, cv.w, p.nch, clo, chi, frac);
+        const int clo = as_int(wv.z);
+        const int nwin = as_int(wv.w);
+        const T kl = kv.x * rec.len;      // tau at the line centre
+        const T el = kv.y * rec.len;
         T sj = 0, sl = 0;
-        step_channels<LANES, T>(I, lane, clo, chi, frac, cv.w, kev.x * rec.len,
-                                kev.y * rec.len, sj, sl);
+        // thin steps everywhere in the wavefront: short series for 1 - beta
+        const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
+        for (int j = lane; j < nwin; j += LANES) {
+            T* __restrict__ cell = I + clo + j;
+            const T xs = (lanef + (T)(j - lane)) * wv.y + wv.x;
+            const T ec = fast_exp2(-xs * xs);
+            const T tau = kl * ec;
+            const T omb = thin ? omb_thin(tau) : omb_any(tau);
+            const T Iin = *cell;
+            const T u = ec - ec * omb;                 // e_c beta_c
+            sj += Iin * u;
+            sl += ec * omb;
+            // I e^-tau + el e_c beta with e^-tau = 1 - tau beta
+            *cell = Iin + u * (el - kl * Iin);
+        }
+        (void)dummy;
         if (ACCUM) {
             sj = group_sum<LANES>(sj);
             sl = group_sum<LANES>(sl);
-            if (lane == 0) {
-                const double wgt = (double)(aw * rec.len);
-                unsafeAtomicAdd(&p.acc[tb + idx].x, wgt * (double)sj);
-                unsafeAtomicAdd(&p.acc[tb + idx].y, wgt * (double)sl);
+            if (lane == LANES - 1) {
+                const T wgt = aw * rec.len;
+                qj[qn] = wgt * sj;
+                ql[qn] = wgt * sl;
+                qi[qn] = idx;
+            }
+            ++qn;
+            if (qn == LANES || s == ns - 1) {
+                if (lane < qn) {
+                    double* a = &acc[qi[lane]].x;
+                    unsafeAtomicAdd(a, (double)qj[lane]);
+                    unsafeAtomicAdd(a + 1, (double)ql[lane]);
+                }
+                qn = 0;
             }
         }
     }
@@ -307,7 +446,7 @@ __global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
         if (ACCUM) {
             sj = group_sum<LANES>(sj);
             sl = group_sum<LANES>(sl);
-            if (lane == 0) {
+            if (lane == LANES - 1) {
                 const double wgt = a * len;
                 unsafeAtomicAdd(&p.acc[tb + k].x, wgt * (double)sj);
                 unsafeAtomicAdd(&p.acc[tb + k].y, wgt * (double)sl);
@@ -447,6 +586,21 @@ hipError_t launch_prepare(hipStream_t s, int nc, const MolDev* mol, int ntr, con
     return hipGetLastError();
 }
 
+hipError_t launch_window_table(hipStream_t s, int nc, int n_dir, const DirDev* dirs, const float4* vel,
+                               const double* bD, double dv, double chalf, double K, int nch, void* win,
+                               bool fp64)
+{
+    const int bs = 256;
+    const dim3 grid((nc + bs - 1) / bs, n_dir);
+    if (fp64)
+        hipLaunchKernelGGL(window_table_kernel<double>, grid, dim3(bs), 0, s, nc, n_dir, dirs, vel, bD, dv,
+                           chalf, K, nch, reinterpret_cast<double4*>(win));
+    else
+        hipLaunchKernelGGL(window_table_kernel<float>, grid, dim3(bs), 0, s, nc, n_dir, dirs, vel, bD, dv,
+                           chalf, K, nch, reinterpret_cast<float4*>(win));
+    return hipGetLastError();
+}
+
 hipError_t launch_lte(hipStream_t s, int nc, const MolDev* mol, const double* Tkin, double* x)
 {
     const int bs = 256;
@@ -464,12 +618,23 @@ int rays_per_block(int lanes, int nch)
 }
 
 template <typename T, int LANES, bool ACCUM>
-hipError_t do_march3d(hipStream_t s, March3DArgs<T> a)
+hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
 {
-    const int rpb = rays_per_block<T>(LANES, a.nch);
+    // Channel vectors are padded by 16 words so that the rays of one
+    // wavefront start in different LDS banks.
+    a.ich = a.nch + 16;
+    int rpb = 256 / LANES;
+    while (rpb > 1 && (size_t)rpb * a.ich * sizeof(T) > 65536) rpb >>= 1;
     a.blocks_per_dir = (a.rays_per_dir + rpb - 1) / rpb;
+    a.step_lds_bytes = (int)(((size_t)max_steps * sizeof(StepRec<T>) + 15) & ~(size_t)15);
+    a.queue_lds_offset = a.step_lds_bytes + (int)((size_t)rpb * a.ich * sizeof(T));
     const dim3 grid(a.blocks_per_dir * a.n_dir, a.ntr);
-    const size_t shm = (size_t)rpb * a.nch * sizeof(T);
+    const size_t shm = (size_t)a.queue_lds_offset + (size_t)rpb * 3 * LANES * sizeof(T);
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)march3d_kernel<T, LANES, ACCUM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((march3d_kernel<T, LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
     return hipGetLastError();
 }
@@ -485,10 +650,13 @@ hipError_t do_march1d(hipStream_t s, const March1DArgs<T>& a)
 }
 
 template <typename T>
-hipError_t dispatch3d(hipStream_t s, const March3DArgs<T>& a, int lanes, bool accum)
+hipError_t dispatch3d(hipStream_t s, const March3DArgs<T>& a, int lanes, bool accum, int max_steps)
 {
-    if (lanes == 32) return accum ? do_march3d<T, 32, true>(s, a) : do_march3d<T, 32, false>(s, a);
-    return accum ? do_march3d<T, 64, true>(s, a) : do_march3d<T, 64, false>(s, a);
+    if (lanes == 16)
+        return accum ? do_march3d<T, 16, true>(s, a, max_steps) : do_march3d<T, 16, false>(s, a, max_steps);
+    if (lanes == 32)
+        return accum ? do_march3d<T, 32, true>(s, a, max_steps) : do_march3d<T, 32, false>(s, a, max_steps);
+    return accum ? do_march3d<T, 64, true>(s, a, max_steps) : do_march3d<T, 64, false>(s, a, max_steps);
 }
 
 template <typename T>
@@ -499,13 +667,15 @@ hipError_t dispatch1d(hipStream_t s, const March1DArgs<T>& a, int lanes, bool ac
 }
 }  // namespace
 
-hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum)
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum,
+                          int max_steps)
 {
-    return dispatch3d<float>(s, a, lanes, accum);
+    return dispatch3d<float>(s, a, lanes, accum, max_steps);
 }
-hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum)
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum,
+                          int max_steps)
 {
-    return dispatch3d<double>(s, a, lanes, accum);
+    return dispatch3d<double>(s, a, lanes, accum, max_steps);
 }
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum)
 {

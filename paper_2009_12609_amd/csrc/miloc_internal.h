@@ -66,7 +66,7 @@ struct March3DArgs {
     int rays_per_dir, blocks_per_dir, n_dir;
     const DirDev* dirs;
     const StepRec<T>* steps;
-    const typename V4<T>::type* cellv;   // {Ux, Uy, Uz, ibs} per cell
+    const typename V4<T>::type* win;     // [n_dir][nc] {x0, ibs, first channel, n channels}
     const typename V2<T>::type* ke;      // [ntr][nc] {khat, ehat}
     const T* Ibg;                        // [ntr], occupation units
     double2* acc;                        // [ntr][nc] raw {J, Lambda} sums
@@ -74,6 +74,9 @@ struct March3DArgs {
     T Kw;                                // window half width * ibs (channels * ibs)
     T* Iout;                             // spectra: [n_dir*rays][nch] or null
     int trans_offset;                    // first transition of this launch
+    int step_lds_bytes;                  // LDS bytes reserved for the step list
+    int ich;                             // LDS stride of one ray's channel vector
+    int queue_lds_offset;                // LDS offset of the per-ray accumulation queues
 };
 
 template <typename T>
@@ -109,8 +112,15 @@ struct SEArgs {
 hipError_t launch_prepare(hipStream_t s, int nc, const MolDev* mol, int ntr, const double* x,
                           const double* nmolLb, const double* ibg_sub, void* ke, bool fp64);
 hipError_t launch_lte(hipStream_t s, int nc, const MolDev* mol, const double* Tkin, double* x);
-hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum);
-hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum);
+// Channel windows of every (direction, cell) of a regular grid.
+hipError_t launch_window_table(hipStream_t s, int nc, int n_dir, const DirDev* dirs, const float4* vel,
+                               const double* bD, double dv, double chalf, double K, int nch, void* win,
+                               bool fp64);
+// max_steps: the longest step list of the launched directions (LDS staging).
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum,
+                          int max_steps);
+hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum,
+                          int max_steps);
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum);
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes, bool accum);
 hipError_t launch_se(hipStream_t s, const SEArgs& a);

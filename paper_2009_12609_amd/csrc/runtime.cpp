@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -101,7 +102,7 @@ struct miloc_ctx {
     bool has_pops = false;
     bool has_rad = false;
     DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
-        d_zero, d_dirs, d_steps, d_flags, d_R, d_bimp, d_area;
+        d_zero, d_dirs, d_steps, d_flags, d_R, d_bimp, d_area, d_vel, d_bD, d_win;
     std::vector<double> Iscale, Ibg;   // per transition: 2 h nu^3 / c^2, background (occupation)
     std::vector<double> q_host;
     int lanes = 32;
@@ -216,26 +217,15 @@ miloc_status ensure_base(miloc_ctx* c)
 template <typename TT>
 void pack_cell_static(miloc_ctx* c, const std::vector<double>& b, std::vector<char>& out)
 {
+    // 1D shells: {v_r / dv, sqrt(log2 e) dv / b}
     const int64_t nc = c->nc;
     const double ibs_f = c->dv * kSqrtLog2e;
-    if (c->kind == 3) {
-        using T4 = typename V4<TT>::type;
-        out.resize(nc * sizeof(T4));
-        T4* v = reinterpret_cast<T4*>(out.data());
-        for (int64_t k = 0; k < nc; ++k) {
-            v[k].x = (TT)((double)c->f_vx[k] / c->dv);
-            v[k].y = (TT)((double)c->f_vy[k] / c->dv);
-            v[k].z = (TT)((double)c->f_vz[k] / c->dv);
-            v[k].w = (TT)(ibs_f / b[k]);
-        }
-    } else {
-        using T2 = typename V2<TT>::type;
-        out.resize(nc * sizeof(T2));
-        T2* v = reinterpret_cast<T2*>(out.data());
-        for (int64_t k = 0; k < nc; ++k) {
-            v[k].x = (TT)(c->vr[k] / c->dv);
-            v[k].y = (TT)(ibs_f / b[k]);
-        }
+    using T2 = typename V2<TT>::type;
+    out.resize(nc * sizeof(T2));
+    T2* v = reinterpret_cast<T2*>(out.data());
+    for (int64_t k = 0; k < nc; ++k) {
+        v[k].x = (TT)(c->vr[k] / c->dv);
+        v[k].y = (TT)(ibs_f / b[k]);
     }
 }
 
@@ -322,8 +312,17 @@ miloc_status ensure_static(miloc_ctx* c)
     double minb = b[0];
     for (int64_t k = 0; k < nc; ++k) minb = std::min(minb, b[k]);
     (void)minb;
+    // lanes per ray: the channel window (at most wmax channels) is covered in
+    // one to three passes of the ray's lane group
     const double wmax = 2.0 * Kd * maxb / c->dv + 2.0;
-    c->lanes = wmax <= 32.0 ? 32 : 64;
+    if (c->kind == 3)
+        c->lanes = wmax <= 32.0 ? 16 : (wmax <= 64.0 ? 32 : 64);
+    else
+        c->lanes = wmax <= 32.0 ? 32 : 64;
+    if (const char* ev = std::getenv("MILOC_LANES")) {
+        const int l = std::atoi(ev);
+        if (l == 32 || l == 64 || (l == 16 && c->kind == 3)) c->lanes = l;
+    }
 
     // geometry, weights W (in march length units) and q = dv/(b sqrt(pi) W)
     std::vector<double> W(nc, 0.0);
@@ -391,11 +390,26 @@ miloc_status ensure_static(miloc_ctx* c)
     HIPCHK(c, c->d_nmolLb.ensure(nc * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->d_q.p, q.data(), nc * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_nmolLb.p, nmolLb.data(), nc * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<char> cvb;
-    if (fp64) pack_cell_static<double>(c, b, cvb); else pack_cell_static<float>(c, b, cvb);
-    HIPCHK(c, c->d_cellv.ensure(cvb.size()));
-    HIPCHK(c, hipMemcpy(c->d_cellv.p, cvb.data(), cvb.size(), hipMemcpyHostToDevice));
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+    if (c->kind == 3) {
+        std::vector<float4> vel(nc);
+        for (int64_t k = 0; k < nc; ++k) vel[k] = make_float4(c->f_vx[k], c->f_vy[k], c->f_vz[k], 0.0f);
+        HIPCHK(c, c->d_vel.ensure(nc * sizeof(float4)));
+        HIPCHK(c, c->d_bD.ensure(nc * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->d_vel.p, vel.data(), nc * sizeof(float4), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->d_bD.p, b.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, c->d_win.ensure((size_t)c->n_dir_dev * nc * 4 * tsz));
+        HIPCHK(c, launch_window_table(c->stream, (int)nc, c->n_dir_dev, c->d_dirs.as<DirDev>(),
+                                      c->d_vel.as<float4>(), c->d_bD.as<double>(), c->dv, c->chalf,
+                                      Kd, c->nch, c->d_win.p, fp64));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->d_cellv.release();
+    } else {
+        std::vector<char> cvb;
+        if (fp64) pack_cell_static<double>(c, b, cvb); else pack_cell_static<float>(c, b, cvb);
+        HIPCHK(c, c->d_cellv.ensure(cvb.size()));
+        HIPCHK(c, hipMemcpy(c->d_cellv.p, cvb.data(), cvb.size(), hipMemcpyHostToDevice));
+    }
     HIPCHK(c, c->d_ke.ensure((size_t)c->T * nc * 2 * tsz));
     HIPCHK(c, c->d_acc.ensure((size_t)c->T * nc * sizeof(double2)));
     c->Ibg.resize(c->T);
@@ -427,7 +441,8 @@ void invalidate_model(miloc_ctx* c)
 template <typename TT>
 miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, bool zdir,
                           const DirDev* d_dirs_override, const void* steps_override, int nd_override,
-                          const double* bimp_override, int nrays_override)
+                          const double* bimp_override, int nrays_override,
+                          const void* win_override = nullptr)
 {
     hipError_t e;
     if (c->kind == 3) {
@@ -441,14 +456,21 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.n_dir = zdir ? nd_override : c->n_dir_dev;
         a.dirs = zdir ? d_dirs_override : c->d_dirs.as<DirDev>();
         a.steps = zdir ? reinterpret_cast<const StepRec<TT>*>(steps_override) : c->d_steps.as<StepRec<TT>>();
-        a.cellv = c->d_cellv.as<typename V4<TT>::type>();
+        a.win = zdir ? reinterpret_cast<const typename V4<TT>::type*>(win_override)
+                     : c->d_win.as<typename V4<TT>::type>();
         a.ke = c->d_ke.as<typename V2<TT>::type>();
         a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
         a.acc = c->d_acc.as<double2>();
         a.chalf = c->chalf;
         a.Kw = (TT)c->Kw;
         a.Iout = Iout;
-        e = launch_march3d(c->stream, a, c->lanes, accum);
+        int max_steps = 0;
+        if (zdir) {
+            max_steps = c->N;
+        } else {
+            for (const DirDev& D : c->dir_host) max_steps = std::max(max_steps, D.nsteps);
+        }
+        e = launch_march3d(c->stream, a, c->lanes, accum, max_steps);
     } else {
         March1DArgs<TT> a{};
         a.n = (int)c->nc;
@@ -918,8 +940,15 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
             HIPCHK(c, hipMemcpy(extra2.p, st.data(), st.size() * sizeof(st[0]), hipMemcpyHostToDevice));
         }
         HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
-        s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0)
-                 : launch_march<float>(c, 1, trans, false, out.as<float>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0);
+        DevBuf zwin;
+        HIPCHK(c, zwin.ensure((size_t)c->nc * 4 * tsz));
+        HIPCHK(c, launch_window_table(c->stream, (int)c->nc, 1, extra.as<DirDev>(), c->d_vel.as<float4>(),
+                                      c->d_bD.as<double>(), c->dv, c->chalf,
+                                      fp64 ? kWindowK64 : kWindowK32, c->nch, zwin.p, fp64));
+        s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0, zwin.p)
+                 : launch_march<float>(c, 1, trans, false, out.as<float>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0, zwin.p);
+        if (s) return s;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
         if (s) return s;
     } else {
         const double Rout = c->R[c->nc - 1];
