@@ -225,6 +225,7 @@ typedef struct {
     int64_t iterations;          /* ALI/LI iterations run                                    */
     int64_t march_launches;      /* launches of the ray-march kernel                          */
     double march_ms;             /* summed device time of those launches (HIP events)        */
+    double accumulate_ms;        /* per-cell gather of the march's per-step sums (3D grids)  */
     double prepare_ms;           /* populations -> opacity/emissivity kernels                */
     double solve_ms;             /* statistical equilibrium + convergence kernels            */
     double ray_steps;            /* ray-cell steps per transition, summed over launches      */

@@ -61,7 +61,8 @@ class Model3DStruct(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("march_launches", ctypes.c_int64),
-                ("march_ms", ctypes.c_double), ("prepare_ms", ctypes.c_double),
+                ("march_ms", ctypes.c_double), ("accumulate_ms", ctypes.c_double),
+                ("prepare_ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("ray_steps", ctypes.c_double),
                 ("channel_updates", ctypes.c_double)]
 

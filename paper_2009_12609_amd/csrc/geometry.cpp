@@ -97,6 +97,21 @@ DirPattern regular_pattern(const double* d, int N)
         flags = nf;
     }
     P.aw = dm;
+    // layer boundaries and cumulative transverse moves (used to find, for a
+    // cell and a step, which ray of the direction was there)
+    const int ns = (int)P.len.size();
+    P.layer_start.assign(N + 1, ns);
+    P.na.resize(ns);
+    P.nb.resize(ns);
+    int l = 0, ca = 0, cb = 0;
+    P.layer_start[0] = 0;
+    for (int s = 0; s < ns; ++s) {
+        if (P.flags[s] & 1) P.layer_start[++l] = s;
+        if (P.flags[s] & 2) ++ca;
+        if (P.flags[s] & 4) ++cb;
+        P.na[s] = ca;
+        P.nb[s] = cb;
+    }
     return P;
 }
 

@@ -20,6 +20,8 @@ struct DirPattern {
     std::vector<double> len;          // step lengths (cell units)
     std::vector<int> flags;           // moves before each step: 1 m, 2 a, 4 b
     std::vector<double> layer_len;    // path length per layer (from the upstream face)
+    std::vector<int> layer_start;     // first step of each layer, N+1 entries
+    std::vector<int> na, nb;          // moves along a / b made up to and including each step
 };
 DirPattern regular_pattern(const double* d, int N);
 

@@ -164,7 +164,7 @@ __global__ void prepare_kernel(int nc, const MolDev* __restrict__ mol, int ntr,
         typename V2<T>::type v;
         v.x = (T)kap;
         v.y = (T)eta;
-        ke[(size_t)t * nc + k] = v;
+        ke[(size_t)k * ntr + t] = v;
     }
 }
 
@@ -278,9 +278,12 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
     int bid = blockIdx.x;
     const int nb = gridDim.x;
     if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+    // transitions vary fastest: the blocks of all transitions of one ray tile
+    // run back to back on one XCD and share the tile's window and cell lines
+    const int t = p.trans_offset + bid % p.ntr;
+    bid /= p.ntr;
     const int q = bid / p.blocks_per_dir;
     const int r = (bid - q * p.blocks_per_dir) * rpb + rib;
-    const int t = p.trans_offset + blockIdx.y;
     extern __shared__ unsigned char smem_raw[];
     StepRec<T>* __restrict__ sst = reinterpret_cast<StepRec<T>*>(smem_raw);
     T* __restrict__ I = reinterpret_cast<T*>(smem_raw + p.step_lds_bytes) + (size_t)rib * p.ich;
@@ -288,17 +291,26 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
     const DirDev D = p.dirs[q];
     for (int i = threadIdx.x; i < D.nsteps; i += blockDim.x) sst[i] = p.steps[D.step0 + i];
     __syncthreads();
-    if (r >= p.rays_per_dir) return;
+    // Rays past the end of the last tile run a copy of the last ray so that
+    // every lane of the wavefront takes part in the queue flushes; their own
+    // results are never written.
+    const int rpw = 64 / LANES;                 // rays per wavefront
+    const int r_first = r - (rib % rpw);        // first ray of this wavefront
+    if (r_first >= p.rays_per_dir) return;      // the whole wavefront is past the end
+    const bool ray_ok = r < p.rays_per_dir;
+    const int rr = ray_ok ? r : p.rays_per_dir - 1;
 
     const int N = p.N;
-    const int i0 = r % N, j0 = r / N;
+    const int i0 = rr % N, j0 = rr / N;
     int ca = i0, cb = j0;
     int idx = D.start_off + i0 * D.sta + j0 * D.stb;
     const T Ibg = p.Ibg[t];
-    const size_t tb = (size_t)t * p.nc;
+    // {khat, ehat} and {J, Lambda} are stored cell-major: [cell][transition]
+    const int ts = p.ntr_total;
     const T4* __restrict__ win = p.win + (size_t)q * p.nc;
-    const T2* __restrict__ ke = p.ke + tb;
-    double2* __restrict__ acc = p.acc + tb;
+    const T2* __restrict__ ke = p.ke + t;
+    T2* __restrict__ E = p.E ? p.E + (size_t)(t - p.trans_offset) * p.e_tstride + (size_t)D.step0 * p.rays_per_dir
+                             : nullptr;
     const T aw = (T)D.aw;
     const int ns = D.nsteps;
     const T lanef = (T)lane;
@@ -308,15 +320,18 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
 
     for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
 
-    // Per-ray queue of pending accumulations {weighted J sum, weighted Lambda
-    // sum, cell}.  Global atomics without return share the load counter on
-    // this architecture, so an atomic issued every step would make the next
-    // step's load wait for it; instead the group flushes LANES queued steps at
-    // once, one entry per lane.
-    T* __restrict__ qj = reinterpret_cast<T*>(smem_raw + p.queue_lds_offset) + (size_t)rib * 3 * LANES;
-    T* __restrict__ ql = qj + LANES;
-    int* __restrict__ qi = reinterpret_cast<int*>(ql + LANES);
-    int qn = 0;
+    // Per-step partial sums {a len sum_c e_c I_c beta_c, a len sum_c e_c (1 - beta_c)}
+    // are queued in LDS and written every LANES steps to E[step][ray] with
+    // plain stores, one entry per lane of the wavefront (lanes with the same
+    // step write neighbouring rays: contiguous bytes).  Stores and loads share
+    // the memory counter, so writing every step would make each step wait for
+    // the previous step's store; device-scope atomics would in addition be
+    // executed in the memory fabric.  The per-cell sums are formed afterwards
+    // by gather3d_kernel.
+    T2* __restrict__ qw = reinterpret_cast<T2*>(smem_raw + p.queue_lds_offset) + (size_t)(rib - rib % rpw) * LANES;
+    const int wl = threadIdx.x & 63;            // lane in the wavefront
+    const int q_ray = wl % rpw, q_step = wl / rpw;
+    int qn = 0, qs0 = 0;
 
     for (int s = 0; s < ns; ++s) {
         const StepRec<T> rec = sst[s];
@@ -325,7 +340,7 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         if (rec.flags & 2) move_transverse(ca, idx, D.sa, D.sta, N, restart);
         if (rec.flags & 4) move_transverse(cb, idx, D.sb, D.stb, N, restart);
         const T4 wv = win[idx];
-        const T2 kv = ke[idx];
+        const T2 kv = ke[(size_t)idx * ts];
         if (restart) {
             // Side exit: the ray re-enters on the opposite face carrying the
             // background again (Sect. 2.2).
@@ -357,25 +372,68 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
             sl = group_sum<LANES>(sl);
             if (lane == LANES - 1) {
                 const T wgt = aw * rec.len;
-                qj[qn] = wgt * sj;
-                ql[qn] = wgt * sl;
-                qi[qn] = idx;
+                T2 v;
+                v.x = wgt * sj;
+                v.y = wgt * sl;
+                qw[qn * rpw + (rib % rpw)] = v;
             }
             ++qn;
             if (qn == LANES || s == ns - 1) {
-                if (lane < qn) {
-                    double* a = &acc[qi[lane]].x;
-                    unsafeAtomicAdd(a, (double)qj[lane]);
-                    unsafeAtomicAdd(a + 1, (double)ql[lane]);
-                }
+                const int rq = r_first + q_ray;
+                if (q_step < qn && rq < p.rays_per_dir)
+                    E[(size_t)(qs0 + q_step) * p.rays_per_dir + rq] = qw[q_step * rpw + q_ray];
+                qs0 += qn;
                 qn = 0;
             }
         }
     }
-    if (!ACCUM && p.Iout) {
+    if (!ACCUM && p.Iout && ray_ok) {
         T* out = p.Iout + ((size_t)q * p.rays_per_dir + r) * p.nch;
         for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
     }
+}
+
+// Sum, for every cell and transition, the per-step partial sums of all rays
+// of the directions of one main axis that crossed the cell.  Thread = cell;
+// the cell's transverse coordinates (ia, ib) vary fastest so that neighbouring
+// threads read neighbouring rays.  For a step s of direction q the ray that was
+// in the cell started at ((ia - sa na_s) mod N, (ib - sb nb_s) mod N).
+template <typename T>
+__global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
+{
+    using T2 = typename V2<T>::type;
+    const int N = p.N;
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= N * N) return;
+    const int ia = pos % N, ib = pos / N;
+    const int cm = blockIdx.y;
+    const int tl = blockIdx.z;
+    const int NN = N * N;
+    const T2* __restrict__ E = p.E + (size_t)tl * p.e_tstride;
+    double sj = 0.0, sl = 0.0;
+    for (int k = 0; k < p.nq; ++k) {
+        const DirDev& D = p.dirs[p.qlist[k]];
+        const int l = D.fwd ? cm : N - 1 - cm;
+        const int s0 = p.lstart[D.lstart0 + l], s1 = p.lstart[D.lstart0 + l + 1];
+        for (int s = s0; s < s1; ++s) {
+            const int2 mv = p.moves[D.step0 + s];
+            int i0 = ia - D.sa * mv.x;
+            int j0 = ib - D.sb * mv.y;
+            i0 += i0 < 0 ? N : 0;
+            i0 -= i0 >= N ? N : 0;
+            j0 += j0 < 0 ? N : 0;
+            j0 -= j0 >= N ? N : 0;
+            const T2 e = E[(size_t)(D.step0 + s) * NN + j0 * N + i0];
+            sj += (double)e.x;
+            sl += (double)e.y;
+        }
+    }
+    const size_t idx = (size_t)ia * p.st_a + (size_t)ib * p.st_b + (size_t)cm * p.st_m;
+    double2* a = p.acc + idx * p.ntr_total + p.trans_offset + tl;
+    double2 v = *a;
+    v.x += sj;
+    v.y += sl;
+    *a = v;
 }
 
 // ---------------------------------------------------------------- 1D march
@@ -406,7 +464,7 @@ __global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
     const int nin = n - 1 - kmin;
     const int nsteps = 2 * nin + 2;
     const T Ibg = p.Ibg[t];
-    const size_t tb = (size_t)t * n;
+    const int ts = p.ntr_total;      // cell-major [shell][transition]
     for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
 
     double zprev = sqrt((R[n - 1] - b) * (R[n - 1] + b));
@@ -435,7 +493,7 @@ __global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
             mu = zi / R[k - 1];
         }
         const T2 sv = p.shellv[k];
-        const T2 kev = p.ke[tb + k];
+        const T2 kev = p.ke[(size_t)k * ts + t];
         const double w = (double)sv.x * mu;
         int clo, chi;
         T frac;
@@ -448,8 +506,8 @@ __global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
             sl = group_sum<LANES>(sl);
             if (lane == LANES - 1) {
                 const double wgt = a * len;
-                unsafeAtomicAdd(&p.acc[tb + k].x, wgt * (double)sj);
-                unsafeAtomicAdd(&p.acc[tb + k].y, wgt * (double)sl);
+                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, wgt * (double)sj);
+                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, wgt * (double)sl);
             }
         }
     }
@@ -502,7 +560,7 @@ __global__ void se_kernel(SEArgs p)
         for (int t = 0; t < p.ntr; ++t) {
             const int u = mol->up[t], l = mol->lo[t];
             const double A = mol->A[t];
-            const double2 a = p.acc[(size_t)t * p.nc + k];
+            const double2 a = p.acc[(size_t)k * p.ntr + t];
             double J = a.x * q;
             const double Lam = a.y * q;
             double Rul;
@@ -623,13 +681,16 @@ hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
     // Channel vectors are padded by 16 words so that the rays of one
     // wavefront start in different LDS banks.
     a.ich = a.nch + 16;
+    // whole wavefronts only (the queue flush uses every lane of a wavefront)
+    const int rpw = 64 / LANES;
     int rpb = 256 / LANES;
-    while (rpb > 1 && (size_t)rpb * a.ich * sizeof(T) > 65536) rpb >>= 1;
+    while (rpb > rpw && (size_t)rpb * a.ich * sizeof(T) > 65536) rpb >>= 1;
     a.blocks_per_dir = (a.rays_per_dir + rpb - 1) / rpb;
     a.step_lds_bytes = (int)(((size_t)max_steps * sizeof(StepRec<T>) + 15) & ~(size_t)15);
     a.queue_lds_offset = a.step_lds_bytes + (int)((size_t)rpb * a.ich * sizeof(T));
-    const dim3 grid(a.blocks_per_dir * a.n_dir, a.ntr);
-    const size_t shm = (size_t)a.queue_lds_offset + (size_t)rpb * 3 * LANES * sizeof(T);
+    const dim3 grid(a.blocks_per_dir * a.n_dir * a.ntr);
+    const size_t shm = (size_t)a.queue_lds_offset + (size_t)rpb * LANES * 2 * sizeof(T);
+    if (shm > 163840) return hipErrorInvalidValue;
     if (shm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)march3d_kernel<T, LANES, ACCUM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -685,6 +746,17 @@ hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes
 {
     return dispatch1d<double>(s, a, lanes, accum);
 }
+
+template <typename T>
+hipError_t do_gather3d(hipStream_t s, const Gather3DArgs<T>& a)
+{
+    const int bs = 256;
+    const dim3 grid((a.N * a.N + bs - 1) / bs, a.N, a.ntr);
+    hipLaunchKernelGGL(gather3d_kernel<T>, grid, dim3(bs), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a) { return do_gather3d(s, a); }
+hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a) { return do_gather3d(s, a); }
 
 hipError_t launch_se(hipStream_t s, const SEArgs& a0)
 {

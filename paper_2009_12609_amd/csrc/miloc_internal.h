@@ -45,6 +45,8 @@ struct DirDev {
     int stride_m;         // signed memory offset of one move along the main axis
     int start_off;        // memory offset of the start cell of ray (0, 0)
     int step0, nsteps;    // slice of the step table
+    int m, fwd;           // main axis, 1 if d_m > 0
+    int lstart0;          // offset of this direction's N+1 layer starts
 };
 
 template <typename T>
@@ -67,16 +69,31 @@ struct March3DArgs {
     const DirDev* dirs;
     const StepRec<T>* steps;
     const typename V4<T>::type* win;     // [n_dir][nc] {x0, ibs, first channel, n channels}
-    const typename V2<T>::type* ke;      // [ntr][nc] {khat, ehat}
+    const typename V2<T>::type* ke;      // [nc][ntr_total] {khat, ehat}
     const T* Ibg;                        // [ntr], occupation units
-    double2* acc;                        // [ntr][nc] raw {J, Lambda} sums
-    double chalf;                        // 1/2 + v_min/dv
-    T Kw;                                // window half width * ibs (channels * ibs)
+    typename V2<T>::type* E;             // per-step partial sums [ntr][total steps][rays]
+    size_t e_tstride;                    // total steps * rays (one transition of E)
     T* Iout;                             // spectra: [n_dir*rays][nch] or null
     int trans_offset;                    // first transition of this launch
     int step_lds_bytes;                  // LDS bytes reserved for the step list
     int ich;                             // LDS stride of one ray's channel vector
     int queue_lds_offset;                // LDS offset of the per-ray accumulation queues
+    int ntr_total;                       // transitions in ke / acc (cell-major stride)
+};
+
+// Per-cell gather of the per-step partial sums written by march3d, for the
+// directions of one main axis.
+template <typename T>
+struct Gather3DArgs {
+    int N, ntr, trans_offset, ntr_total, nq;
+    int st_a, st_b, st_m;                // memory strides of the group's axes
+    const int* qlist;                    // directions of this main axis
+    const DirDev* dirs;
+    const int* lstart;                   // layer starts
+    const int2* moves;                   // cumulative (a, b) moves per step
+    const typename V2<T>::type* E;
+    size_t e_tstride;
+    double2* acc;                        // [nc][ntr_total]
 };
 
 template <typename T>
@@ -86,13 +103,14 @@ struct March1DArgs {
     const double* bimp;                  // impact parameters / R_out
     const double* area;                  // ray weights / R_out^2
     const typename V2<T>::type* shellv;  // {Ur, ibs} per shell
-    const typename V2<T>::type* ke;      // [ntr][n]
-    const T* Ibg;                        // [ntr]
-    double2* acc;                        // [ntr][n]
+    const typename V2<T>::type* ke;      // [n][ntr_total]
+    const T* Ibg;                        // [ntr_total]
+    double2* acc;                        // [n][ntr_total]
     double chalf;
     T Kw;
     T* Iout;                             // spectra: [nrays][nch] or null
     int trans_offset;
+    int ntr_total;                       // transitions in ke / acc (cell-major stride)
 };
 
 struct SEArgs {
@@ -103,7 +121,7 @@ struct SEArgs {
     const double* nH2;                   // [nc]
     const double* Tkin;                  // [nc]
     const double* q;                     // [nc] dv / (b sqrt(pi) W)
-    const double2* acc;                  // [ntr][nc]
+    const double2* acc;                  // [nc][ntr]
     unsigned long long* delta_bits;      // max relative change (as double bits)
     unsigned int* bad;                   // numeric-failure counter
 };
@@ -124,5 +142,7 @@ hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum);
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes, bool accum);
 hipError_t launch_se(hipStream_t s, const SEArgs& a);
+hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a);
+hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a);
 
 }  // namespace miloc

@@ -102,7 +102,11 @@ struct miloc_ctx {
     bool has_pops = false;
     bool has_rad = false;
     DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
-        d_zero, d_dirs, d_steps, d_flags, d_R, d_bimp, d_area, d_vel, d_bD, d_win;
+        d_zero, d_dirs, d_steps, d_flags, d_R, d_bimp, d_area, d_vel, d_bD, d_win, d_lstart, d_moves,
+        d_qlist, d_E;
+    int64_t total_steps = 0;
+    int trans_chunk = 1;
+    int qcount[3] = {0, 0, 0}, qoff[3] = {0, 0, 0};
     std::vector<double> Iscale, Ibg;   // per transition: 2 h nu^3 / c^2, background (occupation)
     std::vector<double> q_host;
     int lanes = 32;
@@ -243,15 +247,19 @@ miloc_status upload_steps(miloc_ctx* c, const std::vector<double>& len, const st
     return MILOC_OK;
 }
 
-// Build the direction table and step patterns for a list of directions.
+// Build the direction table and step patterns for a list of directions, with
+// the per-direction layer starts and cumulative transverse moves.
 void build_patterns(int N, const std::vector<double>& dirs, std::vector<DirDev>& dd,
-                    std::vector<double>& len, std::vector<int>& fl, std::vector<DirPattern>* keep)
+                    std::vector<double>& len, std::vector<int>& fl, std::vector<DirPattern>* keep,
+                    std::vector<int>* lstart = nullptr, std::vector<int2>* moves = nullptr)
 {
     const int nd = (int)dirs.size() / 3;
     const int64_t stride[3] = {1, N, (int64_t)N * N};
     dd.assign(nd, DirDev{});
     len.clear();
     fl.clear();
+    if (lstart) lstart->clear();
+    if (moves) moves->clear();
     for (int q = 0; q < nd; ++q) {
         const double* d = &dirs[3 * q];
         DirPattern P = regular_pattern(d, N);
@@ -267,8 +275,14 @@ void build_patterns(int N, const std::vector<double>& dirs, std::vector<DirDev>&
         D.start_off = fwd ? 0 : (int)((N - 1) * stride[P.m]);
         D.step0 = (int)len.size();
         D.nsteps = (int)P.len.size();
+        D.m = P.m;
+        D.fwd = fwd ? 1 : 0;
+        D.lstart0 = lstart ? (int)lstart->size() : 0;
         len.insert(len.end(), P.len.begin(), P.len.end());
         fl.insert(fl.end(), P.flags.begin(), P.flags.end());
+        if (lstart) lstart->insert(lstart->end(), P.layer_start.begin(), P.layer_start.end());
+        if (moves)
+            for (size_t i = 0; i < P.na.size(); ++i) moves->push_back(make_int2(P.na[i], P.nb[i]));
         if (keep) keep->push_back(std::move(P));
     }
 }
@@ -334,7 +348,9 @@ miloc_status ensure_static(miloc_ctx* c)
         std::vector<double> len;
         std::vector<int> fl;
         std::vector<DirPattern> pats;
-        build_patterns(N, c->dirs, dd, len, fl, &pats);
+        std::vector<int> lst;
+        std::vector<int2> mvs;
+        build_patterns(N, c->dirs, dd, len, fl, &pats, &lst, &mvs);
         // W(cell) = sum over directions of aw * (path per ray in the cell's layer)
         std::vector<double> Wax[3];
         for (int a = 0; a < 3; ++a) Wax[a].assign(N, 0.0);
@@ -352,6 +368,20 @@ miloc_status ensure_static(miloc_ctx* c)
         c->steps_per_trans = steps;
         c->dir_host = dd;
         c->n_dir_dev = (int)dd.size();
+        c->total_steps = (int64_t)len.size();
+        HIPCHK(c, c->d_lstart.ensure(lst.size() * sizeof(int)));
+        HIPCHK(c, hipMemcpy(c->d_lstart.p, lst.data(), lst.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(c, c->d_moves.ensure(mvs.size() * sizeof(int2)));
+        HIPCHK(c, hipMemcpy(c->d_moves.p, mvs.data(), mvs.size() * sizeof(int2), hipMemcpyHostToDevice));
+        std::vector<int> ql;
+        for (int g = 0; g < 3; ++g) {
+            c->qcount[g] = 0;
+            c->qoff[g] = (int)ql.size();
+            for (int q = 0; q < (int)dd.size(); ++q)
+                if (dd[q].m == g) { ql.push_back(q); ++c->qcount[g]; }
+        }
+        HIPCHK(c, c->d_qlist.ensure(std::max<size_t>(1, ql.size()) * sizeof(int)));
+        HIPCHK(c, hipMemcpy(c->d_qlist.p, ql.data(), ql.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCHK(c, c->d_dirs.ensure(dd.size() * sizeof(DirDev)));
         HIPCHK(c, hipMemcpy(c->d_dirs.p, dd.data(), dd.size() * sizeof(DirDev), hipMemcpyHostToDevice));
         st = fp64 ? upload_steps<double>(c, len, fl) : upload_steps<float>(c, len, fl);
@@ -412,6 +442,15 @@ miloc_status ensure_static(miloc_ctx* c)
     }
     HIPCHK(c, c->d_ke.ensure((size_t)c->T * nc * 2 * tsz));
     HIPCHK(c, c->d_acc.ensure((size_t)c->T * nc * sizeof(double2)));
+    if (c->kind == 3) {
+        // per-step partial sums: as many transitions per march launch as fit the budget
+        double budget_gb = 16.0;
+        if (const char* ev = std::getenv("MILOC_STEP_BUFFER_GB")) budget_gb = std::atof(ev);
+        const size_t per_t = (size_t)c->total_steps * c->N * c->N * 2 * tsz;
+        int tc = (int)std::min<double>((double)c->T, std::floor(budget_gb * 1e9 / (double)per_t));
+        c->trans_chunk = tc < 1 ? 1 : tc;
+        HIPCHK(c, c->d_E.ensure(per_t * c->trans_chunk));
+    }
     c->Ibg.resize(c->T);
     std::vector<char> ib(c->T * tsz);
     for (int t = 0; t < c->T; ++t) {
@@ -460,10 +499,10 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
                      : c->d_win.as<typename V4<TT>::type>();
         a.ke = c->d_ke.as<typename V2<TT>::type>();
         a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
-        a.acc = c->d_acc.as<double2>();
-        a.chalf = c->chalf;
-        a.Kw = (TT)c->Kw;
         a.Iout = Iout;
+        a.ntr_total = c->T;
+        a.E = accum ? c->d_E.as<typename V2<TT>::type>() : nullptr;
+        a.e_tstride = (size_t)c->total_steps * c->N * c->N;
         int max_steps = 0;
         if (zdir) {
             max_steps = c->N;
@@ -488,9 +527,38 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.chalf = c->chalf;
         a.Kw = (TT)c->Kw;
         a.Iout = Iout;
+        a.ntr_total = c->T;
         e = launch_march1d(c->stream, a, c->lanes, accum);
     }
     HIPCHK(c, e);
+    return MILOC_OK;
+}
+
+template <typename TT>
+miloc_status launch_gathers(miloc_ctx* c, int toff, int nt)
+{
+    const int64_t stride[3] = {1, c->N, (int64_t)c->N * c->N};
+    for (int g = 0; g < 3; ++g) {
+        if (c->qcount[g] == 0) continue;
+        Gather3DArgs<TT> a{};
+        a.N = c->N;
+        a.ntr = nt;
+        a.trans_offset = toff;
+        a.ntr_total = c->T;
+        a.nq = c->qcount[g];
+        const int ax_a = g == 0 ? 1 : 0, ax_b = g == 2 ? 1 : 2;
+        a.st_a = (int)stride[ax_a];
+        a.st_b = (int)stride[ax_b];
+        a.st_m = (int)stride[g];
+        a.qlist = c->d_qlist.as<int>() + c->qoff[g];
+        a.dirs = c->d_dirs.as<DirDev>();
+        a.lstart = c->d_lstart.as<int>();
+        a.moves = c->d_moves.as<int2>();
+        a.E = c->d_E.as<typename V2<TT>::type>();
+        a.e_tstride = (size_t)c->total_steps * c->N * c->N;
+        a.acc = c->d_acc.as<double2>();
+        HIPCHK(c, launch_gather3d(c->stream, a));
+    }
     return MILOC_OK;
 }
 
@@ -800,9 +868,35 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
                                  c->d_nmolLb.as<double>(), nullptr, c->d_ke.p, fp64));
         HIPCHK(c, hipMemsetAsync(c->d_acc.p, 0, c->d_acc.bytes, c->stream));
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
-        s = fp64 ? launch_march<double>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
-                 : launch_march<float>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
-        if (s) return s;
+        float t_march = 0, t_gather = 0;
+        if (c->kind == 3) {
+            for (int t0 = 0; t0 < c->T; t0 += c->trans_chunk) {
+                const int nt = std::min(c->trans_chunk, c->T - t0);
+                if (t0 > 0) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+                s = fp64 ? launch_march<double>(c, nt, t0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
+                         : launch_march<float>(c, nt, t0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
+                if (s) return s;
+                HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+                s = fp64 ? launch_gathers<double>(c, t0, nt) : launch_gathers<float>(c, t0, nt);
+                if (s) return s;
+                HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
+                HIPCHK(c, hipEventSynchronize(c->ev[5]));
+                float a = 0, b = 0;
+                HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[4]));
+                HIPCHK(c, hipEventElapsedTime(&b, c->ev[4], c->ev[5]));
+                t_march += a;
+                t_gather += b;
+                c->ctr.march_launches += 1;
+            }
+        } else {
+            s = fp64 ? launch_march<double>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
+                     : launch_march<float>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
+            if (s) return s;
+            HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+            HIPCHK(c, hipEventSynchronize(c->ev[4]));
+            HIPCHK(c, hipEventElapsedTime(&t_march, c->ev[1], c->ev[4]));
+            c->ctr.march_launches += 1;
+        }
         HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
         HIPCHK(c, hipMemsetAsync(c->d_flags.p, 0, 16, c->stream));
         SEArgs a{};
@@ -824,14 +918,13 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
         unsigned long long flags[2] = {0, 0};
         HIPCHK(c, hipMemcpyAsync(flags, c->d_flags.p, 16, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        float t01 = 0, t12 = 0, t23 = 0;
+        float t01 = 0, t23 = 0;
         HIPCHK(c, hipEventElapsedTime(&t01, c->ev[0], c->ev[1]));
-        HIPCHK(c, hipEventElapsedTime(&t12, c->ev[1], c->ev[2]));
         HIPCHK(c, hipEventElapsedTime(&t23, c->ev[2], c->ev[3]));
         c->ctr.prepare_ms += t01;
-        c->ctr.march_ms += t12;
+        c->ctr.march_ms += t_march;
+        c->ctr.accumulate_ms += t_gather;
         c->ctr.solve_ms += t23;
-        c->ctr.march_launches += 1;
         c->ctr.ray_steps += c->steps_per_trans * c->T;
         c->ctr.channel_updates += c->steps_per_trans * c->T * c->nch;
         c->ctr.iterations += 1;
@@ -895,9 +988,10 @@ miloc_status miloc_get_radiation(miloc_ctx* c, double* J_out, double* lambda_out
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int t = 0; t < c->T; ++t)
         for (int64_t k = 0; k < c->nc; ++k) {
-            const size_t i = (size_t)t * c->nc + k;
-            if (J_out) J_out[i] = h[i].x * c->q_host[k] * c->Iscale[t];
-            if (lambda_out) lambda_out[i] = h[i].y * c->q_host[k];
+            const size_t i = (size_t)t * c->nc + k;       // output: transition-major
+            const size_t a = (size_t)k * c->T + t;        // device: cell-major
+            if (J_out) J_out[i] = h[a].x * c->q_host[k] * c->Iscale[t];
+            if (lambda_out) lambda_out[i] = h[a].y * c->q_host[k];
         }
     return MILOC_OK;
 }
