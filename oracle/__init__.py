@@ -84,6 +84,16 @@ def lib():
                                   ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   dp, dp, dp, dp, dp, dp]
+        llp = ctypes.POINTER(ctypes.c_longlong)
+        L.orcoct_march.restype = None
+        L.orcoct_march.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ip, ctypes.c_double,
+                                   dp, dp, dp, dp, dp, dp, ctypes.c_int, dp, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   dp, dp, dp, dp, dp, llp]
+        L.orcoct_map_z.restype = None
+        L.orcoct_map_z.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_double, dp, dp, dp, dp,
+                                   dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -369,7 +379,7 @@ class _Problem:
         self.I_bg = planck(np.asarray(mol.nu, dtype=np.float64), T_bg)
 
 
-def _iterate(prob, march, n_iter, use_ali, x0, tol, record):
+def _iterate(prob, march, n_iter, use_ali, x0, tol, record, solve_mask=None):
     mol = prob.mol
     x = lte_populations(mol, prob.T) if x0 is None else _f64(x0).copy()
     hist = []
@@ -388,8 +398,14 @@ def _iterate(prob, march, n_iter, use_ali, x0, tol, record):
             if not use_ali:
                 S = np.where(kap[t] != 0, eta[t] / np.where(kap[t] != 0, kap[t], 1.0), 0.0)
                 J[t] = J[t] + S * Lam[t]
-        R = rate_matrix(mol, prob.n_H2, prob.T, J, Lam, use_ali)
-        x_new = se_solve(R, x)
+        if solve_mask is None:
+            R = rate_matrix(mol, prob.n_H2, prob.T, J, Lam, use_ali)
+            x_new = se_solve(R, x)
+        else:
+            sel = solve_mask
+            R = rate_matrix(mol, prob.n_H2[sel], prob.T[sel], J[:, sel], Lam[:, sel], use_ali)
+            x_new = x.copy()
+            x_new[sel] = se_solve(R, x[sel])
         delta = max_rel_change(x_new, x)
         if record:
             hist.append(dict(x=x_new.copy(), J=J, Lam=Lam, delta=delta))
@@ -431,6 +447,98 @@ def run_3d(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, tol
                         spec, prob.I_bg[t], n_threads)
 
     return _iterate(prob, march, n_iter, use_ali, x0, tol, record)
+
+
+# ---------------------------------------------------------------------------
+# Octrees (Sect. 2.2)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class OctTree:
+    """Global numbering of an octree model: cells level by level; child[g] is
+    the global index of the first of the 8 children of cell g (-1: leaf)."""
+    N: int
+    Lmax: int
+    child: np.ndarray        # int32 [n_cells]
+    level: np.ndarray        # int32 [n_cells]
+    offsets: np.ndarray      # first global index of each level
+
+    @property
+    def leaf(self) -> np.ndarray:
+        return self.child < 0
+
+
+def octree_of(model) -> OctTree:
+    counts = [int(c) for c in model.n_cells_per_level]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    child = np.full(int(offs[-1]), -1, np.int32)
+    level = np.zeros(int(offs[-1]), np.int32)
+    for lev, fc in enumerate(model.first_child):
+        fc = np.asarray(fc, dtype=np.int64)
+        g = slice(int(offs[lev]), int(offs[lev + 1]))
+        level[g] = lev
+        if lev + 1 < len(counts):
+            child[g] = np.where(fc >= 0, fc + offs[lev + 1], -1)
+    return OctTree(N=int(model.n0[0]), Lmax=len(counts) - 1, child=child, level=level, offsets=offs)
+
+
+OCT_STATS = ("root", "split", "side", "terminated", "wrapped", "steps")
+
+
+def march_oct(tree: OctTree, root_cm, vx, vy, vz, bD, kappa, eta, dirs, spec, I_bg, n_threads=0):
+    """One transition through an octree for the given directions; also returns
+    the ray statistics (dict over OCT_STATS).  kappa None: geometry only."""
+    nc = tree.child.shape[0]
+    dirs = _f64(dirs)
+    geo = kappa is None
+    args = [None] * 6 if geo else list(map(_f64, (vx, vy, vz, bD, kappa, eta)))
+    nch = 0 if geo else spec.n_channels
+    J, Lm, W, E = (np.zeros(nc) for _ in range(4))
+    cons = np.zeros(1)
+    st = np.zeros(len(OCT_STATS), np.int64)
+    child = np.ascontiguousarray(tree.child, dtype=np.int32)
+    lib().orcoct_march(tree.N, tree.Lmax, nc, child.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                       float(root_cm), *[_dp(a) for a in args], dirs.shape[0], _dp(dirs), nch,
+                       0.0 if geo else float(spec.v_min), 1.0 if geo else float(spec.dv),
+                       0.0 if geo else float(I_bg), int(n_threads), _dp(J), _dp(Lm), _dp(W),
+                       _dp(E), _dp(cons), st.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+    return MarchResult(J, Lm, W, E, None, float(cons[0])), dict(zip(OCT_STATS, map(int, st)))
+
+
+def run_oct(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, tol=None,
+            n_threads=0, record=True):
+    """Lambda / ALI iteration on an octree model.  Every cell of every level
+    carries populations; only leaves are marched and solved, refined cells
+    keep their starting values."""
+    tree = octree_of(model)
+    leaf = tree.leaf
+    prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
+    dirs = healpix_nside2() if dirs is None else _f64(dirs)
+    vx, vy, vz = _f64(model.vx), _f64(model.vy), _f64(model.vz)
+
+    def march(t, kap, eta):
+        return march_oct(tree, float(model.root_cell_cm), vx, vy, vz, prob.bD, kap, eta, dirs,
+                         spec, prob.I_bg[t], n_threads)[0]
+
+    res = _iterate(prob, march, n_iter, use_ali, x0, tol, record, solve_mask=leaf)
+    return res
+
+
+def spectra_oct(mol, model, spec, T_bg, x, trans, n_threads=0):
+    """+z map of an octree: one line of sight per root surface element on the
+    level-0 ray lattice, Delta I [N*N (index y*N + x), n_ch]."""
+    tree = octree_of(model)
+    N = tree.N
+    prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
+    kap, eta = prepare(mol, _f64(x), prob.n_mol)
+    out = np.zeros(N * N * spec.n_channels)
+    child = np.ascontiguousarray(tree.child, dtype=np.int32)
+    lib().orcoct_map_z(N, tree.Lmax, child.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                       float(model.root_cell_cm), _dp(_f64(model.vx)), _dp(_f64(model.vy)),
+                       _dp(_f64(model.vz)), _dp(prob.bD), _dp(_f64(kap[trans])), _dp(_f64(eta[trans])),
+                       spec.n_channels, float(spec.v_min), float(spec.dv), float(prob.I_bg[trans]),
+                       int(n_threads), _dp(out))
+    return out.reshape(N * N, spec.n_channels) - prob.I_bg[trans]
 
 
 def spectra_1d(mol, model, spec, T_bg, x, trans, impact=None, n_threads=0):

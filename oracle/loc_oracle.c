@@ -431,3 +431,413 @@ void orc3d_march(int N, double delta, const double* vx, const double* vy, const 
     }
     accum_reduce_free(acc, nt, nc, Jraw, Lraw, Wraw, Eraw, cons);
 }
+
+/* ========================================================================= */
+/* 3D octree (Sect. 2.2)                                                      */
+/* ========================================================================= */
+/*
+ * Tree: an N^3 root grid (level 0, cell (x,y,z) at (z N + y) N + x) whose cells
+ * may be split into 8 children, recursively, down to level Lmax.  Cells are
+ * numbered globally; child[g] is the global index of the first of the 8
+ * children of cell g (child offset cx + 2 cy + 4 cz), or -1 if g is a leaf.
+ * Lengths are in root-cell units inside the tracer.
+ *
+ * Rays of one direction live on nested lattices of lines parallel to the
+ * direction (Sect. 2.2: the ray grid follows the spatial discretisation).  In
+ * coordinates u that increase along the direction of travel on every axis
+ * (u = x for d_x >= 0, u = N - x otherwise), a level-l line pierces the
+ * upstream face u_m = 0 at transverse positions o + i h_l, with h_l = 2^-l root
+ * cells and o = h_Lmax / 2.  A line is labelled by its finest-lattice indices
+ * (la, lb): u_a = (la + 1/2) h_Lmax + t d_a (t = path length); its level is the
+ * coarsest lattice that holds it.  The rules, all from Sect. 2.2:
+ *   - a root line starts on every upstream surface element with the
+ *     background intensity;
+ *   - a ray that enters a leaf finer than its current level through the
+ *     leaf's upstream face splits: for every level between, the three other
+ *     lines of the next level that cross the same upstream face of the
+ *     refined cell start there with a copy of the ray's intensity;
+ *   - the ray entering a leaf C through its upstream face (the only line of
+ *     C's level that does so) checks C's illuminated side faces: where the line
+ *     of C's level that enters through a side face is not already present in
+ *     the neighbouring leaf (the neighbour is coarser than that line's level),
+ *     it is created at that face with the intensity the first ray carried at
+ *     C's upstream face (with the background intensity at the model boundary);
+ *   - each created ray is tagged with its line's level; a ray entering a leaf
+ *     coarser than its tag ends there; otherwise its level becomes the leaf's
+ *     (the photon-count rescaling of the paper is the change of the weight
+ *     a = h_L^2 |d_m| in intensity form);
+ *   - a ray leaving through a side of the model re-enters at the opposite side
+ *     at the same main-axis coordinate with the background intensity; a ray
+ *     leaving through the downstream face ends.
+ * Crossings that coincide (to 1e-10 root cells) are taken one after the other
+ * in the order a-face, b-face, main-axis face, as for lines shifted by an
+ * infinitesimal amount towards +a (and a far smaller one towards +b); cells
+ * are half-open [lo, hi) in u.  Every leaf of level L is then crossed, per
+ * direction, by the level-L lines that meet it, with a total path of
+ * h_L / |d_m|.
+ */
+
+#define OCT_TOL 1.0e-10
+
+typedef struct {
+    int N, Lmax;
+    long long P;             /* finest cells per axis: N << Lmax */
+    double h;                /* finest cell size (root units) */
+    const int* child;
+    int ax[3];               /* storage axis of u-axis 0 (a), 1 (b), 2 (m) */
+    int flip[3];             /* per storage axis: direction component < 0 */
+    double du[3];            /* |d| along u-axes a, b, m */
+} oct_geom_t;
+
+static int oct_geom_init(oct_geom_t* G, int N, int Lmax, const int* child, const double* d)
+{
+    G->N = N;
+    G->Lmax = Lmax;
+    G->P = (long long)N << Lmax;
+    G->h = 1.0 / (double)(1 << Lmax);
+    G->child = child;
+    int m = orc3d_main_axis(d);
+    G->ax[2] = m;
+    G->ax[0] = (m == 0) ? 1 : 0;
+    G->ax[1] = (m == 2) ? 1 : 2;
+    for (int s = 0; s < 3; ++s) G->flip[s] = d[s] < 0.0;
+    for (int u = 0; u < 3; ++u) G->du[u] = fabs(d[G->ax[u]]);
+    return m;
+}
+
+/* Leaf containing the finest cell with u-indices f[0..2] (a, b, m); returns
+ * its global index and level. */
+static long oct_leaf(const oct_geom_t* G, const long long* f, int* level)
+{
+    long long s[3];
+    for (int u = 0; u < 3; ++u) {
+        int sa = G->ax[u];
+        s[sa] = G->flip[sa] ? (G->P - 1 - f[u]) : f[u];
+    }
+    const int L = G->Lmax;
+    long g = ((long)(s[2] >> L) * G->N + (long)(s[1] >> L)) * G->N + (long)(s[0] >> L);
+    int l = 0;
+    while (G->child[g] >= 0) {
+        ++l;
+        const int sh = L - l;
+        const int c = (int)((s[0] >> sh) & 1) + 2 * (int)((s[1] >> sh) & 1) + 4 * (int)((s[2] >> sh) & 1);
+        g = G->child[g] + c;
+    }
+    *level = l;
+    return g;
+}
+
+/* Event order: earlier time first, coinciding times in axis order a, b, m. */
+static int oct_before(double t1, int r1, double t2, int r2)
+{
+    if (t1 < t2 - OCT_TOL) return 1;
+    if (t1 > t2 + OCT_TOL) return 0;
+    return r1 < r2;
+}
+
+static int oct_tz(long long v, int cap)
+{
+    int z = 0;
+    while (z < cap && (v & 1) == 0) { v >>= 1; ++z; }
+    return z;
+}
+
+/* Level of the line with finest-lattice indices (la, lb). */
+static int oct_line_level(const oct_geom_t* G, long long la, long long lb)
+{
+    long long ma = ((la % G->P) + G->P) % G->P, mb = ((lb % G->P) + G->P) % G->P;
+    int za = ma == 0 ? G->Lmax : oct_tz(ma, G->Lmax);
+    int zb = mb == 0 ? G->Lmax : oct_tz(mb, G->Lmax);
+    return G->Lmax - (za < zb ? za : zb);
+}
+
+static long long oct_clampll(long long v, long long lo, long long hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+typedef struct {
+    long long l[2];          /* line indices (a, b) */
+    long long f[3];          /* finest u-indices of the first cell */
+    double t;                /* start time */
+    int entry;               /* axis crossed to enter: 0 a, 1 b, 2 m */
+    int tag, lcur;
+    int vec;                 /* saved intensity vector, -1 = background */
+} oct_ray_t;
+
+typedef struct {
+    oct_ray_t* r;
+    int n, cap;
+    double* vec;             /* saved vectors, nch each */
+    int nv, capv;
+} oct_stack_t;
+
+static void oct_push(oct_stack_t* S, const oct_ray_t* r)
+{
+    if (S->n == S->cap) {
+        S->cap = S->cap ? 2 * S->cap : 64;
+        S->r = (oct_ray_t*)realloc(S->r, sizeof(oct_ray_t) * (size_t)S->cap);
+    }
+    S->r[S->n++] = *r;
+}
+
+static int oct_save(oct_stack_t* S, const double* I, int nch)
+{
+    if (S->nv == S->capv) {
+        S->capv = S->capv ? 2 * S->capv : 16;
+        S->vec = (double*)realloc(S->vec, sizeof(double) * (size_t)S->capv * (size_t)(nch > 0 ? nch : 1));
+    }
+    if (nch > 0) memcpy(S->vec + (size_t)S->nv * nch, I, sizeof(double) * (size_t)nch);
+    return S->nv++;
+}
+
+/* Statistics of a march: rays started (root, split, side), rays ended by a
+ * coarser leaf, model-side re-entries, steps. */
+enum { OCT_ROOT, OCT_SPLIT, OCT_SIDE, OCT_TERM, OCT_WRAP, OCT_STEPS, OCT_NSTAT };
+
+/* Trace every ray that root line (i, j) gives rise to.  With nch == 0 only
+ * the path bookkeeping (W) is done.  'plain' traces the single line without
+ * splitting, side rays or termination (lines of sight for maps); I_end then
+ * receives its final intensity. */
+static void oct_trace_root(const oct_geom_t* G, int i, int j, double root_cm,
+                           const double* dvec, const double* vx, const double* vy, const double* vz,
+                           const double* bD, const double* kappa, const double* eta,
+                           int nch, double vmin, double dv, double I_bg, int plain,
+                           accum_t* A, long long* stats, oct_stack_t* S, double* I, double* I_end)
+{
+    const int Lmax = G->Lmax;
+    const double h = G->h;
+    const double dm = G->du[2];
+    S->n = 0;
+    S->nv = 0;
+    oct_ray_t r0;
+    r0.l[0] = (long long)i << Lmax;
+    r0.l[1] = (long long)j << Lmax;
+    r0.f[0] = r0.l[0];
+    r0.f[1] = r0.l[1];
+    r0.f[2] = 0;
+    r0.t = 0.0;
+    r0.entry = 2;
+    r0.tag = 0;
+    r0.lcur = 0;
+    r0.vec = -1;
+    oct_push(S, &r0);
+    stats[OCT_ROOT]++;
+    while (S->n > 0) {
+        oct_ray_t R = S->r[--S->n];
+        if (nch > 0) {
+            if (R.vec < 0) for (int c = 0; c < nch; ++c) I[c] = I_bg;
+            else memcpy(I, S->vec + (size_t)R.vec * nch, sizeof(double) * (size_t)nch);
+        }
+        for (;;) {
+            int L;
+            const long g = oct_leaf(G, R.f, &L);
+            if (!plain && L < R.tag) { stats[OCT_TERM]++; break; }
+            const long long size = 1LL << (Lmax - L);
+            const double Dc = (double)size * h;
+            long long lo[3];
+            for (int u = 0; u < 3; ++u) lo[u] = (R.f[u] / size) * size;
+            if (!plain && R.entry == 2) {
+                int saved = -1;
+                /* upstream split, one level at a time */
+                for (int l = R.lcur + 1; l <= L; ++l) {
+                    const int sh = Lmax - l;
+                    const long long st = 1LL << sh;
+                    const long long sa = (R.f[0] >> sh) & 1, sb = (R.f[1] >> sh) & 1;
+                    if (saved < 0) saved = oct_save(S, I, nch);
+                    for (long long na = 0; na < 2; ++na)
+                        for (long long nb = 0; nb < 2; ++nb) {
+                            if (na == sa && nb == sb) continue;
+                            oct_ray_t c = R;
+                            c.l[0] = R.l[0] + (na - sa) * st;
+                            c.l[1] = R.l[1] + (nb - sb) * st;
+                            c.f[0] = R.f[0] + (na - sa) * st;
+                            c.f[1] = R.f[1] + (nb - sb) * st;
+                            c.entry = 2;
+                            c.tag = l;
+                            c.lcur = l;
+                            c.vec = saved;
+                            oct_push(S, &c);
+                            stats[OCT_SPLIT]++;
+                        }
+                }
+                /* side rays through the illuminated side faces of C */
+                const double t_mexit = (double)(lo[2] + size) * h / dm;
+                double tx[2] = {INFINITY, INFINITY};
+                for (int x = 0; x < 2; ++x) {
+                    if (!(G->du[x] > 0.0)) continue;
+                    const double rel = ((double)R.l[x] + 0.5) * h + R.t * G->du[x] - (double)lo[x] * h;
+                    tx[x] = R.t + (Dc - rel) / G->du[x];
+                }
+                for (int x = 0; x < 2; ++x) {
+                    const int y = 1 - x;
+                    if (!(G->du[x] > 0.0) || !oct_before(tx[x], x, t_mexit, 2)) continue;
+                    const int shift_y = (G->du[y] > 0.0) && oct_before(tx[y], y, tx[x], x);
+                    long long nl[2];
+                    nl[x] = R.l[x] - size;
+                    nl[y] = R.l[y] - (shift_y ? size : 0);
+                    const int lev = oct_line_level(G, nl[0], nl[1]);
+                    const int boundary = lo[x] == 0;
+                    long long nf[3];
+                    nf[x] = boundary ? G->P - 1 : lo[x] - 1;
+                    nf[y] = lo[y];
+                    nf[2] = lo[2];
+                    int LN;
+                    (void)oct_leaf(G, nf, &LN);
+                    if (!(LN < L && LN < lev)) continue;
+                    oct_ray_t c;
+                    c.l[0] = nl[0];
+                    c.l[1] = nl[1];
+                    c.t = tx[x];
+                    c.f[x] = lo[x];
+                    const double py = ((double)nl[y] + 0.5) * h + tx[x] * G->du[y];
+                    c.f[y] = oct_clampll((long long)floor(py / h), lo[y], lo[y] + size - 1);
+                    c.f[2] = oct_clampll((long long)floor(tx[x] * dm / h), lo[2], lo[2] + size - 1);
+                    c.entry = x;
+                    c.tag = lev;
+                    c.lcur = L;
+                    if (boundary) c.vec = -1;
+                    else {
+                        if (saved < 0) saved = oct_save(S, I, nch);
+                        c.vec = saved;
+                    }
+                    oct_push(S, &c);
+                    stats[OCT_SIDE]++;
+                }
+            }
+            R.lcur = L;
+            /* step through C */
+            double te[3];
+            for (int x = 0; x < 2; ++x)
+                te[x] = G->du[x] > 0.0
+                            ? ((double)(lo[x] + size) * h - ((double)R.l[x] + 0.5) * h) / G->du[x]
+                            : INFINITY;
+            te[2] = (double)(lo[2] + size) * h / dm;
+            int ex = 0;
+            for (int u = 1; u < 3; ++u)
+                if (oct_before(te[u], u, te[ex], ex)) ex = u;
+            double s = te[ex] - R.t;
+            if (s < 0.0) s = 0.0;
+            const double a_w = (Dc * root_cm) * (Dc * root_cm) * dm;
+            const double s_cm = s * root_cm;
+            if (nch > 0) {
+                const double w = vx[g] * dvec[0] + vy[g] * dvec[1] + vz[g] * dvec[2];
+                double in = 0.0, out = 0.0;
+                for (int c = 0; c < nch; ++c) in += I[c];
+                double sj, sl, se;
+                cell_step(nch, vmin, dv, I, kappa[g], eta[g], bD[g], w, s_cm, &sj, &sl, &se);
+                for (int c = 0; c < nch; ++c) out += I[c];
+                if (A) {
+                    A->J[g] += a_w * s_cm * sj;
+                    A->L[g] += a_w * s_cm * sl;
+                    A->E[g] += a_w * s_cm * se;
+                    A->cons += a_w * dv * (in - out);
+                }
+            }
+            if (A) A->W[g] += a_w * s_cm;
+            stats[OCT_STEPS]++;
+            /* cross the exit face */
+            R.t = te[ex];
+            for (int u = 0; u < 3; ++u) {
+                if (u == ex) continue;
+                const double pu = u == 2 ? R.t * dm : ((double)R.l[u] + 0.5) * h + R.t * G->du[u];
+                R.f[u] = oct_clampll((long long)floor(pu / h), lo[u], lo[u] + size - 1);
+            }
+            R.f[ex] = lo[ex] + size;
+            R.entry = ex;
+            if (ex == 2) {
+                if (R.f[2] >= G->P) break;           /* downstream face: the ray escapes */
+            } else if (R.f[ex] >= G->P) {             /* model side: re-enter opposite */
+                R.f[ex] -= G->P;
+                R.l[ex] -= G->P;
+                if (nch > 0) for (int c = 0; c < nch; ++c) I[c] = I_bg;
+                stats[OCT_WRAP]++;
+            }
+        }
+        if (plain && I_end && nch > 0) memcpy(I_end, I, sizeof(double) * (size_t)nch);
+    }
+}
+
+/* March one transition through an octree for all directions (see above).
+ * Per-cell FP64 inputs over all cells (only leaves are used).  Raw sums as
+ * orc3d_march; 'stats' receives OCT_NSTAT counters (may be NULL).  With
+ * nch == 0 only W is produced (kappa, eta, velocities may be NULL). */
+void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_cm,
+                  const double* vx, const double* vy, const double* vz,
+                  const double* bD, const double* kappa, const double* eta,
+                  int n_dir, const double* dirs,
+                  int nch, double vmin, double dv, double I_bg, int n_threads,
+                  double* Jraw, double* Lraw, double* Wraw, double* Eraw, double* cons,
+                  long long* stats)
+{
+    int nt = nthreads_of(n_threads);
+    accum_t* acc = accum_alloc(nt, n_cells);
+    long long* st = (long long*)calloc((size_t)nt * OCT_NSTAT, sizeof(long long));
+    long n_task = (long)n_dir * N * N;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        oct_stack_t S = {0};
+        double* I = (double*)malloc(sizeof(double) * (size_t)(nch > 0 ? nch : 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (long r = 0; r < n_task; ++r) {
+            const int q = (int)(r / ((long)N * N));
+            const int rem = (int)(r % ((long)N * N));
+            oct_geom_t G;
+            oct_geom_init(&G, N, Lmax, child, dirs + 3 * q);
+            oct_trace_root(&G, rem % N, rem / N, root_cm, dirs + 3 * q, vx, vy, vz, bD, kappa, eta,
+                           nch, vmin, dv, I_bg, 0, &acc[tid], st + (size_t)tid * OCT_NSTAT, &S, I, NULL);
+        }
+        free(S.r);
+        free(S.vec);
+        free(I);
+    }
+    accum_reduce_free(acc, nt, n_cells, Jraw, Lraw, Wraw, Eraw, cons);
+    if (stats)
+        for (int k = 0; k < OCT_NSTAT; ++k) {
+            long long v = 0;
+            for (int t = 0; t < nt; ++t) v += st[(size_t)t * OCT_NSTAT + k];
+            stats[k] = v;
+        }
+    free(st);
+}
+
+/* +z map of an octree: one straight line of sight per root surface element
+ * (x, y) on the level-0 ray lattice of the +z direction (transverse offset
+ * h_Lmax / 2 from the element's corner), marched without accumulation.
+ * I_out[(y N + x) * nch + c] is the intensity leaving the top face. */
+void orcoct_map_z(int N, int Lmax, const int* child, double root_cm,
+                  const double* vx, const double* vy, const double* vz,
+                  const double* bD, const double* kappa, const double* eta,
+                  int nch, double vmin, double dv, double I_bg, int n_threads, double* I_out)
+{
+    int nt = nthreads_of(n_threads);
+    const double dz[3] = {0.0, 0.0, 1.0};
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        oct_stack_t S = {0};
+        double* I = (double*)malloc(sizeof(double) * (size_t)nch);
+        long long st[OCT_NSTAT];
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (long r = 0; r < (long)N * N; ++r) {
+            oct_geom_t G;
+            oct_geom_init(&G, N, Lmax, child, dz);
+            oct_trace_root(&G, (int)(r % N), (int)(r / N), root_cm, dz, vx, vy, vz, bD, kappa, eta,
+                           nch, vmin, dv, I_bg, 1, NULL, st, &S, I, I_out + (size_t)r * nch);
+        }
+        free(S.r);
+        free(S.vec);
+        free(I);
+    }
+}

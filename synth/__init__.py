@@ -301,6 +301,131 @@ def uniform_cube(N: int, box_cm: float, n_H2: float, T_kin: float, b_turb: float
 
 
 # ---------------------------------------------------------------------------
+# Octrees
+# ---------------------------------------------------------------------------
+# Layout: level 0 is the N^3 root grid in cell order (z*N + y)*N + x; the
+# children of a refined level-l cell are 8 consecutive level-(l+1) cells,
+# child offset cx + 2 cy + 4 cz, and the refined cells of a level hand out
+# their children in index order.  first_child[l][i] is the level-(l+1) index
+# of the first child of cell i of level l, -1 for a leaf.  Field arrays hold
+# every cell of every level, level by level (values of refined cells are
+# samples at their centres and carry no meaning).
+
+
+def _morton3(x, y, z, bits):
+    m = np.zeros(x.shape, np.int64)
+    for b in range(bits):
+        m |= ((x >> b) & 1).astype(np.int64) << (3 * b)
+        m |= ((y >> b) & 1).astype(np.int64) << (3 * b + 1)
+        m |= ((z >> b) & 1).astype(np.int64) << (3 * b + 2)
+    return m
+
+
+def octree_structure(N_root: int, n_refine: int, frac: float, score):
+    """Refine, level by level, the fraction ``frac`` of cells with the highest
+    ``score(level, ix, iy, iz)`` (ties: lower Morton index first).  Returns
+    (coords per level [(ix, iy, iz) int64 arrays], first_child per level)."""
+    iz, iy, ix = np.meshgrid(np.arange(N_root), np.arange(N_root), np.arange(N_root), indexing="ij")
+    coords = [(ix.reshape(-1).astype(np.int64), iy.reshape(-1).astype(np.int64),
+               iz.reshape(-1).astype(np.int64))]
+    first_child = []
+    for lev in range(n_refine):
+        cx, cy, cz = coords[lev]
+        n = cx.shape[0]
+        n_ref = int(round(frac * n))
+        fc = np.full(n, -1, np.int32)
+        if n_ref > 0:
+            sc = np.asarray(score(lev, cx, cy, cz), dtype=np.float64)
+            bits = int(math.ceil(math.log2(N_root))) + lev + 1
+            order = np.lexsort((_morton3(cx, cy, cz, bits), -sc))
+            chosen = np.sort(order[:n_ref])
+            fc[chosen] = 8 * np.arange(n_ref, dtype=np.int32)
+            off = np.arange(8)
+            kx = (2 * cx[chosen][:, None] + (off & 1)).reshape(-1)
+            ky = (2 * cy[chosen][:, None] + ((off >> 1) & 1)).reshape(-1)
+            kz = (2 * cz[chosen][:, None] + ((off >> 2) & 1)).reshape(-1)
+            coords.append((kx, ky, kz))
+        else:
+            coords.append((np.zeros(0, np.int64),) * 3)
+        first_child.append(fc)
+        if n_ref == 0:
+            break
+    first_child.append(np.full(coords[-1][0].shape[0], -1, np.int32))
+    return coords, first_child
+
+
+def _trilinear(grid, px, py, pz):
+    """Periodic trilinear interpolation of a cell-centred (x, y, z) grid at
+    positions in box units [0, 1)."""
+    G = grid.shape[0]
+    out = np.zeros(px.shape, np.float64)
+    q = [p * G - 0.5 for p in (px, py, pz)]
+    i0 = [np.floor(v).astype(np.int64) for v in q]
+    fr = [v - i for v, i in zip(q, i0)]
+    for dx in (0, 1):
+        wx = fr[0] if dx else 1.0 - fr[0]
+        for dy in (0, 1):
+            wy = fr[1] if dy else 1.0 - fr[1]
+            for dz in (0, 1):
+                wz = fr[2] if dz else 1.0 - fr[2]
+                out += wx * wy * wz * grid[(i0[0] + dx) % G, (i0[1] + dy) % G, (i0[2] + dz) % G]
+    return out
+
+
+def octree_centres(N_root, coords):
+    """Cell centres (box units) of every cell, level by level."""
+    pts = []
+    for lev, (cx, cy, cz) in enumerate(coords):
+        n_l = N_root << lev
+        pts.append(((cx + 0.5) / n_l, (cy + 0.5) / n_l, (cz + 0.5) / n_l))
+    return [np.concatenate([p[k] for p in pts]) for k in range(3)]
+
+
+def octree_cloud(N_root: int = 64, n_refine: int = 4, frac: float = 0.34, grf_N: int = 256,
+                 box_pc: float = 2.0, sigma_ln: float = 1.0, mean_n: float = 1.0e3,
+                 v_rms_kms: float = 1.0, T_kin: float = 15.0, b_turb_kms: float = 0.0,
+                 abundance: float = 1.0e-9, seed: int = 4001) -> Model3D:
+    """Turbulent cloud on an octree: the lognormal k^-4 density and solenoidal
+    k^-4 velocity of ``turbulent_cube`` generated on a grf_N^3 grid and sampled
+    trilinearly (periodic) at every cell centre; each level refines its
+    densest fraction ``frac`` of cells."""
+    g = grf_k4(grf_N, seed)
+    rho = np.exp(sigma_ln * g)
+    rho *= mean_n / rho.mean()
+    u = solenoidal_k4(grf_N, seed, v_rms_kms * KMS)
+
+    def score(lev, cx, cy, cz):
+        n_l = N_root << lev
+        return _trilinear(rho, (cx + 0.5) / n_l, (cy + 0.5) / n_l, (cz + 0.5) / n_l)
+
+    coords, fc = octree_structure(N_root, n_refine, frac, score)
+    px, py, pz = octree_centres(N_root, coords)
+    nc = px.shape[0]
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return Model3D(n0=(N_root,) * 3, root_cell_cm=box_pc * PC_CM / N_root,
+                   n_H2=f32(_trilinear(rho, px, py, pz)), T_kin=f32(np.full(nc, T_kin)),
+                   b_turb=f32(np.full(nc, b_turb_kms * KMS)),
+                   vx=f32(_trilinear(u[0], px, py, pz)), vy=f32(_trilinear(u[1], px, py, pz)),
+                   vz=f32(_trilinear(u[2], px, py, pz)), abundance=f32(np.full(nc, abundance)),
+                   n_oct_levels=len(fc), n_cells_per_level=[int(c[0].shape[0]) for c in coords],
+                   first_child=fc)
+
+
+def octree_random(N_root: int, n_refine: int, frac: float, seed: int, box_cm: float,
+                  n_H2: float, T_kin: float, b_turb: float, abundance: float,
+                  velocity=(0.0, 0.0, 0.0)) -> Model3D:
+    """Octree with uniform fields whose refined cells are drawn at random
+    (seeded): the geometry-only cases of the tests."""
+    rng = np.random.default_rng(seed)
+    coords, fc = octree_structure(N_root, n_refine, frac, lambda lev, cx, cy, cz: rng.random(cx.shape[0]))
+    nc = sum(int(c[0].shape[0]) for c in coords)
+    full = lambda v: np.full(nc, v, np.float32)
+    return Model3D(n0=(N_root,) * 3, root_cell_cm=box_cm / N_root, n_H2=full(n_H2), T_kin=full(T_kin),
+                   b_turb=full(b_turb), vx=full(velocity[0]), vy=full(velocity[1]), vz=full(velocity[2]),
+                   abundance=full(abundance), n_oct_levels=len(fc),
+                   n_cells_per_level=[int(c[0].shape[0]) for c in coords], first_child=fc)
+
+# ---------------------------------------------------------------------------
 # Named workloads
 # ---------------------------------------------------------------------------
 
@@ -335,3 +460,41 @@ def array_digest(*arrays) -> str:
     for a in arrays:
         h.update(np.ascontiguousarray(a).tobytes())
     return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+# 1D request stream (parameter-search style)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ServeRequest:
+    mol: Molecule
+    model: Model1D
+    spec: Spectral
+    arrival_s: float
+    T_bg: float = 2.73
+
+
+def serving_stream(n: int, seed: int = 5001, rate_per_s: float = 100.0,
+                   shells=(50, 2000), levels=(2, 5, 10, 20), channels=(64, 128, 256)):
+    """Requests with Poisson arrivals: shells uniform in [shells], level count
+    and channel count uniform over the given sets, the log-shell geometry of
+    the small 1D cloud (0.01-0.1 pc, n ~ r^-2) with the density scaled by a
+    log-uniform factor in [0.1, 10], T_kin log-uniform in [5, 20] K, infall
+    amplitude log-uniform in [0.01, 0.3] km/s at 0.05 pc with an r^-1/2 law,
+    X = 1e-9, b_turb = 0.2 km/s, +-2 km/s band, one ray per shell."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(n):
+        t += rng.exponential(1.0 / rate_per_s)
+        ns = int(rng.integers(shells[0], shells[1] + 1))
+        L = int(rng.choice(levels))
+        nch = int(rng.choice(channels))
+        dens = float(10 ** rng.uniform(-1, 1))
+        T = float(10 ** rng.uniform(np.log10(5.0), np.log10(20.0)))
+        inf = float(10 ** rng.uniform(np.log10(0.01), np.log10(0.3)))
+        m = cloud_1d_log(n_shells=ns, n_out=1.0e3 * dens, T_kin=T, b_turb_kms=0.2,
+                         abundance=1.0e-9, infall_kms_at_005pc=inf)
+        out.append(ServeRequest(rotor_molecule(L), m, Spectral.symmetric(nch, 2.0), t))
+    return out
