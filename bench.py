@@ -86,6 +86,96 @@ def cpu_baseline(w, budget_s=15.0):
                       f"full {N}^3 cube, all {w.spec.n_channels} channels ({t_total:.1f} s)"}
 
 
+def _pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def serve_bench(n_req=48, seed=5001, tol=1e-6, max_iter=500):
+    """1D request stream (50-2000 shells, 2/5/10/20 levels, 64/128/256
+    channels): model solves/s with every request queued at once (arrival rate
+    far above capacity), p50/p99 latency at 0.5x and 0.8x of that capacity
+    with Poisson arrivals, and the same requests solved one at a time through a
+    single-model context."""
+    import numpy as np
+
+    import paper_2009_12609_amd as miloc
+    import synth
+
+    reqs = synth.serving_stream(n_req, seed=seed)
+    srv = miloc.Server(0, hbm_budget_bytes=8 << 30, max_slots=256)
+    # warm-up: one small request through the whole loop
+    w0 = synth.serving_stream(1, seed=seed + 99, shells=(50, 50))[0]
+    t_w = srv.submit(w0.mol, w0.model, w0.spec, w0.T_bg, tol, max_iter)
+    if not srv.wait(t_w, 120.0):
+        raise RuntimeError("serving warm-up request did not finish")
+    srv.take(t_w)
+
+    def run_stream(rate):
+        t_start = time.perf_counter()
+        tickets = []
+        gaps = np.diff([0.0] + [r.arrival_s for r in reqs]) if rate else None
+        t_next = t_start
+        for i, r in enumerate(reqs):
+            if rate:
+                t_next += gaps[i] * (100.0 / rate)        # stream drawn at 100/s, rescaled
+                dt = t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            tickets.append(srv.submit(r.mol, r.model, r.spec, r.T_bg, tol, max_iter))
+        lat, iters, bad = [], [], 0
+        for t in tickets:
+            if not srv.wait(t, 600.0):
+                raise RuntimeError("serving request did not finish")
+            _, _, info, rc = srv.take(t)
+            bad += rc != miloc.OK
+            lat.append(info["latency_s"])
+            iters.append(info["iterations"])
+        return time.perf_counter() - t_start, lat, iters, bad
+
+    el_sat, lat_sat, iters, bad = run_stream(None)
+    cap = n_req / el_sat
+    st = srv.stats()
+    lat_runs = {}
+    for f in (0.5, 0.8):
+        el, lat, _, b = run_stream(f * cap)
+        bad += b
+        lat_runs[f"{f:g}x"] = {"rate_per_s": f * cap, "p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99)}
+    srv.close()
+
+    # one model at a time on the same GPU, same requests
+    t0 = time.perf_counter()
+    lat1 = []
+    for r in reqs:
+        ts = time.perf_counter()
+        ctx = miloc.Context(0)
+        ctx.load_molecule(r.mol)
+        ctx.load_model_1d(r.model)
+        ctx.set_spectral(r.spec.n_channels, r.spec.v_min, r.spec.dv)
+        ctx.set_background(r.T_bg)
+        ctx.run(max_iter, tol=tol)
+        for t in range(r.mol.n_trans):
+            ctx.spectra(t, impact=np.array([0.0]))
+        ctx.populations()
+        ctx.close()
+        lat1.append(time.perf_counter() - ts)
+    el1 = time.perf_counter() - t0
+    return {
+        "metric": "model solves/s (1D batched, to 1e-6)",
+        "value": cap,
+        "unit": "solves/s",
+        "requests": n_req,
+        "failed": int(bad),
+        "mean_iterations": float(np.mean(iters)),
+        "saturation_s": el_sat,
+        "peak_resident": int(st["peak_active"]),
+        "latency": lat_runs,
+        "one_at_a_time": {"value": n_req / el1, "p50_service_s": _pct(lat1, 50)},
+        "speedup": cap / (n_req / el1),
+        "stream": f"seed {seed}: shells U[50,2000], levels {{2,5,10,20}}, channels {{64,128,256}}, +-2 km/s",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +183,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128, help="grid size (128 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", type=int, default=0, metavar="N_REQ",
+                    help="also run the 1D request stream with N_REQ requests (adds a 'serving' object)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -177,11 +269,14 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "march3d_kernel<float,32,true>",
+            "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true>",
             "bytes_per_step": BYTES_PER_STEP,
             "kernel_source_hash": src_hash,
         },
     }
+    ctx.close()
+    if args.serve > 0:
+        out["serving"] = serve_bench(args.serve)
     if not args.no_cpu_baseline and N == 128:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -230,10 +230,95 @@ typedef struct {
     double solve_ms;             /* statistical equilibrium + convergence kernels            */
     double ray_steps;            /* ray-cell steps per transition, summed over launches      */
     double channel_updates;      /* ray_steps x n_channels (nominal, window not subtracted)  */
+    int32_t march_lanes;         /* lanes per ray of the march kernel (set by the first run) */
+    int32_t reserved;
 } miloc_counters;
 
 miloc_status miloc_get_counters(const miloc_ctx* ctx, miloc_counters* out);
 miloc_status miloc_reset_counters(miloc_ctx* ctx);
+
+/* ----------------------------------------------------------------- serving */
+/* A request loop for 1D models (continuous batching).  Requests are queued by
+ * miloc_server_submit (inputs copied before return) and admitted by a worker
+ * thread of the server when one of max_slots slots is free and the request's
+ * device footprint fits in the remaining part of hbm_budget_bytes (first fit
+ * in arrival order).  Each tick advances every resident model by one ALI
+ * iteration (Sect. 2: march all transitions, FP32 with FP64 accumulation; FP64
+ * equilibrium solves; FP64 convergence test per model) through one captured
+ * HIP graph; models join and leave between ticks.  A model finishes when its
+ * maximum relative change drops below tol (MILOC_OK), after max_iter
+ * iterations (MILOC_ENOTCONV if tol > 0), or on a numerical failure
+ * (MILOC_ENUMERIC); a failing request does not disturb the others.  On
+ * completion the server computes the spectra of every transition towards the
+ * model centre (impact parameter 0).  All server calls are thread-safe.
+ * Limits per request: 2..20 levels, at most 19 transitions x 8192 rays,
+ * 1..2048 shells, 8..1024 channels. */
+typedef struct miloc_server miloc_server;
+
+typedef struct {
+    int iterations;       /* ALI iterations run                                   */
+    double last_delta;    /* maximum relative change of the last iteration        */
+    double latency_s;     /* submit -> result ready (host clock)                  */
+    double queue_s;       /* submit -> admitted                                   */
+    int status;           /* miloc_status of the request                          */
+} miloc_result_info;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, cancelled;
+    int64_t queued, active, peak_active;   /* current / largest number resident   */
+    int64_t ticks;                         /* graph replays                        */
+    double busy_s;                         /* host time spent in ticks             */
+    int64_t arena_used;                    /* device bytes held by resident models */
+} miloc_server_stats;
+
+/* hbm_budget_bytes (>= 1 MiB) is allocated up front as the arena of resident
+ * models; max_slots in 1..4096.  The worker thread starts immediately. */
+miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int max_slots, miloc_server** out);
+
+/* Stops the worker after the current tick; queued requests are dropped. */
+void miloc_server_destroy(miloc_server* server);
+
+const char* miloc_server_last_error(const miloc_server* server);
+
+/* Queue one request.  n_channels, v_min_cms, dv_cms as miloc_set_spectral;
+ * T_bg_K as miloc_set_background; tol > 0 is the convergence threshold of
+ * the maximum relative population change.  *ticket identifies the request.
+ * MILOC_EINVAL for invalid inputs (nothing queued), MILOC_EBUSY if the
+ * request can never fit the budget. */
+miloc_status miloc_server_submit(miloc_server* server, const miloc_molecule* mol, const miloc_model1d* model,
+                                 int n_channels, double v_min_cms, double dv_cms, double T_bg_K, double tol,
+                                 int max_iter, uint64_t* ticket);
+
+/* Device bytes the request would hold in the server's arena while resident
+ * (validates the inputs exactly as miloc_server_submit does; queues nothing).
+ * Lets a caller size hbm_budget_bytes. */
+miloc_status miloc_server_footprint(miloc_server* server, const miloc_molecule* mol, const miloc_model1d* model,
+                                    int n_channels, double v_min_cms, double dv_cms, double T_bg_K,
+                                    size_t* bytes);
+
+/* *done = 1 when the request has finished (any status). */
+miloc_status miloc_server_poll(miloc_server* server, uint64_t ticket, int* done);
+
+/* Block until the request finishes or timeout_s elapses; *done as poll. */
+miloc_status miloc_server_wait(miloc_server* server, uint64_t ticket, double timeout_s, int* done);
+
+/* Sizes of a request's results. */
+miloc_status miloc_server_result_sizes(miloc_server* server, uint64_t ticket, int* n_shells, int* n_levels,
+                                       int* n_trans, int* n_channels);
+
+/* Results of a finished request, which is then forgotten: populations
+ * x_out[n_shells*n_levels], centre spectra dI[n_trans*n_channels]
+ * (erg s^-1 cm^-2 Hz^-1 sr^-1), info.  Any output pointer may be NULL.
+ * Returns the request's status (MILOC_ESTATE if not finished yet or
+ * cancelled). */
+miloc_status miloc_server_take(miloc_server* server, uint64_t ticket, double* x_out, double* spectra_out,
+                               miloc_result_info* info);
+
+/* Cancel a queued or resident request (a resident one leaves after the
+ * current tick). */
+miloc_status miloc_server_cancel(miloc_server* server, uint64_t ticket);
+
+miloc_status miloc_server_get_stats(miloc_server* server, miloc_server_stats* out);
 
 #ifdef __cplusplus
 }

@@ -64,8 +64,25 @@ class Counters(ctypes.Structure):
                 ("march_ms", ctypes.c_double), ("accumulate_ms", ctypes.c_double),
                 ("prepare_ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("ray_steps", ctypes.c_double),
-                ("channel_updates", ctypes.c_double)]
+                ("channel_updates", ctypes.c_double), ("march_lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
+
+class ResultInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("last_delta", ctypes.c_double),
+                ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("peak_active", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("busy_s", ctypes.c_double),
+                ("arena_used", ctypes.c_int64)]
+
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
 
 SIGNATURES = {
     "miloc_version": (ctypes.c_char_p, []),
@@ -89,6 +106,21 @@ SIGNATURES = {
     "miloc_get_spectra": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     "miloc_get_counters": (ctypes.c_int, [_vp, ctypes.POINTER(Counters)]),
     "miloc_reset_counters": (ctypes.c_int, [_vp]),
+    "miloc_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "miloc_server_destroy": (None, [_vp]),
+    "miloc_server_last_error": (ctypes.c_char_p, [_vp]),
+    "miloc_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(MolStruct), ctypes.POINTER(Model1DStruct),
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, _u64p]),
+    "miloc_server_footprint": (ctypes.c_int, [_vp, ctypes.POINTER(MolStruct), ctypes.POINTER(Model1DStruct),
+                                              ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "miloc_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _ip]),
+    "miloc_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_double, _ip]),
+    "miloc_server_result_sizes": (ctypes.c_int, [_vp, ctypes.c_uint64, _ip, _ip, _ip, _ip]),
+    "miloc_server_take": (ctypes.c_int, [_vp, ctypes.c_uint64, _dp, _dp, ctypes.POINTER(ResultInfo)]),
+    "miloc_server_cancel": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "miloc_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
 }
 
 _lib = None
@@ -127,6 +159,107 @@ def _f32(a):
 
 def _ptr(a, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct)) if a is not None else ctypes.POINTER(ct)()
+
+
+def _mol_struct(mol, keep):
+    E, g = _f64(mol.E_K), _f64(mol.g)
+    up = np.ascontiguousarray(np.asarray(mol.up, dtype=np.int32))
+    lo = np.ascontiguousarray(np.asarray(mol.lo, dtype=np.int32))
+    A, nu, gd = _f64(mol.A), _f64(mol.nu), _f64(mol.gamma_down)
+    keep.extend([E, g, up, lo, A, nu, gd])
+    return MolStruct(int(E.shape[0]), _ptr(E, ctypes.c_double), _ptr(g, ctypes.c_double),
+                     int(up.shape[0]), _ptr(up, ctypes.c_int), _ptr(lo, ctypes.c_int),
+                     _ptr(A, ctypes.c_double), _ptr(nu, ctypes.c_double), _ptr(gd, ctypes.c_double),
+                     float(mol.mass_amu))
+
+
+def _model1d_struct(m, keep):
+    arrs = [_f64(a) for a in (m.r_out, m.n_H2, m.T_kin, m.b_turb, m.v_r, m.abundance)]
+    imp = None if getattr(m, "impact", None) is None else _f64(m.impact)
+    keep.extend(arrs + [imp])
+    return Model1DStruct(int(arrs[0].shape[0]), *[_ptr(a, ctypes.c_double) for a in arrs],
+                         int(m.n_rays), _ptr(imp, ctypes.c_double))
+
+
+class Server:
+    """1D request loop with continuous batching (miloc_server_*)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 4 << 30, max_slots: int = 256):
+        self._lib = load_library()
+        h = _vp()
+        rc = self._lib.miloc_server_create(int(device), int(hbm_budget_bytes), int(max_slots), ctypes.byref(h))
+        if rc != OK:
+            raise MilocError(rc, "miloc_server_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.miloc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            msg = self._lib.miloc_server_last_error(self._h)
+            raise MilocError(rc, msg.decode() if msg else "")
+        return rc
+
+    def submit(self, mol, model, spec, T_bg=2.73, tol=1e-6, max_iter=500) -> int:
+        keep = []
+        ms = _mol_struct(mol, keep)
+        md = _model1d_struct(model, keep)
+        t = ctypes.c_uint64(0)
+        self._check(self._lib.miloc_server_submit(self._h, ctypes.byref(ms), ctypes.byref(md),
+                                                  int(spec.n_channels), float(spec.v_min), float(spec.dv),
+                                                  float(T_bg), float(tol), int(max_iter), ctypes.byref(t)))
+        return int(t.value)
+
+    def footprint(self, mol, model, spec, T_bg=2.73) -> int:
+        """Arena bytes the request would hold while resident."""
+        keep = []
+        ms = _mol_struct(mol, keep)
+        md = _model1d_struct(model, keep)
+        b = ctypes.c_size_t(0)
+        self._check(self._lib.miloc_server_footprint(self._h, ctypes.byref(ms), ctypes.byref(md),
+                                                     int(spec.n_channels), float(spec.v_min), float(spec.dv),
+                                                     float(T_bg), ctypes.byref(b)))
+        return int(b.value)
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int(0)
+        self._check(self._lib.miloc_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0) -> bool:
+        d = ctypes.c_int(0)
+        self._check(self._lib.miloc_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s),
+                                                ctypes.byref(d)))
+        return bool(d.value)
+
+    def take(self, ticket: int):
+        """(x [n_shells, n_levels], centre spectra [n_trans, n_channels], info dict, status)."""
+        n, L, T, nch = (ctypes.c_int(0) for _ in range(4))
+        self._check(self._lib.miloc_server_result_sizes(self._h, ctypes.c_uint64(ticket), ctypes.byref(n),
+                                                        ctypes.byref(L), ctypes.byref(T), ctypes.byref(nch)))
+        x = np.zeros((n.value, L.value))
+        sp = np.zeros((T.value, nch.value))
+        info = ResultInfo()
+        rc = self._lib.miloc_server_take(self._h, ctypes.c_uint64(ticket), _ptr(x, ctypes.c_double),
+                                         _ptr(sp, ctypes.c_double), ctypes.byref(info))
+        return x, sp, {k: getattr(info, k) for k, _ in ResultInfo._fields_}, rc
+
+    def cancel(self, ticket: int):
+        self._check(self._lib.miloc_server_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(self._lib.miloc_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
 
 class Context:

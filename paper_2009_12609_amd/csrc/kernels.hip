@@ -144,13 +144,11 @@ __device__ __forceinline__ void window(double w, double chalf, T Kw, T ibs, int 
 // march carries I - I_bg directly: I_out - I_bg = (I_in - I_bg) e^-tau
 // + (ehat - I_bg khat) len e_c beta, without cancellation where I ~ I_bg.
 template <typename T>
-__global__ void prepare_kernel(int nc, const MolDev* __restrict__ mol, int ntr,
-                               const double* __restrict__ x, const double* __restrict__ nmolLb,
-                               const double* __restrict__ ibg_sub,
-                               typename V2<T>::type* __restrict__ ke)
+__device__ __forceinline__ void prepare_cell(int k, const MolDev* __restrict__ mol, int ntr,
+                                             const double* __restrict__ x, const double* __restrict__ nmolLb,
+                                             const double* __restrict__ ibg_sub,
+                                             typename V2<T>::type* __restrict__ ke)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nc) return;
     const int L = mol->L;
     const double* xk = x + (size_t)k * L;
     const double base = nmolLb[k];
@@ -166,6 +164,17 @@ __global__ void prepare_kernel(int nc, const MolDev* __restrict__ mol, int ntr,
         v.y = (T)eta;
         ke[(size_t)k * ntr + t] = v;
     }
+}
+
+template <typename T>
+__global__ void prepare_kernel(int nc, const MolDev* __restrict__ mol, int ntr,
+                               const double* __restrict__ x, const double* __restrict__ nmolLb,
+                               const double* __restrict__ ibg_sub,
+                               typename V2<T>::type* __restrict__ ke)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    prepare_cell<T>(k, mol, ntr, x, nmolLb, ibg_sub, ke);
 }
 
 __global__ void lte_kernel(int nc, const MolDev* __restrict__ mol, const double* __restrict__ Tkin,
@@ -437,95 +446,142 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
 }
 
 // ---------------------------------------------------------------- 1D march
-template <typename T, int LANES, bool ACCUM>
-__global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
-{
-    using T2 = typename V2<T>::type;
-    const int rpb = blockDim.x / LANES;
-    const int lane = threadIdx.x % LANES;
-    const int rib = threadIdx.x / LANES;
-    const int j = blockIdx.x * rpb + rib;
-    const int t = p.trans_offset + blockIdx.y;
-    extern __shared__ unsigned char smem_raw[];
-    T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)rib * p.nch;
-    if (j >= p.nrays) return;
+namespace {
 
-    const int n = p.n;
-    const double* __restrict__ R = p.R;
-    const double b = p.bimp[j];
-    const double a = p.area[j];
-    // innermost shell reached: first k with R[k] > b
+__device__ __forceinline__ int kmin_of(const double* __restrict__ R, int n, double b)
+{
+    // innermost shell reached by a ray of impact parameter b: first k with R[k] > b
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (R[mid] > b) hi = mid; else lo = mid + 1;
     }
-    const int kmin = lo;
-    const int nin = n - 1 - kmin;
-    const int nsteps = 2 * nin + 2;
-    const T Ibg = p.Ibg[t];
-    const int ts = p.ntr_total;      // cell-major [shell][transition]
-    for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+    return lo;
+}
 
-    double zprev = sqrt((R[n - 1] - b) * (R[n - 1] + b));
-    for (int s = 0; s < nsteps; ++s) {
-        int k;
-        double len, mu;
-        if (s < nin) {                       // inwards through shell k
-            k = n - 1 - s;
-            const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
-            len = zprev - zi;
-            mu = -zprev / R[k];
-            zprev = zi;
-        } else if (s == nin) {               // tangent shell, first half
-            k = kmin;
-            len = zprev;
-            mu = -zprev / R[k];
-        } else if (s == nin + 1) {           // tangent shell, second half
-            k = kmin;
-            len = zprev;
-            mu = 0.0;
-        } else {                             // outwards through shell k
-            k = kmin + (s - nin - 1);
-            const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
-            const double zo = sqrt((R[k] - b) * (R[k] + b));
-            len = zo - zi;
-            mu = zi / R[k - 1];
+__device__ __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
+__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+
+}  // namespace
+
+// One workgroup marches rays ray0 .. ray0 + rays_per_block - 1 of one
+// transition through a 1D shell model.  Geometry in FP64 on the fly.  With
+// p.lds_acc the per-step sums go to per-shell LDS accumulators (LDS atomics
+// do not stall the next step's loads) and are flushed to the FP64 global sums
+// once per workgroup; otherwise each step issues two FP64 atomics.
+template <typename T, int LANES, bool ACCUM>
+__device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0, int t, unsigned char* smem_raw)
+{
+    using T2 = typename V2<T>::type;
+    const int lane = threadIdx.x % LANES;
+    const int rib = threadIdx.x / LANES;
+    const int j = ray0 + rib;
+    const int n = p.n;
+    const bool lds_acc = ACCUM && p.lds_acc;
+    T* __restrict__ sacc = reinterpret_cast<T*>(smem_raw);                 // [n][2] when lds_acc
+    T* __restrict__ I = reinterpret_cast<T*>(smem_raw + (lds_acc ? p.acc_lds_bytes : 0)) + (size_t)rib * p.nch;
+    const double* __restrict__ R = p.R;
+    const int ts = p.ntr_total;      // cell-major [shell][transition]
+    const int kmin0 = kmin_of(R, n, p.bimp[ray0]);   // block's rays are sorted by impact parameter
+    if (lds_acc) {
+        for (int k = kmin0 + (int)threadIdx.x; k < n; k += blockDim.x) {
+            sacc[2 * k] = (T)0;
+            sacc[2 * k + 1] = (T)0;
         }
-        const T2 sv = p.shellv[k];
-        const T2 kev = p.ke[(size_t)k * ts + t];
-        const double w = (double)sv.x * mu;
-        int clo, chi;
-        T frac;
-        window<T>(w, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
-        const T tl = (T)len;
-        T sj = 0, sl = 0;
-        step_channels<LANES, T>(I, lane, clo, chi, frac, sv.y, kev.x * tl, kev.y * tl, sj, sl);
-        if (ACCUM) {
-            sj = group_sum<LANES>(sj);
-            sl = group_sum<LANES>(sl);
-            if (lane == LANES - 1) {
-                const double wgt = a * len;
-                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, wgt * (double)sj);
-                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, wgt * (double)sl);
+        __syncthreads();
+    }
+    if (j < p.nrays) {
+        const double b = p.bimp[j];
+        const double a = p.area[j];
+        const int kmin = kmin_of(R, n, b);
+        const int nin = n - 1 - kmin;
+        const int nsteps = 2 * nin + 2;
+        const T Ibg = p.Ibg[t];
+        for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+
+        double zprev = sqrt((R[n - 1] - b) * (R[n - 1] + b));
+        for (int s = 0; s < nsteps; ++s) {
+            int k;
+            double len, mu;
+            if (s < nin) {                       // inwards through shell k
+                k = n - 1 - s;
+                const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
+                len = zprev - zi;
+                mu = -zprev / R[k];
+                zprev = zi;
+            } else if (s == nin) {               // tangent shell, first half
+                k = kmin;
+                len = zprev;
+                mu = -zprev / R[k];
+            } else if (s == nin + 1) {           // tangent shell, second half
+                k = kmin;
+                len = zprev;
+                mu = 0.0;
+            } else {                             // outwards through shell k
+                k = kmin + (s - nin - 1);
+                const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
+                const double zo = sqrt((R[k] - b) * (R[k] + b));
+                len = zo - zi;
+                mu = zi / R[k - 1];
+            }
+            const T2 sv = p.shellv[k];
+            const T2 kev = p.ke[(size_t)k * ts + t];
+            const double w = (double)sv.x * mu;
+            int clo, chi;
+            T frac;
+            window<T>(w, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
+            const T tl = (T)len;
+            T sj = 0, sl = 0;
+            step_channels<LANES, T>(I, lane, clo, chi, frac, sv.y, kev.x * tl, kev.y * tl, sj, sl);
+            if (ACCUM) {
+                sj = group_sum<LANES>(sj);
+                sl = group_sum<LANES>(sl);
+                if (lane == LANES - 1) {
+                    const double wgt = a * len;
+                    if (lds_acc) {
+                        lds_add(&sacc[2 * k], (T)wgt * sj);
+                        lds_add(&sacc[2 * k + 1], (T)wgt * sl);
+                    } else {
+                        unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, wgt * (double)sj);
+                        unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, wgt * (double)sl);
+                    }
+                }
+            }
+        }
+        if (!ACCUM && p.Iout) {
+            T* out = p.Iout + ((size_t)(t - p.trans_offset) * p.nrays + j) * p.nch;
+            for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
+        }
+    }
+    if (lds_acc) {
+        __syncthreads();
+        for (int k = kmin0 + (int)threadIdx.x; k < n; k += blockDim.x) {
+            const T vj = sacc[2 * k], vl = sacc[2 * k + 1];
+            if (vj != (T)0 || vl != (T)0) {
+                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, (double)vj);
+                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, (double)vl);
             }
         }
     }
-    if (!ACCUM && p.Iout) {
-        T* out = p.Iout + (size_t)j * p.nch;
-        for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
-    }
+}
+
+template <typename T, int LANES, bool ACCUM>
+__global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int rpb = blockDim.x / LANES;
+    march1d_block<T, LANES, ACCUM>(p, blockIdx.x * rpb, p.trans_offset + blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------------------- SE solve
 // One thread per cell.  The (L+1) x L augmented matrix lives in LDS with the
 // thread index fastest, M[(row*(L+1) + col)*bs + tid].
-__global__ void se_kernel(SEArgs p)
+// Statistical equilibrium of cell k (Sect. 2): rates with the absorbed counts
+// in place of B I, ALI form with A scaled by the escape probability.  The
+// augmented matrix lives in LDS, sm[(row*(L+1) + col)*bs + tid].  Returns the
+// cell's maximum relative population change (0 if k is out of range).
+__device__ double se_cell(const SEArgs& p, int k, int tid, int bs, double* __restrict__ sm)
 {
-    extern __shared__ double sm[];
-    const int tid = threadIdx.x;
-    const int k = blockIdx.x * blockDim.x + tid;
-    const int bs = p.bs;
     const MolDev* __restrict__ mol = p.mol;
     const int L = p.L;
     const int W = L + 1;
@@ -555,8 +611,7 @@ __global__ void se_kernel(SEArgs p)
                 MM(u, l) += Clu;  MM(l, l) -= Clu;
             }
         }
-        // radiative rates with the absorbed counts in place of B I (Sect. 2);
-        // ALI: A scaled by the escape probability 1 - Lambda
+        // radiative rates; ALI: A scaled by the escape probability 1 - Lambda
         for (int t = 0; t < p.ntr; ++t) {
             const int u = mol->up[t], l = mol->lo[t];
             const double A = mol->A[t];
@@ -619,14 +674,110 @@ __global__ void se_kernel(SEArgs p)
     }
 #undef MM
 #undef BZ
-    // positive doubles order like their bit patterns
+    return dmax;
+}
+
+// Maximum over the block of a non-negative double (bit-pattern order), folded
+// into *dst with one atomic per wavefront (or partial wavefront).
+__device__ __forceinline__ void block_max_to(double v, int bs, unsigned long long* dst)
+{
     const int width = bs < 64 ? bs : 64;
-    unsigned long long bits = (unsigned long long)__double_as_longlong(dmax);
+    unsigned long long bits = (unsigned long long)__double_as_longlong(v);
     for (int o = width >> 1; o > 0; o >>= 1) {
         const unsigned long long other = __shfl_xor(bits, o, width);
         bits = other > bits ? other : bits;
     }
-    if ((tid % width) == 0 && bits != 0ull) atomicMax(p.delta_bits, bits);
+    if (((int)threadIdx.x % width) == 0 && bits != 0ull) atomicMax(dst, bits);
+}
+
+__global__ void se_kernel(SEArgs p)
+{
+    extern __shared__ double sm[];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const double dmax = se_cell(p, k, threadIdx.x, p.bs, sm);
+    block_max_to(dmax, p.bs, p.delta_bits);
+}
+
+// ---------------------------------------------------------------- serving
+// Model-indexed kernels for the 1D request loop.  Each runs a fixed grid that
+// walks a device work list, so one captured graph serves every tick whatever
+// set of models is resident; the lists are rewritten between ticks.
+
+__global__ __launch_bounds__(256) void serve_prepare_kernel(const ServeModel* __restrict__ models,
+                                                            const int2* __restrict__ items,
+                                                            const int* __restrict__ n_items)
+{
+    const int n = *n_items;
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const int2 it = items[w];
+        const ServeModel& M = models[it.x];
+        const int k = it.y + threadIdx.x;
+        if (k < M.nc) {
+            prepare_cell<float>(k, M.mol, M.T, M.x, M.nmolLb, nullptr, M.ke_w);
+            for (int t = 0; t < M.T; ++t) M.acc_w[(size_t)k * M.T + t] = make_double2(0.0, 0.0);
+        }
+        if (it.y == 0 && threadIdx.x == 0) {
+            *M.delta_bits = 0ull;
+            *M.bad = 0u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void serve_march_kernel(const ServeModel* __restrict__ models,
+                                                          const int4* __restrict__ items,
+                                                          const int* __restrict__ n_items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int n = *n_items;
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const int4 it = items[w];                  // model, transition, first ray
+        const March1DArgs<float> a = models[it.x].m;
+        march1d_block<float, 64, true>(a, it.z, it.y, smem_raw);
+        __syncthreads();
+    }
+}
+
+__global__ void serve_se_kernel(const ServeModel* __restrict__ models, const int2* __restrict__ items,
+                                const int* __restrict__ n_items)
+{
+    extern __shared__ double sm[];
+    const int n = *n_items;
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const int2 it = items[w];
+        const ServeModel& M = models[it.x];
+        SEArgs a{};
+        a.nc = M.nc;
+        a.L = M.L;
+        a.ntr = M.T;
+        a.use_ali = 1;
+        a.bs = blockDim.x;
+        a.mol = M.mol;
+        a.x_old = M.x;
+        a.x_new = M.xn;
+        a.nH2 = M.nH2;
+        a.Tkin = M.Tk;
+        a.q = M.q;
+        a.acc = M.acc_w;
+        a.delta_bits = M.delta_bits;
+        a.bad = M.bad;
+        const double dmax = se_cell(a, it.y + threadIdx.x, threadIdx.x, blockDim.x, sm);
+        block_max_to(dmax, blockDim.x, M.delta_bits);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void serve_copy_kernel(const ServeModel* __restrict__ models,
+                                                         const int2* __restrict__ items,
+                                                         const int* __restrict__ n_items)
+{
+    const int n = *n_items;
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const int2 it = items[w];
+        const ServeModel& M = models[it.x];
+        const int k = it.y + threadIdx.x;
+        if (k < M.nc)
+            for (int i = 0; i < M.L; ++i) M.x[(size_t)k * M.L + i] = M.xn[(size_t)k * M.L + i];
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -701,11 +852,13 @@ hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
 }
 
 template <typename T, int LANES, bool ACCUM>
-hipError_t do_march1d(hipStream_t s, const March1DArgs<T>& a)
+hipError_t do_march1d(hipStream_t s, March1DArgs<T> a)
 {
     const int rpb = rays_per_block<T>(LANES, a.nch);
     const dim3 grid((a.nrays + rpb - 1) / rpb, a.ntr);
-    const size_t shm = (size_t)rpb * a.nch * sizeof(T);
+    a.acc_lds_bytes = (int)((((size_t)a.n * 2 * sizeof(T)) + 15) & ~(size_t)15);
+    a.lds_acc = ACCUM && ((size_t)a.acc_lds_bytes + (size_t)rpb * a.nch * sizeof(T) <= 65536) ? 1 : 0;
+    const size_t shm = (a.lds_acc ? (size_t)a.acc_lds_bytes : 0) + (size_t)rpb * a.nch * sizeof(T);
     hipLaunchKernelGGL((march1d_kernel<T, LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
     return hipGetLastError();
 }
@@ -713,6 +866,8 @@ hipError_t do_march1d(hipStream_t s, const March1DArgs<T>& a)
 template <typename T>
 hipError_t dispatch3d(hipStream_t s, const March3DArgs<T>& a, int lanes, bool accum, int max_steps)
 {
+    if (lanes == 8)
+        return accum ? do_march3d<T, 8, true>(s, a, max_steps) : do_march3d<T, 8, false>(s, a, max_steps);
     if (lanes == 16)
         return accum ? do_march3d<T, 16, true>(s, a, max_steps) : do_march3d<T, 16, false>(s, a, max_steps);
     if (lanes == 32)
@@ -757,6 +912,37 @@ hipError_t do_gather3d(hipStream_t s, const Gather3DArgs<T>& a)
 }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a) { return do_gather3d(s, a); }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a) { return do_gather3d(s, a); }
+
+hipError_t launch_serve_tick(hipStream_t s, const ServeTables& tb, const ServeGrid& g)
+{
+    hipLaunchKernelGGL(serve_prepare_kernel, dim3(g.cell_blocks), dim3(256), 0, s, tb.models, tb.cell_items,
+                       tb.n_cell);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(serve_march_kernel, dim3(g.march_blocks), dim3(256), g.march_lds, s, tb.models,
+                       tb.march_items, tb.n_march);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(serve_se_kernel, dim3(g.se_blocks), dim3(g.se_bs), g.se_lds, s, tb.models, tb.se_items,
+                       tb.n_se);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(serve_copy_kernel, dim3(g.cell_blocks), dim3(256), 0, s, tb.models, tb.cell_items,
+                       tb.n_cell);
+    return hipGetLastError();
+}
+
+hipError_t serve_set_attributes(const ServeGrid& g)
+{
+    hipError_t e = hipSuccess;
+    if (g.march_lds > 65536)
+        e = hipFuncSetAttribute((const void*)serve_march_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                g.march_lds);
+    if (e == hipSuccess && g.se_lds > 65536)
+        e = hipFuncSetAttribute((const void*)serve_se_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                g.se_lds);
+    return e;
+}
 
 hipError_t launch_se(hipStream_t s, const SEArgs& a0)
 {

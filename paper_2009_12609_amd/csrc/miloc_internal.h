@@ -108,9 +108,11 @@ struct March1DArgs {
     double2* acc;                        // [n][ntr_total]
     double chalf;
     T Kw;
-    T* Iout;                             // spectra: [nrays][nch] or null
+    T* Iout;                             // spectra: [ntr][nrays][nch] or null
     int trans_offset;
     int ntr_total;                       // transitions in ke / acc (cell-major stride)
+    int lds_acc;                         // per-shell LDS accumulators (set by the launcher)
+    int acc_lds_bytes;                   // their size
 };
 
 struct SEArgs {
@@ -126,7 +128,43 @@ struct SEArgs {
     unsigned int* bad;                   // numeric-failure counter
 };
 
+// One resident model of the 1D request loop (device table entry).  All
+// pointers point into the server's device arena.
+struct ServeModel {
+    March1DArgs<float> m;                // march of all transitions, FP32, LDS accumulators
+    const MolDev* mol;
+    const double* nmolLb;
+    float2* ke_w;                        // = m.ke (writable)
+    double2* acc_w;                      // = m.acc
+    double* x;                           // populations [nc][L]
+    double* xn;                          // solve output
+    const double* nH2;
+    const double* Tk;
+    const double* q;
+    unsigned long long* delta_bits;      // this model's max relative change of the tick
+    unsigned int* bad;
+    int nc, L, T, pad;
+};
+
+// Device work lists of one tick.
+struct ServeTables {
+    const ServeModel* models;
+    const int4* march_items;             // (model, transition, first ray, 0)
+    const int* n_march;
+    const int2* cell_items;              // (model, first cell), 256 cells each
+    const int* n_cell;
+    const int2* se_items;                // (model, first cell), se_bs cells each
+    const int* n_se;
+};
+
+struct ServeGrid {
+    int march_blocks, cell_blocks, se_blocks, se_bs;
+    int march_lds, se_lds;
+};
+
 // Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_serve_tick(hipStream_t s, const ServeTables& tb, const ServeGrid& g);
+hipError_t serve_set_attributes(const ServeGrid& g);
 hipError_t launch_prepare(hipStream_t s, int nc, const MolDev* mol, int ntr, const double* x,
                           const double* nmolLb, const double* ibg_sub, void* ke, bool fp64);
 hipError_t launch_lte(hipStream_t s, int nc, const MolDev* mol, const double* Tkin, double* x);

@@ -335,7 +335,7 @@ miloc_status ensure_static(miloc_ctx* c)
         c->lanes = wmax <= 32.0 ? 32 : 64;
     if (const char* ev = std::getenv("MILOC_LANES")) {
         const int l = std::atoi(ev);
-        if (l == 32 || l == 64 || (l == 16 && c->kind == 3)) c->lanes = l;
+        if (l == 32 || l == 64 || ((l == 16 || l == 8) && c->kind == 3)) c->lanes = l;
     }
 
     // geometry, weights W (in march length units) and q = dv/(b sqrt(pi) W)
@@ -1082,6 +1082,8 @@ miloc_status miloc_get_counters(const miloc_ctx* c, miloc_counters* out)
 {
     if (!c || !out) return MILOC_EINVAL;
     *out = c->ctr;
+    out->march_lanes = c->lanes;
+    out->reserved = 0;
     return MILOC_OK;
 }
 
