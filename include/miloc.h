@@ -124,12 +124,25 @@ typedef struct {
     const double* impact_cm;
 } miloc_model1d;
 
-/* 3D regular model (Sect. 2.2 with the grid unrefined): n0[0] = n0[1] =
- * n0[2] = N (2..1024) cubic cells of side root_cell_cm.  Cell (x, y, z) is
- * stored at index (z*N + y)*N + x.  n_oct_levels must be 0 (octrees are not
- * accepted by this version: MILOC_EINVAL); n_cells_per_level and first_child
- * are then ignored.  Per-cell float fields as in miloc_model1d plus the
- * velocity vector (vx, vy, vz) [cm/s]. */
+/* 3D model on an N^3 root grid of cubic cells of side root_cell_cm
+ * (Sect. 2.2).  Root cell (x, y, z) has index (z*N + y)*N + x.
+ *   n_oct_levels = 0: regular grid, 2 <= N <= 1024; n_cells_per_level and
+ *     first_child are ignored and the fields hold N^3 values.
+ *   n_oct_levels >= 1: octree with levels 0..n_oct_levels-1 (at most 12),
+ *     1 <= N <= 1024.  n_cells_per_level[l] cells per level (level 0: N^3);
+ *     cells are numbered level by level (global index = cells of the levels
+ *     before + index in the level), at most 2^28 - 1 in all.  first_child[l][i]
+ *     (l < n_oct_levels - 1) is the level-(l+1) index of the first of the 8
+ *     children of cell i of level l, children ordered cx + 2 cy + 4 cz by
+ *     their position in the parent, or -1 for a leaf; child blocks are
+ *     multiples of 8, each claimed by exactly one parent, and the last level
+ *     has no children.  The fields hold one value per cell of every level;
+ *     values of refined cells are read but have no effect (their populations
+ *     are left as set).  Rays follow the refinement (new rays where it
+ *     increases, ending where it decreases); 48 directions give every leaf the
+ *     same path length per unit size for each direction.
+ * Per-cell float fields as in miloc_model1d plus the velocity vector
+ * (vx, vy, vz) [cm/s].  The library copies everything it needs. */
 typedef struct {
     int n0[3];
     int n_oct_levels;
@@ -148,6 +161,21 @@ typedef struct {
 /* Loading a model replaces the previous one (1D or 3D) and its populations. */
 miloc_status miloc_load_model_1d(miloc_ctx* ctx, const miloc_model1d* model);
 miloc_status miloc_load_model_3d(miloc_ctx* ctx, const miloc_model3d* model);
+
+/* Ray schedule of an octree model for the given directions (Sect. 2.2), as
+ * the octree march replays it; host computation only (needs no device or
+ * context), for inspection and tests.  With steps_out and trees_out NULL only
+ * the sizes are returned; otherwise steps_out receives 2 * n_steps words
+ * (word 0: cell index in bits 0..27, bit 28 "save the incoming intensity",
+ * bits 29..30 how the intensity starts: 0 continue, 1 background, 2 copy of
+ * the last saved vector, 3 copy of it and drop it; word 1: the step length in
+ * root-cell units as an IEEE float) and trees_out 4 * n_trees values (first
+ * step, step count, direction, root element j*N + i), largest trees first.
+ * plain != 0 traces single lines (no new rays, no ending).  MILOC_EINVAL for
+ * an invalid model or directions. */
+miloc_status miloc_octree_schedule(const miloc_model3d* model, int n_dir, const double* dirs, int plain,
+                                   int64_t* n_steps, int64_t* n_trees, int* max_depth, uint32_t* steps_out,
+                                   int64_t* trees_out);
 
 /* Velocity channels (Sect. 2: a regular velocity grid per ray):
  * centres v_c = v_min + (c + 1/2) dv, c = 0..n_channels-1 (8..4096).  The

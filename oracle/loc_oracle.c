@@ -472,7 +472,9 @@ void orc3d_march(int N, double delta, const double* vx, const double* vy, const 
  * Crossings that coincide (to 1e-10 root cells) are taken one after the other
  * in the order a-face, b-face, main-axis face, as for lines shifted by an
  * infinitesimal amount towards +a (and a far smaller one towards +b); cells
- * are half-open [lo, hi) in u.  Every leaf of level L is then crossed, per
+ * are half-open [lo, hi) in u, and a point that a crossing leaves exactly on
+ * a face of another axis is on the side that order gives (below the face if
+ * that axis comes later).  Every leaf of level L is then crossed, per
  * direction, by the level-L lines that meet it, with a total path of
  * h_L / |d_m|.
  */
@@ -554,6 +556,17 @@ static int oct_line_level(const oct_geom_t* G, long long la, long long lb)
 static long long oct_clampll(long long v, long long lo, long long hi)
 {
     return v < lo ? lo : (v > hi ? hi : v);
+}
+
+/* Finest-cell index along u-axis u of a point at coordinate pos reached by a
+ * crossing of axis ex.  A point on a face of axis u is below it if that
+ * crossing comes later in the order a, b, m, else above it. */
+static long long oct_index_after(const oct_geom_t* G, double pos, int u, int ex)
+{
+    const double x = pos / G->h;
+    const double k = nearbyint(x);
+    if (fabs(x - k) <= OCT_TOL / G->h) return (long long)k - (u > ex ? 1 : 0);
+    return (long long)floor(x);
 }
 
 typedef struct {
@@ -691,8 +704,8 @@ static void oct_trace_root(const oct_geom_t* G, int i, int j, double root_cm,
                     c.t = tx[x];
                     c.f[x] = lo[x];
                     const double py = ((double)nl[y] + 0.5) * h + tx[x] * G->du[y];
-                    c.f[y] = oct_clampll((long long)floor(py / h), lo[y], lo[y] + size - 1);
-                    c.f[2] = oct_clampll((long long)floor(tx[x] * dm / h), lo[2], lo[2] + size - 1);
+                    c.f[y] = oct_clampll(oct_index_after(G, py, y, x), lo[y], lo[y] + size - 1);
+                    c.f[2] = oct_clampll(oct_index_after(G, tx[x] * dm, 2, x), lo[2], lo[2] + size - 1);
                     c.entry = x;
                     c.tag = lev;
                     c.lcur = L;
@@ -741,7 +754,7 @@ static void oct_trace_root(const oct_geom_t* G, int i, int j, double root_cm,
             for (int u = 0; u < 3; ++u) {
                 if (u == ex) continue;
                 const double pu = u == 2 ? R.t * dm : ((double)R.l[u] + 0.5) * h + R.t * G->du[u];
-                R.f[u] = oct_clampll((long long)floor(pu / h), lo[u], lo[u] + size - 1);
+                R.f[u] = oct_clampll(oct_index_after(G, pu, u, ex), lo[u], lo[u] + size - 1);
             }
             R.f[ex] = lo[ex] + size;
             R.entry = ex;

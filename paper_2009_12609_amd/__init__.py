@@ -92,6 +92,8 @@ SIGNATURES = {
     "miloc_load_molecule": (ctypes.c_int, [_vp, ctypes.POINTER(MolStruct)]),
     "miloc_load_model_1d": (ctypes.c_int, [_vp, ctypes.POINTER(Model1DStruct)]),
     "miloc_load_model_3d": (ctypes.c_int, [_vp, ctypes.POINTER(Model3DStruct)]),
+    "miloc_octree_schedule": (ctypes.c_int, [ctypes.POINTER(Model3DStruct), ctypes.c_int, _dp, ctypes.c_int,
+                                             _i64p, _i64p, _ip, ctypes.POINTER(ctypes.c_uint32), _i64p]),
     "miloc_set_spectral": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
     "miloc_set_background": (ctypes.c_int, [_vp, ctypes.c_double]),
     "miloc_set_directions_healpix": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -179,6 +181,47 @@ def _model1d_struct(m, keep):
     keep.extend(arrs + [imp])
     return Model1DStruct(int(arrs[0].shape[0]), *[_ptr(a, ctypes.c_double) for a in arrs],
                          int(m.n_rays), _ptr(imp, ctypes.c_double))
+
+
+def _model3d_struct(m, keep):
+    """Model3DStruct of a regular grid or an octree; arrays kept alive in keep."""
+    arrs = [_f32(a) for a in (m.n_H2, m.T_kin, m.b_turb, m.vx, m.vy, m.vz, m.abundance)]
+    keep.extend(arrs)
+    n0 = (ctypes.c_int * 3)(*[int(v) for v in m.n0])
+    nl = int(getattr(m, "n_oct_levels", 0) or 0)
+    counts = _i64p()
+    fc = ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))()
+    if nl > 0:
+        cnt = np.ascontiguousarray(np.asarray(m.n_cells_per_level, dtype=np.int64))
+        tabs = [np.ascontiguousarray(np.asarray(t, dtype=np.int32)) for t in m.first_child]
+        ptrs = (ctypes.POINTER(ctypes.c_int32) * len(tabs))(*[_ptr(t, ctypes.c_int32) for t in tabs])
+        keep.extend([cnt, tabs, ptrs])
+        counts = _ptr(cnt, ctypes.c_int64)
+        fc = ctypes.cast(ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))
+    return Model3DStruct(n0, nl, float(m.root_cell_cm), counts, fc,
+                         *[_ptr(a, ctypes.c_float) for a in arrs])
+
+
+def octree_schedule(model, dirs, plain=False):
+    """Host-built ray schedule of an octree model (miloc_octree_schedule):
+    (steps uint32 [n_steps, 2], trees int64 [n_trees, 4], max_depth)."""
+    L = load_library()
+    keep = []
+    s = _model3d_struct(model, keep)
+    d = _f64(dirs).reshape(-1, 3)
+    ns, nt, md = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int(0)
+    rc = L.miloc_octree_schedule(ctypes.byref(s), int(d.shape[0]), _ptr(d, ctypes.c_double), int(bool(plain)),
+                                 ctypes.byref(ns), ctypes.byref(nt), ctypes.byref(md), None, None)
+    if rc != OK:
+        raise MilocError(rc, "miloc_octree_schedule failed")
+    steps = np.zeros((ns.value, 2), np.uint32)
+    trees = np.zeros((nt.value, 4), np.int64)
+    rc = L.miloc_octree_schedule(ctypes.byref(s), int(d.shape[0]), _ptr(d, ctypes.c_double), int(bool(plain)),
+                                 ctypes.byref(ns), ctypes.byref(nt), ctypes.byref(md),
+                                 _ptr(steps, ctypes.c_uint32), _ptr(trees, ctypes.c_int64))
+    if rc != OK:
+        raise MilocError(rc, "miloc_octree_schedule failed")
+    return steps, trees, md.value
 
 
 class Server:
@@ -311,11 +354,8 @@ class Context:
         self._check(self._lib.miloc_load_model_1d(self._h, ctypes.byref(s)))
 
     def load_model_3d(self, m):
-        arrs = [_f32(a) for a in (m.n_H2, m.T_kin, m.b_turb, m.vx, m.vy, m.vz, m.abundance)]
-        n0 = (ctypes.c_int * 3)(*[int(v) for v in m.n0])
-        s = Model3DStruct(n0, int(getattr(m, "n_oct_levels", 0)), float(m.root_cell_cm),
-                          _i64p(), ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))(),
-                          *[_ptr(a, ctypes.c_float) for a in arrs])
+        keep = []
+        s = _model3d_struct(m, keep)
         self._check(self._lib.miloc_load_model_3d(self._h, ctypes.byref(s)))
 
     def set_spectral(self, n_channels: int, v_min: float, dv: float):

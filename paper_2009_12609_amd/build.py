@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmiloc.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "geometry.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "geometry.cpp", "octree.cpp", "server.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -445,6 +445,111 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
     *a = v;
 }
 
+// ---------------------------------------------------------------- octree march
+// Persistent lane groups of 16 take work units (one root line's rays for one
+// transition) from a global counter, largest units first.  Each unit replays
+// its host-built step list: a record names the leaf and the step length and
+// says how the ray's intensity starts (continue, background, or the top saved
+// vector, Sect. 2.2: new rays copy the intensity of the ray that creates
+// them) and whether to save the incoming intensity first.  Saved vectors live
+// in a per-group stack in device memory.  The step itself is the regular
+// grid's: channel window of the (direction, leaf) pair, I e^-tau + S(1 -
+// e^-tau), absorbed-count and Lambda sums folded into FP64 accumulators.
+template <typename T, bool ACCUM>
+__global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
+{
+    constexpr int LANES = 16;
+    using T2 = typename V2<T>::type;
+    using T4 = typename V4<T>::type;
+    const int lane = threadIdx.x % LANES;
+    const int grp = threadIdx.x / LANES;
+    const size_t gid = (size_t)blockIdx.x * (blockDim.x / LANES) + grp;
+    extern __shared__ unsigned char smem_raw[];
+    T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)grp * p.ich;
+    T* __restrict__ stk = p.stack + gid * (size_t)p.depth * p.ich;
+    const T lanef = (T)lane;
+    for (;;) {
+        unsigned long long item = 0;
+        if (lane == 0) item = atomicAdd(p.counter, 1ull);
+        item = __shfl(item, 0, LANES);
+        if (item >= (unsigned long long)p.n_items) break;
+        const long long tree = (long long)(item / (unsigned long long)p.ntr);
+        const int t = p.trans_offset + (int)(item % (unsigned long long)p.ntr);
+        const OctTreeRec tr = p.trees[tree];
+        const T4* __restrict__ win = p.win + (size_t)tr.q * p.nc;
+        const T2* __restrict__ ke = p.ke + t;
+        const uint2* __restrict__ rec = p.steps + tr.off;
+        const T aw = (T)p.aw[tr.q];
+        const T Ibg = p.Ibg[t];
+        const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
+        int sp = -1;
+        uint2 mine = make_uint2(0u, 0u);
+        double mine64 = 0.0;
+        for (int s = 0; s < tr.n; ++s) {
+            const int k = s & (LANES - 1);
+            if (k == 0) {
+                const int si = s + lane;
+                mine = si < tr.n ? rec[si] : make_uint2(0u, 0u);
+                if (sizeof(T) == 8 && rec64) mine64 = si < tr.n ? rec64[si] : 0.0;
+            }
+            const unsigned w0 = __shfl(mine.x, k, LANES);
+            T len = (T)__uint_as_float(__shfl(mine.y, k, LANES));
+            if (sizeof(T) == 8 && rec64) len = (T)__shfl(mine64, k, LANES);
+            const int cell = (int)(w0 & kOctCellMask);
+            const unsigned mode = w0 >> kOctModeShift;
+            if (mode == kOctModeBg) {
+                for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+            } else if (mode != kOctModeKeep && sp >= 0) {
+                const T* __restrict__ src = stk + (size_t)sp * p.ich;
+                for (int c = lane; c < p.nch; c += LANES) I[c] = src[c];
+                if (mode == kOctModePop) --sp;
+            }
+            if ((w0 & kOctSave) && sp + 1 < p.depth) {
+                ++sp;
+                T* __restrict__ dst = stk + (size_t)sp * p.ich;
+                for (int c = lane; c < p.nch; c += LANES) dst[c] = I[c];
+            }
+            __builtin_amdgcn_wave_barrier();
+            const T4 wv = win[cell];
+            const T2 kv = ke[(size_t)cell * p.ntr_total];
+            const int clo = as_int(wv.z);
+            const int nwin = as_int(wv.w);
+            const T kl = kv.x * len;
+            const T el = kv.y * len;
+            T sj = 0, sl = 0;
+            const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
+            for (int j = lane; j < nwin; j += LANES) {
+                T* __restrict__ cp = I + clo + j;
+                const T xs = (lanef + (T)(j - lane)) * wv.y + wv.x;
+                const T ec = fast_exp2(-xs * xs);
+                const T tau = kl * ec;
+                const T omb = thin ? omb_thin(tau) : omb_any(tau);
+                const T Iin = *cp;
+                const T u = ec - ec * omb;
+                sj += Iin * u;
+                sl += ec * omb;
+                *cp = Iin + u * (el - kl * Iin);
+            }
+            if (ACCUM) {
+                sj = group_sum<LANES>(sj);
+                sl = group_sum<LANES>(sl);
+                if (lane == LANES - 1) {
+                    const double wgt = (double)(aw * len);
+                    double2* a = p.acc + (size_t)cell * p.ntr_total + t;
+                    unsafeAtomicAdd(&a->x, wgt * (double)sj);
+                    unsafeAtomicAdd(&a->y, wgt * (double)sl);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (!ACCUM && p.Iout) {
+            T* out = p.Iout + (size_t)tr.r * p.nch;
+            for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // ---------------------------------------------------------------- 1D march
 namespace {
 
@@ -595,6 +700,11 @@ __device__ double se_cell(const SEArgs& p, int k, int tid, int bs, double* __res
         const double nH2 = p.nH2[k];
         const double T = p.Tkin[k];
         const double q = p.q[k];
+        if (q < 0.0) {
+            // a refined octree cell: no rays cross it, its populations are kept
+            for (int i = 0; i < L; ++i) p.x_new[(size_t)k * L + i] = xo[i];
+            return 0.0;
+        }
 
         for (int i = 0; i < L; ++i) {
             for (int j = 0; j < W; ++j) MM(i, j) = 0.0;
@@ -912,6 +1022,31 @@ hipError_t do_gather3d(hipStream_t s, const Gather3DArgs<T>& a)
 }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a) { return do_gather3d(s, a); }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a) { return do_gather3d(s, a); }
+
+template <typename T>
+hipError_t do_march_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, bool accum)
+{
+    constexpr int kGroupsPerBlock = 16;
+    const int blocks = (groups + kGroupsPerBlock - 1) / kGroupsPerBlock;
+    const size_t shm = (size_t)kGroupsPerBlock * a.ich * sizeof(T);
+    if (shm > 64 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipMemsetAsync(a.counter, 0, sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    if (accum)
+        hipLaunchKernelGGL((march_oct_kernel<T, true>), dim3(blocks), dim3(kGroupsPerBlock * 16), shm, s, a);
+    else
+        hipLaunchKernelGGL((march_oct_kernel<T, false>), dim3(blocks), dim3(kGroupsPerBlock * 16), shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum)
+{
+    return do_march_oct(s, a, groups, accum);
+}
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<double>& a, int groups, bool accum)
+{
+    return do_march_oct(s, a, groups, accum);
+}
 
 hipError_t launch_serve_tick(hipStream_t s, const ServeTables& tb, const ServeGrid& g)
 {

@@ -122,7 +122,7 @@ struct SEArgs {
     double* x_new;                       // [nc][L]
     const double* nH2;                   // [nc]
     const double* Tkin;                  // [nc]
-    const double* q;                     // [nc] dv / (b sqrt(pi) W)
+    const double* q;                     // [nc] dv / (b sqrt(pi) W); < 0: cell not solved
     const double2* acc;                  // [nc][ntr]
     unsigned long long* delta_bits;      // max relative change (as double bits)
     unsigned int* bad;                   // numeric-failure counter
@@ -162,6 +162,44 @@ struct ServeGrid {
     int march_lds, se_lds;
 };
 
+// Octree ray schedules.  Step record: word 0 = cell | flags, word 1 = the
+// step length (root-cell units) as float bits.
+constexpr uint32_t kOctCellMask = 0x0FFFFFFFu;
+constexpr uint32_t kOctSave = 1u << 28;        // push the incoming intensity before the step
+constexpr int kOctModeShift = 29;              // how the intensity starts at this step:
+constexpr uint32_t kOctModeKeep = 0;           //   continue
+constexpr uint32_t kOctModeBg = 1;             //   background (ray start or side re-entry)
+constexpr uint32_t kOctModePeek = 2;           //   copy of the top saved vector
+constexpr uint32_t kOctModePop = 3;            //   copy of the top saved vector, then drop it
+
+// One work unit: every ray one root line gives rise to, in processing order.
+struct OctTreeRec {
+    int64_t off;     // first step record
+    int32_t n;       // records
+    int32_t q;       // direction
+    int32_t r;       // root element (j N + i) on the upstream face
+    int32_t depth;   // saved vectors alive at most
+};
+
+template <typename T>
+struct OctMarchArgs {
+    int nc, nch, ich;                    // cells, channels, LDS stride of a channel vector
+    int ntr, trans_offset, ntr_total;    // transitions of this launch / in ke and acc
+    long long n_items;                   // trees x ntr (transitions vary fastest)
+    const OctTreeRec* trees;
+    const uint2* steps;
+    const double* len64;                 // FP64 step lengths (FP64 march), else null
+    const double* aw;                    // |d_m| per direction
+    const typename V4<T>::type* win;     // [n_dir][nc]
+    const typename V2<T>::type* ke;      // [nc][ntr_total]
+    const T* Ibg;                        // [ntr_total]
+    double2* acc;                        // [nc][ntr_total] {J, Lambda} raw sums
+    T* Iout;                             // no accumulation: [trees][nch] leaving intensity
+    unsigned long long* counter;         // work counter, zero at launch
+    T* stack;                            // [groups][depth][ich] saved vectors
+    int depth;
+};
+
 // Kernel launchers (kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_serve_tick(hipStream_t s, const ServeTables& tb, const ServeGrid& g);
 hipError_t serve_set_attributes(const ServeGrid& g);
@@ -182,5 +220,8 @@ hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes
 hipError_t launch_se(hipStream_t s, const SEArgs& a);
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a);
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a);
+// groups: lane groups of 16 (the persistent grid); the counter is cleared here.
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum);
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<double>& a, int groups, bool accum);
 
 }  // namespace miloc

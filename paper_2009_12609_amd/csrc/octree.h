@@ -1,0 +1,47 @@
+// octree.h -- host-side octree ray schedules (see octree.cpp).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "miloc_internal.h"
+
+namespace miloc {
+
+// An octree in global cell numbering: level-0 root cells (z N + y) N + x
+// first, then each level in turn; child[g] is the global index of the first
+// of the 8 children (offset cx + 2 cy + 4 cz) of cell g, -1 for a leaf.
+struct OctModel {
+    int N = 0;
+    int Lmax = 0;
+    std::vector<int32_t> child;
+    std::vector<int8_t> level;
+    std::vector<int64_t> level_start;   // first global index of each level (+ total)
+};
+
+// Builds the global numbering from per-level first-child tables and checks
+// that every child block lies inside the next level and is claimed once.
+// Returns an empty string on success, else the reason.
+std::string octree_from_levels(int N, int n_levels, const int64_t* n_cells_per_level,
+                               const int32_t* const* first_child, OctModel& out);
+
+struct OctSchedule {
+    std::vector<uint32_t> rec;        // 2 words per step
+    std::vector<double> len64;        // FP64 step lengths (only when asked for)
+    std::vector<OctTreeRec> trees;
+    int max_depth = 0;
+    int64_t n_steps = 0;
+    int64_t n_rays = 0;
+};
+
+// Ray schedule of every root element and direction (Sect. 2.2); 'plain'
+// traces single lines (no new rays, no termination: lines of sight).  Trees
+// are ordered by decreasing length.  Uses up to n_threads host threads.
+// want_len64 also keeps the FP64 step lengths (for the FP64 march).
+// Returns an empty string on success, else the reason.
+std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, bool plain, int n_threads,
+                            OctSchedule& out, bool want_len64 = false);
+
+}  // namespace miloc

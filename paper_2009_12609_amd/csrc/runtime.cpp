@@ -10,9 +10,11 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "geometry.h"
+#include "octree.h"
 #include "miloc.h"
 #include "miloc_internal.h"
 
@@ -80,13 +82,14 @@ struct miloc_ctx {
     double mass_amu = 0;
 
     // model
-    int kind = 0;   // 1: 1D shells, 3: 3D regular grid
+    int kind = 0;   // 1: 1D shells, 3: 3D regular grid, 4: octree
     int64_t nc = 0;
     std::vector<double> R, nH2, Tk, bt, vr, X, impact;   // 1D (FP64)
     int nrays = 0;
     int N = 0;
     double delta = 0;
     std::vector<float> f_nH2, f_T, f_bt, f_vx, f_vy, f_vz, f_X;   // 3D
+    OctModel oct;                                                 // octree structure
 
     // settings
     bool has_spec = false;
@@ -103,7 +106,9 @@ struct miloc_ctx {
     bool has_rad = false;
     DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
         d_zero, d_dirs, d_steps, d_flags, d_R, d_bimp, d_area, d_vel, d_bD, d_win, d_lstart, d_moves,
-        d_qlist, d_E;
+        d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter;
+    int64_t oct_trees = 0;
+    int oct_depth = 0, oct_groups = 0;
     int64_t total_steps = 0;
     int trans_chunk = 1;
     int qcount[3] = {0, 0, 0}, qoff[3] = {0, 0, 0};
@@ -287,6 +292,110 @@ void build_patterns(int N, const std::vector<double>& dirs, std::vector<DirDev>&
     }
 }
 
+int host_threads()
+{
+    const unsigned n = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, n));
+}
+
+// Upload an octree schedule; returns the device buffers through the arguments.
+miloc_status upload_oct_schedule(miloc_ctx* c, const OctSchedule& S, DevBuf& steps, DevBuf& trees)
+{
+    HIPCHK(c, steps.ensure(std::max<size_t>(1, S.rec.size()) * sizeof(uint32_t)));
+    HIPCHK(c, hipMemcpy(steps.p, S.rec.data(), S.rec.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHK(c, trees.ensure(std::max<size_t>(1, S.trees.size()) * sizeof(OctTreeRec)));
+    HIPCHK(c, hipMemcpy(trees.p, S.trees.data(), S.trees.size() * sizeof(OctTreeRec), hipMemcpyHostToDevice));
+    return MILOC_OK;
+}
+
+// Octree: ray schedules of every direction, direction table, weights W
+// (root-cell units) and the persistent-group stack.
+miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
+{
+    const int nd = (int)c->dirs.size() / 3;
+    OctSchedule S;
+    const bool fp64 = c->precision == MILOC_MARCH_FP64;
+    const std::string e = octree_schedule(c->oct, c->dirs, false, host_threads(), S, fp64);
+    if (!e.empty()) return fail(c, MILOC_EINVAL, e);
+    if (fp64) {
+        HIPCHK(c, c->d_olen64.ensure(std::max<size_t>(1, S.len64.size()) * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->d_olen64.p, S.len64.data(), S.len64.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        c->d_olen64.release();
+    }
+    std::vector<DirDev> dd(nd);
+    std::vector<double> aw(nd);
+    for (int q = 0; q < nd; ++q) {
+        const double* d = &c->dirs[3 * (size_t)q];
+        DirDev& D = dd[q];
+        D.d[0] = d[0]; D.d[1] = d[1]; D.d[2] = d[2];
+        D.m = main_axis(d);
+        D.aw = std::fabs(d[D.m]);
+        aw[q] = D.aw;
+    }
+    // per direction every leaf of level L carries h_L^3 of sum a s (Sect. 2.2:
+    // equal path length per cell for each direction)
+    for (int64_t k = 0; k < c->nc; ++k) {
+        const double hl = std::ldexp(1.0, -(int)c->oct.level[k]);
+        W[k] = c->oct.child[k] >= 0 ? 0.0 : nd * hl * hl * hl;
+    }
+    c->dir_host = dd;
+    c->n_dir_dev = nd;
+    c->steps_per_trans = (double)S.n_steps;
+    c->total_steps = S.n_steps;
+    c->oct_trees = (int64_t)S.trees.size();
+    c->oct_depth = S.max_depth;
+    HIPCHK(c, c->d_dirs.ensure(dd.size() * sizeof(DirDev)));
+    HIPCHK(c, hipMemcpy(c->d_dirs.p, dd.data(), dd.size() * sizeof(DirDev), hipMemcpyHostToDevice));
+    HIPCHK(c, c->d_oaw.ensure(aw.size() * sizeof(double)));
+    HIPCHK(c, hipMemcpy(c->d_oaw.p, aw.data(), aw.size() * sizeof(double), hipMemcpyHostToDevice));
+    miloc_status st = upload_oct_schedule(c, S, c->d_osteps, c->d_otrees);
+    if (st != MILOC_OK) return st;
+    // persistent groups: 8 blocks of 16 groups per compute unit, fewer if the
+    // saved-vector stacks would pass 2 GB
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
+    const size_t tsz = c->precision == MILOC_MARCH_FP64 ? sizeof(double) : sizeof(float);
+    const size_t per_group = (size_t)std::max(1, c->oct_depth) * c->nch * tsz;
+    int64_t groups = (int64_t)prop.multiProcessorCount * 8 * 16;
+    groups = std::min<int64_t>(groups, std::max<int64_t>(16, (int64_t)((2ull << 30) / per_group)));
+    groups = std::min<int64_t>(groups, std::max<int64_t>(16, c->oct_trees * c->T));
+    groups = (groups + 15) / 16 * 16;
+    c->oct_groups = (int)groups;
+    HIPCHK(c, c->d_ostack.ensure((size_t)groups * per_group));
+    HIPCHK(c, c->d_ocounter.ensure(sizeof(unsigned long long)));
+    return MILOC_OK;
+}
+
+template <typename TT>
+miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, const DevBuf& steps,
+                        const DevBuf& trees, int64_t n_trees, const double* aw, const void* win, int groups,
+                        const double* len64)
+{
+    OctMarchArgs<TT> a{};
+    a.nc = (int)c->nc;
+    a.nch = c->nch;
+    a.ich = c->nch;
+    a.ntr = ntr;
+    a.trans_offset = toff;
+    a.ntr_total = c->T;
+    a.n_items = (long long)n_trees * ntr;
+    a.trees = trees.as<OctTreeRec>();
+    a.steps = steps.as<uint2>();
+    a.len64 = len64;
+    a.aw = aw;
+    a.win = reinterpret_cast<const typename V4<TT>::type*>(win);
+    a.ke = c->d_ke.as<typename V2<TT>::type>();
+    a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
+    a.acc = c->d_acc.as<double2>();
+    a.Iout = Iout;
+    a.counter = c->d_ocounter.as<unsigned long long>();
+    a.stack = c->d_ostack.as<TT>();
+    a.depth = accum ? c->oct_depth : 0;
+    HIPCHK(c, launch_march_oct(c->stream, a, groups, accum));
+    return MILOC_OK;
+}
+
 // Everything the march needs beyond the base arrays (needs the spectral grid).
 miloc_status ensure_static(miloc_ctx* c)
 {
@@ -303,7 +412,7 @@ miloc_status ensure_static(miloc_ctx* c)
         b[k] = doppler_b(cv.T(k), cv.bt(k), c->mass_amu);
         maxb = std::max(maxb, b[k]);
         double u;
-        if (c->kind == 3) {
+        if (c->kind >= 3) {
             const double ux = c->f_vx[k], uy = c->f_vy[k], uz = c->f_vz[k];
             u = std::sqrt(ux * ux + uy * uy + uz * uz);
         } else {
@@ -331,11 +440,13 @@ miloc_status ensure_static(miloc_ctx* c)
     const double wmax = 2.0 * Kd * maxb / c->dv + 2.0;
     if (c->kind == 3)
         c->lanes = wmax <= 32.0 ? 16 : (wmax <= 64.0 ? 32 : 64);
+    else if (c->kind == 4)
+        c->lanes = 16;                    // octree march: groups of 16, any window width
     else
         c->lanes = wmax <= 32.0 ? 32 : 64;
     if (const char* ev = std::getenv("MILOC_LANES")) {
         const int l = std::atoi(ev);
-        if (l == 32 || l == 64 || ((l == 16 || l == 8) && c->kind == 3)) c->lanes = l;
+        if (c->kind != 4 && (l == 32 || l == 64 || ((l == 16 || l == 8) && c->kind == 3))) c->lanes = l;
     }
 
     // geometry, weights W (in march length units) and q = dv/(b sqrt(pi) W)
@@ -386,6 +497,10 @@ miloc_status ensure_static(miloc_ctx* c)
         HIPCHK(c, hipMemcpy(c->d_dirs.p, dd.data(), dd.size() * sizeof(DirDev), hipMemcpyHostToDevice));
         st = fp64 ? upload_steps<double>(c, len, fl) : upload_steps<float>(c, len, fl);
         if (st != MILOC_OK) return st;
+    } else if (c->kind == 4) {
+        Lunit = c->delta;
+        st = build_octree_march(c, W);
+        if (st != MILOC_OK) return st;
     } else {
         const int n = (int)c->nc;
         Lunit = c->R[n - 1];
@@ -413,6 +528,12 @@ miloc_status ensure_static(miloc_ctx* c)
     for (int64_t k = 0; k < nc; ++k) {
         const double bs = b[k] * std::sqrt(kPi);
         q[k] = W[k] > 0 ? c->dv / (bs * W[k]) : 0.0;
+        if (c->kind == 4) {
+            // the octree march leaves out the leaf's h_L^2 of the ray weight;
+            // refined cells are not solved
+            const double hl = std::ldexp(1.0, -(int)c->oct.level[k]);
+            q[k] = c->oct.child[k] >= 0 ? -1.0 : q[k] * hl * hl;
+        }
         nmolLb[k] = cv.nH2(k) * cv.X(k) * Lunit / bs;
     }
     c->q_host = q;
@@ -421,7 +542,7 @@ miloc_status ensure_static(miloc_ctx* c)
     HIPCHK(c, hipMemcpy(c->d_q.p, q.data(), nc * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_nmolLb.p, nmolLb.data(), nc * sizeof(double), hipMemcpyHostToDevice));
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
-    if (c->kind == 3) {
+    if (c->kind >= 3) {
         std::vector<float4> vel(nc);
         for (int64_t k = 0; k < nc; ++k) vel[k] = make_float4(c->f_vx[k], c->f_vy[k], c->f_vz[k], 0.0f);
         HIPCHK(c, c->d_vel.ensure(nc * sizeof(float4)));
@@ -712,18 +833,26 @@ miloc_status miloc_load_model_3d(miloc_ctx* c, const miloc_model3d* m)
     if (s) return s;
     if (!m || !m->n_H2 || !m->T_kin || !m->b_turb_cms || !m->vx || !m->vy || !m->vz || !m->abundance)
         return fail(c, MILOC_EINVAL, "NULL model field");
-    if (m->n_oct_levels != 0) return fail(c, MILOC_EINVAL, "octree models are not supported by this version");
+    if (m->n_oct_levels < 0) return fail(c, MILOC_EINVAL, "n_oct_levels must be >= 0");
     const int N = m->n0[0];
-    if (N < 2 || N > 1024 || m->n0[1] != N || m->n0[2] != N)
-        return fail(c, MILOC_EINVAL, "grid must be N^3 with 2 <= N <= 1024");
+    const int Nmin = m->n_oct_levels > 0 ? 1 : 2;
+    if (N < Nmin || N > 1024 || m->n0[1] != N || m->n0[2] != N)
+        return fail(c, MILOC_EINVAL, "grid must be N^3 with 2 <= N <= 1024 (octree roots: 1 <= N)");
     if (!(m->root_cell_cm > 0) || !std::isfinite(m->root_cell_cm)) return fail(c, MILOC_EINVAL, "bad cell size");
-    const int64_t nc = (int64_t)N * N * N;
+    OctModel oct;
+    int64_t nc = (int64_t)N * N * N;
+    if (m->n_oct_levels > 0) {
+        const std::string e = octree_from_levels(N, m->n_oct_levels, m->n_cells_per_level, m->first_child, oct);
+        if (!e.empty()) return fail(c, MILOC_EINVAL, e);
+        nc = oct.level_start.back();
+    }
     if (!nonneg_all(m->n_H2, nc) || !finite_all(m->n_H2, nc) || !positive_all(m->T_kin, nc) ||
         !finite_all(m->T_kin, nc) || !nonneg_all(m->b_turb_cms, nc) || !finite_all(m->b_turb_cms, nc) ||
         !finite_all(m->vx, nc) || !finite_all(m->vy, nc) || !finite_all(m->vz, nc) ||
         !nonneg_all(m->abundance, nc) || !finite_all(m->abundance, nc))
         return fail(c, MILOC_EINVAL, "negative or non-finite cell values");
-    c->kind = 3;
+    c->kind = m->n_oct_levels > 0 ? 4 : 3;
+    c->oct = std::move(oct);
     c->nc = nc;
     c->N = N;
     c->delta = m->root_cell_cm;
@@ -736,6 +865,39 @@ miloc_status miloc_load_model_3d(miloc_ctx* c, const miloc_model3d* m)
     c->f_X.assign(m->abundance, m->abundance + nc);
     c->R.clear(); c->nH2.clear(); c->Tk.clear(); c->bt.clear(); c->vr.clear(); c->X.clear();
     invalidate_model(c);
+    return MILOC_OK;
+}
+
+miloc_status miloc_octree_schedule(const miloc_model3d* m, int n_dir, const double* dirs, int plain,
+                                   int64_t* n_steps, int64_t* n_trees, int* max_depth, uint32_t* steps_out,
+                                   int64_t* trees_out)
+{
+    if (!m || m->n_oct_levels < 1 || !dirs || n_dir < 1 || n_dir > 1024) return MILOC_EINVAL;
+    const int N = m->n0[0];
+    if (N < 1 || N > 1024 || m->n0[1] != N || m->n0[2] != N) return MILOC_EINVAL;
+    OctModel oct;
+    if (!octree_from_levels(N, m->n_oct_levels, m->n_cells_per_level, m->first_child, oct).empty())
+        return MILOC_EINVAL;
+    std::vector<double> d(3 * (size_t)n_dir);
+    for (int q = 0; q < n_dir; ++q) {
+        const double x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
+        const double nrm = std::sqrt(x * x + y * y + z * z);
+        if (!(nrm > 0) || !std::isfinite(nrm)) return MILOC_EINVAL;
+        d[3 * q] = x / nrm; d[3 * q + 1] = y / nrm; d[3 * q + 2] = z / nrm;
+    }
+    OctSchedule S;
+    if (!octree_schedule(oct, d, plain != 0, host_threads(), S).empty()) return MILOC_EINVAL;
+    if (n_steps) *n_steps = S.n_steps;
+    if (n_trees) *n_trees = (int64_t)S.trees.size();
+    if (max_depth) *max_depth = S.max_depth;
+    if (steps_out) std::memcpy(steps_out, S.rec.data(), S.rec.size() * sizeof(uint32_t));
+    if (trees_out)
+        for (size_t i = 0; i < S.trees.size(); ++i) {
+            trees_out[4 * i] = S.trees[i].off;
+            trees_out[4 * i + 1] = S.trees[i].n;
+            trees_out[4 * i + 2] = S.trees[i].q;
+            trees_out[4 * i + 3] = S.trees[i].r;
+        }
     return MILOC_OK;
 }
 
@@ -888,6 +1050,16 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
                 t_gather += b;
                 c->ctr.march_launches += 1;
             }
+        } else if (c->kind == 4) {
+            s = fp64 ? launch_oct<double>(c, c->T, 0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
+                                          c->d_oaw.as<double>(), c->d_win.p, c->oct_groups, c->d_olen64.as<double>())
+                     : launch_oct<float>(c, c->T, 0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
+                                         c->d_oaw.as<double>(), c->d_win.p, c->oct_groups, nullptr);
+            if (s) return s;
+            HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+            HIPCHK(c, hipEventSynchronize(c->ev[4]));
+            HIPCHK(c, hipEventElapsedTime(&t_march, c->ev[1], c->ev[4]));
+            c->ctr.march_launches += 1;
         } else {
             s = fp64 ? launch_march<double>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
                      : launch_march<float>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
@@ -990,8 +1162,9 @@ miloc_status miloc_get_radiation(miloc_ctx* c, double* J_out, double* lambda_out
         for (int64_t k = 0; k < c->nc; ++k) {
             const size_t i = (size_t)t * c->nc + k;       // output: transition-major
             const size_t a = (size_t)k * c->T + t;        // device: cell-major
-            if (J_out) J_out[i] = h[a].x * c->q_host[k] * c->Iscale[t];
-            if (lambda_out) lambda_out[i] = h[a].y * c->q_host[k];
+            const double qk = c->q_host[k] > 0 ? c->q_host[k] : 0.0;
+            if (J_out) J_out[i] = h[a].x * qk * c->Iscale[t];
+            if (lambda_out) lambda_out[i] = h[a].y * qk;
         }
     return MILOC_OK;
 }
@@ -1012,7 +1185,42 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
     // march I - I_bg from zero (see prepare_kernel)
     HIPCHK(c, launch_prepare(c->stream, (int)c->nc, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
                              c->d_nmolLb.as<double>(), c->d_Ibg64.as<double>(), c->d_ke.p, fp64));
-    if (c->kind == 3) {
+    if (c->kind == 4) {
+        if (impact_cm) return fail(c, MILOC_EINVAL, "3D spectra take no impact parameters");
+        if (n_los != c->N * c->N) return fail(c, MILOC_EINVAL, "3D spectra need n_los = N*N");
+        // +z lines of sight on the root ray lattice, traced without new rays
+        const std::vector<double> zd = {0.0, 0.0, 1.0};
+        OctSchedule S;
+        const std::string e = octree_schedule(c->oct, zd, true, host_threads(), S, fp64);
+        if (!e.empty()) return fail(c, MILOC_EINVAL, e);
+        DevBuf steps, trees, zdir, zaw, zwin, zlen;
+        s = upload_oct_schedule(c, S, steps, trees);
+        if (s) return s;
+        if (fp64) {
+            HIPCHK(c, zlen.ensure(std::max<size_t>(1, S.len64.size()) * sizeof(double)));
+            HIPCHK(c, hipMemcpy(zlen.p, S.len64.data(), S.len64.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+        DirDev D{};
+        D.d[2] = 1.0;
+        D.m = 2;
+        D.aw = 1.0;
+        HIPCHK(c, zdir.ensure(sizeof(DirDev)));
+        HIPCHK(c, hipMemcpy(zdir.p, &D, sizeof(DirDev), hipMemcpyHostToDevice));
+        HIPCHK(c, zaw.ensure(sizeof(double)));
+        HIPCHK(c, hipMemcpy(zaw.p, &D.aw, sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, zwin.ensure((size_t)c->nc * 4 * tsz));
+        HIPCHK(c, launch_window_table(c->stream, (int)c->nc, 1, zdir.as<DirDev>(), c->d_vel.as<float4>(),
+                                      c->d_bD.as<double>(), c->dv, c->chalf,
+                                      fp64 ? kWindowK64 : kWindowK32, c->nch, zwin.p, fp64));
+        HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
+        const int groups = (int)std::min<int64_t>(c->oct_groups, ((int64_t)n_los + 15) / 16 * 16);
+        s = fp64 ? launch_oct<double>(c, 1, trans, false, out.as<double>(), steps, trees, (int64_t)S.trees.size(),
+                                      zaw.as<double>(), zwin.p, groups, zlen.as<double>())
+                 : launch_oct<float>(c, 1, trans, false, out.as<float>(), steps, trees, (int64_t)S.trees.size(),
+                                     zaw.as<double>(), zwin.p, groups, nullptr);
+        if (s) return s;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else if (c->kind == 3) {
         if (impact_cm) return fail(c, MILOC_EINVAL, "3D spectra take no impact parameters");
         if (n_los != c->N * c->N) return fail(c, MILOC_EINVAL, "3D spectra need n_los = N*N");
         std::vector<double> zd = {0.0, 0.0, 1.0};

@@ -354,22 +354,26 @@ def octree_structure(N_root: int, n_refine: int, frac: float, score):
     return coords, first_child
 
 
-def _trilinear(grid, px, py, pz):
-    """Periodic trilinear interpolation of a cell-centred (x, y, z) grid at
-    positions in box units [0, 1)."""
-    G = grid.shape[0]
-    out = np.zeros(px.shape, np.float64)
+def _trilinear(grids, px, py, pz):
+    """Periodic trilinear interpolation of cell-centred (x, y, z) grids at
+    positions in box units [0, 1); one output per grid."""
+    G = grids[0].shape[0]
+    outs = [np.zeros(px.shape, np.float64) for _ in grids]
     q = [p * G - 0.5 for p in (px, py, pz)]
     i0 = [np.floor(v).astype(np.int64) for v in q]
     fr = [v - i for v, i in zip(q, i0)]
     for dx in (0, 1):
         wx = fr[0] if dx else 1.0 - fr[0]
+        ix = (i0[0] + dx) % G
         for dy in (0, 1):
-            wy = fr[1] if dy else 1.0 - fr[1]
+            wxy = wx * (fr[1] if dy else 1.0 - fr[1])
+            iy = (i0[1] + dy) % G
             for dz in (0, 1):
-                wz = fr[2] if dz else 1.0 - fr[2]
-                out += wx * wy * wz * grid[(i0[0] + dx) % G, (i0[1] + dy) % G, (i0[2] + dz) % G]
-    return out
+                w = wxy * (fr[2] if dz else 1.0 - fr[2])
+                flat = (ix * G + iy) * G + (i0[2] + dz) % G
+                for g, o in zip(grids, outs):
+                    o += w * g.reshape(-1)[flat]
+    return outs
 
 
 def octree_centres(N_root, coords):
@@ -396,17 +400,17 @@ def octree_cloud(N_root: int = 64, n_refine: int = 4, frac: float = 0.34, grf_N:
 
     def score(lev, cx, cy, cz):
         n_l = N_root << lev
-        return _trilinear(rho, (cx + 0.5) / n_l, (cy + 0.5) / n_l, (cz + 0.5) / n_l)
+        return _trilinear([rho], (cx + 0.5) / n_l, (cy + 0.5) / n_l, (cz + 0.5) / n_l)[0]
 
     coords, fc = octree_structure(N_root, n_refine, frac, score)
     px, py, pz = octree_centres(N_root, coords)
     nc = px.shape[0]
+    n_s, ux, uy, uz = _trilinear([rho, u[0], u[1], u[2]], px, py, pz)
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return Model3D(n0=(N_root,) * 3, root_cell_cm=box_pc * PC_CM / N_root,
-                   n_H2=f32(_trilinear(rho, px, py, pz)), T_kin=f32(np.full(nc, T_kin)),
+                   n_H2=f32(n_s), T_kin=f32(np.full(nc, T_kin)),
                    b_turb=f32(np.full(nc, b_turb_kms * KMS)),
-                   vx=f32(_trilinear(u[0], px, py, pz)), vy=f32(_trilinear(u[1], px, py, pz)),
-                   vz=f32(_trilinear(u[2], px, py, pz)), abundance=f32(np.full(nc, abundance)),
+                   vx=f32(ux), vy=f32(uy), vz=f32(uz), abundance=f32(np.full(nc, abundance)),
                    n_oct_levels=len(fc), n_cells_per_level=[int(c[0].shape[0]) for c in coords],
                    first_child=fc)
 
@@ -453,6 +457,16 @@ def workload_3d_regular(N: int = 128, seed: int = 3001) -> Workload:
     return Workload(f"3d-regular-{N}^3-rotor10", rotor_molecule(10),
                     Spectral.symmetric(256, 4.0), 2.73,
                     turbulent_cube(N=N, seed=seed), 2, extra={"nside": 2})
+
+
+def workload_octree(N_root: int = 64, n_refine: int = 4, seed: int = 4001) -> Workload:
+    """Octree turbulent cloud: 64^3 root grid, 2 pc box, four refinement levels
+    each refining the densest 34% of its cells (about 2e7 leaves), fields
+    from a 256^3 lognormal / solenoidal k^-4 realisation sampled at the cell
+    centres, T = 15 K, 10-level rotor, 256 channels over +-4 km/s."""
+    m = octree_cloud(N_root=N_root, n_refine=n_refine, frac=0.34, grf_N=256, box_pc=2.0, seed=seed)
+    return Workload(f"octree-{N_root}^3-L{n_refine}-rotor10", rotor_molecule(10),
+                    Spectral.symmetric(256, 4.0), 2.73, m, 1, extra={"nside": 2})
 
 
 def array_digest(*arrays) -> str:
