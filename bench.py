@@ -86,6 +86,58 @@ def cpu_baseline(w, budget_s=15.0):
                       f"full {N}^3 cube, all {w.spec.n_channels} channels ({t_total:.1f} s)"}
 
 
+OCT_BYTES_PER_STEP = 48.0     # the regular step's 40 B plus the 8 B step record
+
+
+def octree_bench(steps=2, warmup=1):
+    """Octree leg: 64^3 root, four refinement levels (about 2e7 leaves), 10-level
+    rotor, 48 directions, 256 channels; ALI iterations with the inputs resident
+    and the ray schedules built (outside the timed region)."""
+    import paper_2009_12609_amd as miloc
+    import synth
+
+    t0 = time.perf_counter()
+    w = synth.workload_octree()
+    t_gen = time.perf_counter() - t0
+    ctx = miloc.Context(0)
+    ctx.load_molecule(w.mol)
+    ctx.load_model_3d(w.model)
+    ctx.set_spectral(w.spec.n_channels, w.spec.v_min, w.spec.dv)
+    ctx.set_background(w.T_bg)
+    t0 = time.perf_counter()
+    ctx.init_lte()
+    ctx.run(max(1, warmup))              # builds the ray schedules, then warm-up iterations
+    t_setup = time.perf_counter() - t0
+    ctx.init_lte()
+    ctx.reset_counters()
+    t0 = time.perf_counter()
+    ctx.run(steps)
+    elapsed = time.perf_counter() - t0
+    cnt = ctx.counters()
+    ctx.close()
+    launches = max(1, cnt["march_launches"])
+    march_ms = cnt["march_ms"] / launches
+    steps_per_launch = cnt["ray_steps"] / launches
+    achieved = steps_per_launch * OCT_BYTES_PER_STEP / (march_ms * 1e-3) / 1e9
+    return {
+        "metric": "ray-cell-channel updates/s (3D octree)",
+        "value": cnt["channel_updates"] / elapsed,
+        "unit": "ray-cell-channel updates/s",
+        "steps": steps,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "workload": w.name,
+        "n_cells_per_level": list(map(int, w.model.n_cells_per_level)),
+        "ray_cell_steps_per_iteration": cnt["ray_steps"] / max(1, cnt["iterations"]),
+        "march_ms_per_launch": march_ms,
+        "solve_ms_per_step": cnt["solve_ms"] / max(1, cnt["iterations"]),
+        "setup_s": t_setup,
+        "generate_s": t_gen,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "march_oct_kernel<float,true>", "bytes_per_step": OCT_BYTES_PER_STEP},
+    }
+
+
 def _pct(a, q):
     import numpy as np
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
@@ -185,6 +237,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=0, metavar="N_REQ",
                     help="also run the 1D request stream with N_REQ requests (adds a 'serving' object)")
+    ap.add_argument("--octree", type=int, default=0, metavar="STEPS",
+                    help="also time STEPS iterations of the octree workload (adds an 'octree' object)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -275,6 +329,8 @@ def main():
         },
     }
     ctx.close()
+    if args.octree > 0:
+        out["octree"] = octree_bench(args.octree)
     if args.serve > 0:
         out["serving"] = serve_bench(args.serve)
     if not args.no_cpu_baseline and N == 128:

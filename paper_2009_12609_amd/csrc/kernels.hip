@@ -342,14 +342,29 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
     const int q_ray = wl % rpw, q_step = wl / rpw;
     int qn = 0, qs0 = 0;
 
+    // The cell of step s + 1 follows from the step list alone, so its window
+    // and {khat, ehat} loads are issued before step s is computed.
+    StepRec<T> rec_n = sst[0];
+    bool restart_n = false;
+    if (rec_n.flags & 1) idx += D.stride_m;
+    if (rec_n.flags & 2) move_transverse(ca, idx, D.sa, D.sta, N, restart_n);
+    if (rec_n.flags & 4) move_transverse(cb, idx, D.sb, D.stb, N, restart_n);
+    T4 wv_n = win[idx];
+    T2 kv_n = ke[(size_t)idx * ts];
     for (int s = 0; s < ns; ++s) {
-        const StepRec<T> rec = sst[s];
-        bool restart = false;
-        if (rec.flags & 1) idx += D.stride_m;
-        if (rec.flags & 2) move_transverse(ca, idx, D.sa, D.sta, N, restart);
-        if (rec.flags & 4) move_transverse(cb, idx, D.sb, D.stb, N, restart);
-        const T4 wv = win[idx];
-        const T2 kv = ke[(size_t)idx * ts];
+        const StepRec<T> rec = rec_n;
+        const bool restart = restart_n;
+        const T4 wv = wv_n;
+        const T2 kv = kv_n;
+        if (s + 1 < ns) {
+            rec_n = sst[s + 1];
+            restart_n = false;
+            if (rec_n.flags & 1) idx += D.stride_m;
+            if (rec_n.flags & 2) move_transverse(ca, idx, D.sa, D.sta, N, restart_n);
+            if (rec_n.flags & 4) move_transverse(cb, idx, D.sb, D.stb, N, restart_n);
+            wv_n = win[idx];
+            kv_n = ke[(size_t)idx * ts];
+        }
         if (restart) {
             // Side exit: the ray re-enters on the opposite face carrying the
             // background again (Sect. 2.2).
@@ -483,18 +498,33 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         const T Ibg = p.Ibg[t];
         const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
         int sp = -1;
-        uint2 mine = make_uint2(0u, 0u);
-        double mine64 = 0.0;
+        // records arrive 16 at a time, one per lane, and are broadcast with
+        // shuffles; the next step's cell data are loaded before this step runs
+        uint2 mine = rec[lane < tr.n ? lane : 0];
+        double mine64 = (sizeof(T) == 8 && rec64) ? rec64[lane < tr.n ? lane : 0] : 0.0;
+        unsigned w0_n = __shfl(mine.x, 0, LANES);
+        T len_n = (T)__uint_as_float(__shfl(mine.y, 0, LANES));
+        if (sizeof(T) == 8 && rec64) len_n = (T)__shfl(mine64, 0, LANES);
+        T4 wv_n = win[w0_n & kOctCellMask];
+        T2 kv_n = ke[(size_t)(w0_n & kOctCellMask) * p.ntr_total];
         for (int s = 0; s < tr.n; ++s) {
-            const int k = s & (LANES - 1);
-            if (k == 0) {
-                const int si = s + lane;
-                mine = si < tr.n ? rec[si] : make_uint2(0u, 0u);
-                if (sizeof(T) == 8 && rec64) mine64 = si < tr.n ? rec64[si] : 0.0;
+            const unsigned w0 = w0_n;
+            const T len = len_n;
+            const T4 wv = wv_n;
+            const T2 kv = kv_n;
+            if (s + 1 < tr.n) {
+                const int k = (s + 1) & (LANES - 1);
+                if (k == 0) {
+                    const int si = s + 1 + lane < tr.n ? s + 1 + lane : s + 1;
+                    mine = rec[si];
+                    if (sizeof(T) == 8 && rec64) mine64 = rec64[si];
+                }
+                w0_n = __shfl(mine.x, k, LANES);
+                len_n = (T)__uint_as_float(__shfl(mine.y, k, LANES));
+                if (sizeof(T) == 8 && rec64) len_n = (T)__shfl(mine64, k, LANES);
+                wv_n = win[w0_n & kOctCellMask];
+                kv_n = ke[(size_t)(w0_n & kOctCellMask) * p.ntr_total];
             }
-            const unsigned w0 = __shfl(mine.x, k, LANES);
-            T len = (T)__uint_as_float(__shfl(mine.y, k, LANES));
-            if (sizeof(T) == 8 && rec64) len = (T)__shfl(mine64, k, LANES);
             const int cell = (int)(w0 & kOctCellMask);
             const unsigned mode = w0 >> kOctModeShift;
             if (mode == kOctModeBg) {
@@ -510,8 +540,6 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
                 for (int c = lane; c < p.nch; c += LANES) dst[c] = I[c];
             }
             __builtin_amdgcn_wave_barrier();
-            const T4 wv = win[cell];
-            const T2 kv = ke[(size_t)cell * p.ntr_total];
             const int clo = as_int(wv.z);
             const int nwin = as_int(wv.w);
             const T kl = kv.x * len;
