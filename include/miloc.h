@@ -280,7 +280,7 @@ miloc_status miloc_reset_counters(miloc_ctx* ctx);
  * completion the server computes the spectra of every transition towards the
  * model centre (impact parameter 0).  All server calls are thread-safe.
  * Limits per request: 2..20 levels, at most 19 transitions x 8192 rays,
- * 1..2048 shells, 8..1024 channels. */
+ * 1..2048 shells, 8..512 channels. */
 typedef struct miloc_server miloc_server;
 
 typedef struct {

@@ -9,7 +9,7 @@
 //     rays sit at the same fractional transverse offset and cross cell faces
 //     in the same order.  One representative ray, traced analytically in FP64,
 //     gives the step list every ray of the direction follows (translated).
-//   * 1D impact-parameter chords through shells (Sect. 2.1) for the weights W.
+//   * the step layout of 1D impact-parameter rays through shells (Sect. 2.1).
 #include "geometry.h"
 
 #include <algorithm>
@@ -115,22 +115,19 @@ DirPattern regular_pattern(const double* d, int N)
     return P;
 }
 
-void shell_weights(int n, const double* R, int nrays, const double* b, const double* area,
-                   double* W, int64_t* nsteps_total)
+int64_t shell_ray_layout(int n, const double* R, int nrays, const double* b, std::vector<int64_t>& off,
+                         std::vector<int>& kmin)
 {
-    std::fill(W, W + n, 0.0);
-    int64_t steps = 0;
+    off.resize(nrays);
+    kmin.resize(nrays);
+    int64_t total = 0;
     for (int j = 0; j < nrays; ++j) {
-        int kmin = 0;
-        while (kmin < n && !(R[kmin] > b[j])) ++kmin;
-        if (kmin >= n) continue;
-        auto z = [&](int k) { return std::sqrt((R[k] - b[j]) * (R[k] + b[j])); };
-        // every shell outside kmin is crossed twice (in and out), kmin once
-        for (int k = kmin + 1; k < n; ++k) W[k] += area[j] * 2.0 * (z(k) - z(k - 1));
-        W[kmin] += area[j] * 2.0 * z(kmin);
-        steps += 2 * (n - 1 - kmin) + 2;
+        const int km = std::min<int>(n - 1, (int)(std::upper_bound(R, R + n, b[j]) - R));
+        kmin[j] = km;
+        off[j] = total;
+        total += 2 * (int64_t)(n - 1 - km) + 2;
     }
-    if (nsteps_total) *nsteps_total = steps;
+    return total;
 }
 
 }  // namespace miloc

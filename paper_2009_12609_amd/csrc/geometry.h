@@ -25,8 +25,9 @@ struct DirPattern {
 };
 DirPattern regular_pattern(const double* d, int N);
 
-// 1D ray-sampled volumes W_k = sum_j area_j * (path of ray j in shell k).
-void shell_weights(int n, const double* R, int nrays, const double* b, const double* area,
-                   double* W, int64_t* nsteps_total);
+// Innermost shell (first k with R[k] > b, R[n-1] = 1) and first step record
+// of each 1D ray; each ray has 2 (n - 1 - kmin) + 2 steps.  Returns the total.
+int64_t shell_ray_layout(int n, const double* R, int nrays, const double* b, std::vector<int64_t>& off,
+                         std::vector<int>& kmin);
 
 }  // namespace miloc

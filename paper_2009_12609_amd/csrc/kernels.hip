@@ -581,27 +581,20 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
 // ---------------------------------------------------------------- 1D march
 namespace {
 
-__device__ __forceinline__ int kmin_of(const double* __restrict__ R, int n, double b)
-{
-    // innermost shell reached by a ray of impact parameter b: first k with R[k] > b
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (R[mid] > b) hi = mid; else lo = mid + 1;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
 
 }  // namespace
 
 // One workgroup marches rays ray0 .. ray0 + rays_per_block - 1 of one
-// transition through a 1D shell model.  Geometry in FP64 on the fly.  With
-// p.lds_acc the per-step sums go to per-shell LDS accumulators (LDS atomics
-// do not stall the next step's loads) and are flushed to the FP64 global sums
-// once per workgroup; otherwise each step issues two FP64 atomics.
+// transition through a 1D shell model.  Each ray's steps {length, Doppler
+// shift in channels} were computed once on the host in FP64 (Sect. 2.1: the
+// paths are fixed, so they are precomputed); the shell of step s follows from
+// s and the ray's innermost shell.  Records arrive 16 at a time, one per
+// lane, and the next step's shell data are loaded before the current step
+// runs.  With p.lds_acc the per-step sums go to per-shell LDS accumulators
+// (LDS atomics do not stall the next step's loads), flushed to the FP64
+// global sums once per workgroup; otherwise each step issues two FP64 atomics.
 template <typename T, int LANES, bool ACCUM>
 __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0, int t, unsigned char* smem_raw)
 {
@@ -613,9 +606,8 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
     const bool lds_acc = ACCUM && p.lds_acc;
     T* __restrict__ sacc = reinterpret_cast<T*>(smem_raw);                 // [n][2] when lds_acc
     T* __restrict__ I = reinterpret_cast<T*>(smem_raw + (lds_acc ? p.acc_lds_bytes : 0)) + (size_t)rib * p.nch;
-    const double* __restrict__ R = p.R;
     const int ts = p.ntr_total;      // cell-major [shell][transition]
-    const int kmin0 = kmin_of(R, n, p.bimp[ray0]);   // block's rays are sorted by impact parameter
+    const int kmin0 = p.kmin[ray0];  // the block's rays are sorted by impact parameter
     if (lds_acc) {
         for (int k = kmin0 + (int)threadIdx.x; k < n; k += blockDim.x) {
             sacc[2 * k] = (T)0;
@@ -624,53 +616,48 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
         __syncthreads();
     }
     if (j < p.nrays) {
-        const double b = p.bimp[j];
         const double a = p.area[j];
-        const int kmin = kmin_of(R, n, b);
+        const int kmin = p.kmin[j];
         const int nin = n - 1 - kmin;
         const int nsteps = 2 * nin + 2;
+        const T2* __restrict__ rec = p.steps + p.ray_off[j];
         const T Ibg = p.Ibg[t];
         for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
-
-        double zprev = sqrt((R[n - 1] - b) * (R[n - 1] + b));
+        auto shell_of = [&](int s) {
+            return s < nin ? n - 1 - s : (s <= nin + 1 ? kmin : kmin + (s - nin - 1));
+        };
+        T2 mine = rec[lane < nsteps ? lane : 0];
+        T2 r_n;
+        r_n.x = __shfl(mine.x, 0, LANES);
+        r_n.y = __shfl(mine.y, 0, LANES);
+        int k_n = shell_of(0);
+        T2 sv_n = p.shellv[k_n];
+        T2 kev_n = p.ke[(size_t)k_n * ts + t];
         for (int s = 0; s < nsteps; ++s) {
-            int k;
-            double len, mu;
-            if (s < nin) {                       // inwards through shell k
-                k = n - 1 - s;
-                const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
-                len = zprev - zi;
-                mu = -zprev / R[k];
-                zprev = zi;
-            } else if (s == nin) {               // tangent shell, first half
-                k = kmin;
-                len = zprev;
-                mu = -zprev / R[k];
-            } else if (s == nin + 1) {           // tangent shell, second half
-                k = kmin;
-                len = zprev;
-                mu = 0.0;
-            } else {                             // outwards through shell k
-                k = kmin + (s - nin - 1);
-                const double zi = sqrt((R[k - 1] - b) * (R[k - 1] + b));
-                const double zo = sqrt((R[k] - b) * (R[k] + b));
-                len = zo - zi;
-                mu = zi / R[k - 1];
+            const T2 r = r_n;
+            const int k = k_n;
+            const T2 sv = sv_n;
+            const T2 kev = kev_n;
+            if (s + 1 < nsteps) {
+                const int q = (s + 1) & (LANES - 1);
+                if (q == 0) mine = rec[s + 1 + lane < nsteps ? s + 1 + lane : s + 1];
+                r_n.x = __shfl(mine.x, q, LANES);
+                r_n.y = __shfl(mine.y, q, LANES);
+                k_n = shell_of(s + 1);
+                sv_n = p.shellv[k_n];
+                kev_n = p.ke[(size_t)k_n * ts + t];
             }
-            const T2 sv = p.shellv[k];
-            const T2 kev = p.ke[(size_t)k * ts + t];
-            const double w = (double)sv.x * mu;
             int clo, chi;
             T frac;
-            window<T>(w, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
-            const T tl = (T)len;
+            window<T>((double)r.y, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
+            const T tl = r.x;
             T sj = 0, sl = 0;
             step_channels<LANES, T>(I, lane, clo, chi, frac, sv.y, kev.x * tl, kev.y * tl, sj, sl);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
                 if (lane == LANES - 1) {
-                    const double wgt = a * len;
+                    const double wgt = a * (double)tl;
                     if (lds_acc) {
                         lds_add(&sacc[2 * k], (T)wgt * sj);
                         lds_add(&sacc[2 * k + 1], (T)wgt * sl);
@@ -680,6 +667,7 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
         if (!ACCUM && p.Iout) {
             T* out = p.Iout + ((size_t)(t - p.trans_offset) * p.nrays + j) * p.nch;
@@ -696,6 +684,76 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
             }
         }
     }
+}
+
+// Steps of 1D rays (Sect. 2.1), one workgroup per ray: ray j of impact
+// parameter b_j enters at the outer radius (R[n-1] = 1), goes inwards to its
+// innermost shell kmin_j, whose chord is split at the tangent point into two
+// halves, and back out.  Record s: {path length, Doppler shift in channels
+// v_r mu / dv}, mu = cosine between the direction and the outward radius at
+// the start of the step.  FP64 geometry, rounded once to T.
+template <typename T>
+__global__ __launch_bounds__(256) void ray_steps_kernel(int n, const double* __restrict__ R,
+                                                        const double* __restrict__ b,
+                                                        const int* __restrict__ kmin,
+                                                        const long long* __restrict__ off,
+                                                        const double* __restrict__ vr_dv,
+                                                        typename V2<T>::type* __restrict__ out)
+{
+    const int j = blockIdx.x;
+    const double bj = b[j];
+    const int km = kmin[j];
+    const int nin = n - 1 - km;
+    const int ns = 2 * nin + 2;
+    typename V2<T>::type* __restrict__ o = out + off[j];
+    auto z = [&](int k) { return sqrt(fmax(0.0, (R[k] - bj) * (R[k] + bj))); };
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        int k;
+        double len, mu;
+        if (s < nin) {
+            k = n - 1 - s;
+            const double zo = z(k);
+            len = zo - z(k - 1);
+            mu = -zo / R[k];
+        } else if (s == nin) {
+            k = km;
+            len = z(k);
+            mu = -len / R[k];
+        } else if (s == nin + 1) {
+            k = km;
+            len = z(k);
+            mu = 0.0;
+        } else {
+            k = km + (s - nin - 1);
+            const double zi = z(k - 1);
+            len = z(k) - zi;
+            mu = zi / R[k - 1];
+        }
+        o[s].x = (T)len;
+        o[s].y = (T)(vr_dv[k] * mu);
+    }
+}
+
+// Ray-sampled shell volumes W_k = sum_j a_j (path of ray j in shell k), one
+// thread per shell: a ray with b_j < R_{k-1} crosses shell k twice, one with
+// R_{k-1} <= b_j < R_k has it as its tangent shell (full chord).
+__global__ __launch_bounds__(256) void shell_weights_kernel(int n, const double* __restrict__ R, int nrays,
+                                                            const double* __restrict__ b,
+                                                            const double* __restrict__ area,
+                                                            double* __restrict__ W)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double ro = R[k], ri = k > 0 ? R[k - 1] : 0.0;
+    double w = 0.0;
+    for (int j = 0; j < nrays; ++j) {
+        const double bj = b[j];
+        if (!(ro > bj)) continue;
+        const double zo = sqrt((ro - bj) * (ro + bj));
+        const double zi = ri > bj ? sqrt((ri - bj) * (ri + bj)) : 0.0;
+        w += area[j] * 2.0 * (zo - zi);
+    }
+    W[k] = w;
 }
 
 template <typename T, int LANES, bool ACCUM>
@@ -870,7 +928,7 @@ __global__ __launch_bounds__(256) void serve_march_kernel(const ServeModel* __re
     for (int w = blockIdx.x; w < n; w += gridDim.x) {
         const int4 it = items[w];                  // model, transition, first ray
         const March1DArgs<float> a = models[it.x].m;
-        march1d_block<float, 64, true>(a, it.z, it.y, smem_raw);
+        march1d_block<float, 16, true>(a, it.z, it.y, smem_raw);
         __syncthreads();
     }
 }
@@ -1016,6 +1074,7 @@ hipError_t dispatch3d(hipStream_t s, const March3DArgs<T>& a, int lanes, bool ac
 template <typename T>
 hipError_t dispatch1d(hipStream_t s, const March1DArgs<T>& a, int lanes, bool accum)
 {
+    if (lanes == 16) return accum ? do_march1d<T, 16, true>(s, a) : do_march1d<T, 16, false>(s, a);
     if (lanes == 32) return accum ? do_march1d<T, 32, true>(s, a) : do_march1d<T, 32, false>(s, a);
     return accum ? do_march1d<T, 64, true>(s, a) : do_march1d<T, 64, false>(s, a);
 }
@@ -1030,6 +1089,25 @@ hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes
                           int max_steps)
 {
     return dispatch3d<double>(s, a, lanes, accum, max_steps);
+}
+hipError_t launch_shell_weights(hipStream_t s, int n, const double* R, int nrays, const double* b,
+                                const double* area, double* W)
+{
+    hipLaunchKernelGGL(shell_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, R, nrays, b, area, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_steps(hipStream_t s, int n, const double* R, int nrays, const double* b, const int* kmin,
+                            const long long* off, const double* vr_dv, void* out, bool fp64)
+{
+    if (nrays <= 0) return hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL(ray_steps_kernel<double>, dim3(nrays), dim3(256), 0, s, n, R, b, kmin, off, vr_dv,
+                           reinterpret_cast<double2*>(out));
+    else
+        hipLaunchKernelGGL(ray_steps_kernel<float>, dim3(nrays), dim3(256), 0, s, n, R, b, kmin, off, vr_dv,
+                           reinterpret_cast<float2*>(out));
+    return hipGetLastError();
 }
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum)
 {

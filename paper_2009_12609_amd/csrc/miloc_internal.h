@@ -99,8 +99,9 @@ struct Gather3DArgs {
 template <typename T>
 struct March1DArgs {
     int n, nrays, nch, ntr;
-    const double* R;                     // outer radii / R_out
-    const double* bimp;                  // impact parameters / R_out
+    const typename V2<T>::type* steps;   // per ray: 2 (n - 1 - kmin) + 2 steps {len / R_out, Doppler shift / dv}
+    const long long* ray_off;            // first step of each ray
+    const int* kmin;                     // innermost shell of each ray
     const double* area;                  // ray weights / R_out^2
     const typename V2<T>::type* shellv;  // {Ur, ibs} per shell
     const typename V2<T>::type* ke;      // [n][ntr_total]
@@ -215,6 +216,13 @@ hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes,
                           int max_steps);
 hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum,
                           int max_steps);
+// W_k = sum_j area_j * (path of ray j in shell k), normalised units.
+hipError_t launch_shell_weights(hipStream_t s, int n, const double* R, int nrays, const double* b,
+                                const double* area, double* W);
+// Step records of 1D rays (see ray_steps_kernel); R, b normalised to R_out,
+// off[j] = first record of ray j, kmin[j] its innermost shell.
+hipError_t launch_ray_steps(hipStream_t s, int n, const double* R, int nrays, const double* b, const int* kmin,
+                            const long long* off, const double* vr_dv, void* out, bool fp64);
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum);
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes, bool accum);
 hipError_t launch_se(hipStream_t s, const SEArgs& a);

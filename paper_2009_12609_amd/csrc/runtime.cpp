@@ -105,14 +105,15 @@ struct miloc_ctx {
     bool has_pops = false;
     bool has_rad = false;
     DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
-        d_zero, d_dirs, d_steps, d_flags, d_R, d_bimp, d_area, d_vel, d_bD, d_win, d_lstart, d_moves,
-        d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter;
+        d_zero, d_dirs, d_steps, d_flags, d_R, d_vrdv, d_area, d_vel, d_bD, d_win, d_lstart, d_moves,
+        d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter, d_1steps, d_1off, d_1kmin;
     int64_t oct_trees = 0;
     int oct_depth = 0, oct_groups = 0;
     int64_t total_steps = 0;
     int trans_chunk = 1;
     int qcount[3] = {0, 0, 0}, qoff[3] = {0, 0, 0};
     std::vector<double> Iscale, Ibg;   // per transition: 2 h nu^3 / c^2, background (occupation)
+    std::vector<double> Rn;            // 1D: outer radii / R_out
     std::vector<double> q_host;
     int lanes = 32;
     double steps_per_trans = 0;
@@ -249,6 +250,30 @@ miloc_status upload_steps(miloc_ctx* c, const std::vector<double>& len, const st
     HIPCHK(c, c->d_steps.ensure(std::max<size_t>(1, st.size()) * sizeof(StepRec<TT>)));
     HIPCHK(c, hipMemcpy(c->d_steps.p, st.data(), st.size() * sizeof(StepRec<TT>),
                         hipMemcpyHostToDevice));
+    return MILOC_OK;
+}
+
+// 1D: step records {len / R_out, Doppler shift in channels} of rays with the
+// given impact parameters (/ R_out), built on the device; first step and
+// innermost shell of each ray.
+miloc_status upload_ray_steps(miloc_ctx* c, const std::vector<double>& bn, bool fp64, DevBuf& steps, DevBuf& off,
+                              DevBuf& kmin)
+{
+    const int n = (int)c->nc;
+    std::vector<int64_t> o;
+    std::vector<int> km;
+    const int64_t total = shell_ray_layout(n, c->Rn.data(), (int)bn.size(), bn.data(), o, km);
+    DevBuf db;
+    HIPCHK(c, db.ensure(std::max<size_t>(1, bn.size()) * sizeof(double)));
+    HIPCHK(c, hipMemcpy(db.p, bn.data(), bn.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, off.ensure(std::max<size_t>(1, o.size()) * sizeof(int64_t)));
+    HIPCHK(c, hipMemcpy(off.p, o.data(), o.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(c, kmin.ensure(std::max<size_t>(1, km.size()) * sizeof(int)));
+    HIPCHK(c, hipMemcpy(kmin.p, km.data(), km.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, steps.ensure(std::max<int64_t>(1, total) * (fp64 ? sizeof(double2) : sizeof(float2))));
+    HIPCHK(c, launch_ray_steps(c->stream, n, c->d_R.as<double>(), (int)bn.size(), db.as<double>(), kmin.as<int>(),
+                               off.as<long long>(), c->d_vrdv.as<double>(), steps.p, fp64));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return MILOC_OK;
 }
 
@@ -440,13 +465,13 @@ miloc_status ensure_static(miloc_ctx* c)
     const double wmax = 2.0 * Kd * maxb / c->dv + 2.0;
     if (c->kind == 3)
         c->lanes = wmax <= 32.0 ? 16 : (wmax <= 64.0 ? 32 : 64);
-    else if (c->kind == 4)
-        c->lanes = 16;                    // octree march: groups of 16, any window width
     else
-        c->lanes = wmax <= 32.0 ? 32 : 64;
+        c->lanes = 16;                    // octree and 1D marches: groups of 16, any window width
     if (const char* ev = std::getenv("MILOC_LANES")) {
         const int l = std::atoi(ev);
-        if (c->kind != 4 && (l == 32 || l == 64 || ((l == 16 || l == 8) && c->kind == 3))) c->lanes = l;
+        if ((c->kind == 1 && (l == 16 || l == 32 || l == 64)) ||
+            (c->kind == 3 && (l == 8 || l == 16 || l == 32 || l == 64)))
+            c->lanes = l;
     }
 
     // geometry, weights W (in march length units) and q = dv/(b sqrt(pi) W)
@@ -507,6 +532,7 @@ miloc_status ensure_static(miloc_ctx* c)
         std::vector<double> Rn(n), bn(c->nrays), an(c->nrays);
         for (int k = 0; k < n; ++k) Rn[k] = c->R[k] / Lunit;
         Rn[n - 1] = 1.0;
+        c->Rn = Rn;
         for (int j = 0; j < c->nrays; ++j) bn[j] = c->impact[j] / Lunit;
         // ray weights: annulus between the mid-points of neighbouring impact parameters
         for (int j = 0; j < c->nrays; ++j) {
@@ -514,15 +540,30 @@ miloc_status ensure_static(miloc_ctx* c)
             const double e1 = j == c->nrays - 1 ? 1.0 : 0.5 * (bn[j] + bn[j + 1]);
             an[j] = kPi * (e1 * e1 - e0 * e0);
         }
-        int64_t steps = 0;
-        shell_weights(n, Rn.data(), c->nrays, bn.data(), an.data(), W.data(), &steps);
-        c->steps_per_trans = (double)steps;
-        HIPCHK(c, c->d_R.ensure(n * sizeof(double)));
-        HIPCHK(c, c->d_bimp.ensure(c->nrays * sizeof(double)));
         HIPCHK(c, c->d_area.ensure(c->nrays * sizeof(double)));
-        HIPCHK(c, hipMemcpy(c->d_R.p, Rn.data(), n * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(c->d_bimp.p, bn.data(), c->nrays * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(c, hipMemcpy(c->d_area.p, an.data(), c->nrays * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<double> vrdv(n);
+        for (int k = 0; k < n; ++k) vrdv[k] = c->vr[k] / c->dv;
+        HIPCHK(c, c->d_R.ensure(n * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->d_R.p, Rn.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, c->d_vrdv.ensure(n * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->d_vrdv.p, vrdv.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        st = upload_ray_steps(c, bn, fp64, c->d_1steps, c->d_1off, c->d_1kmin);
+        if (st != MILOC_OK) return st;
+        // ray-sampled volumes on the device (the rays' paths, FP64)
+        {
+            DevBuf db, dW;
+            HIPCHK(c, db.ensure(c->nrays * sizeof(double)));
+            HIPCHK(c, hipMemcpy(db.p, bn.data(), c->nrays * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(c, dW.ensure(n * sizeof(double)));
+            HIPCHK(c, launch_shell_weights(c->stream, n, c->d_R.as<double>(), c->nrays, db.as<double>(),
+                                           c->d_area.as<double>(), dW.as<double>()));
+            HIPCHK(c, hipMemcpyAsync(W.data(), dW.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+        std::vector<int64_t> o;
+        std::vector<int> km;
+        c->steps_per_trans = (double)shell_ray_layout(n, Rn.data(), c->nrays, bn.data(), o, km);
     }
     std::vector<double> q(nc), nmolLb(nc);
     for (int64_t k = 0; k < nc; ++k) {
@@ -602,7 +643,8 @@ template <typename TT>
 miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, bool zdir,
                           const DirDev* d_dirs_override, const void* steps_override, int nd_override,
                           const double* bimp_override, int nrays_override,
-                          const void* win_override = nullptr)
+                          const void* win_override = nullptr, const DevBuf* ray_steps = nullptr,
+                          const DevBuf* ray_off = nullptr, const DevBuf* ray_kmin = nullptr)
 {
     hipError_t e;
     if (c->kind == 3) {
@@ -638,8 +680,10 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.nch = c->nch;
         a.ntr = ntr;
         a.trans_offset = toff;
-        a.R = c->d_R.as<double>();
-        a.bimp = bimp_override ? bimp_override : c->d_bimp.as<double>();
+        a.steps = ray_steps ? reinterpret_cast<const typename V2<TT>::type*>(ray_steps->p)
+                            : c->d_1steps.as<typename V2<TT>::type>();
+        a.ray_off = ray_steps ? ray_off->as<long long>() : c->d_1off.as<long long>();
+        a.kmin = ray_steps ? ray_kmin->as<int>() : c->d_1kmin.as<int>();
         a.area = bimp_override ? bimp_override : c->d_area.as<double>();
         a.shellv = c->d_cellv.as<typename V2<TT>::type>();
         a.ke = c->d_ke.as<typename V2<TT>::type>();
@@ -1270,8 +1314,12 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
         HIPCHK(c, extra.ensure(bn.size() * sizeof(double)));
         HIPCHK(c, hipMemcpy(extra.p, bn.data(), bn.size() * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
-        s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los)
-                 : launch_march<float>(c, 1, trans, false, out.as<float>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los);
+        DevBuf rs, ro, rk;
+        s = upload_ray_steps(c, bn, fp64, rs, ro, rk);
+        if (s) return s;
+        s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los, nullptr, &rs, &ro, &rk)
+                 : launch_march<float>(c, 1, trans, false, out.as<float>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los, nullptr, &rs, &ro, &rk);
+        if (s) return s;
         if (s) return s;
     }
     const size_t n = (size_t)n_los * c->nch;

@@ -44,9 +44,9 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrtLog2e = 1.2011224087864498;
 constexpr double kWindowK = 5.0;           // FP32 march: profile < e^-25 outside
 constexpr int kMaxServeShells = 2048;      // per-shell LDS accumulators
-constexpr int kMaxServeChannels = 1024;
+constexpr int kMaxServeChannels = 512;
 constexpr int kMaxServeLevels = 20;
-constexpr int kRaysPerBlock = 4;           // 64 lanes per ray, 256 threads
+constexpr int kRaysPerBlock = 16;          // 16 lanes per ray, 256 threads
 constexpr int kSeBs = 16;
 
 double now_s()
@@ -109,6 +109,7 @@ struct Request {
     double mass = 0;
     // model
     int n = 0, nrays = 0;
+    int64_t n_steps = 0;      // ray steps of the model's rays plus the centre line of sight
     std::vector<double> R, nH2, Tk, bt, vr, X, impact;
     int nch = 0;
     double vmin = 0, dv = 0, Tbg = 0, tol = 0;
@@ -125,13 +126,16 @@ struct Request {
     size_t off = 0, bytes = 0;
     int slot = -1;
     ServeModel desc{};
+    double* d_ibg64 = nullptr;  // arena copies: background (FP64) and the spectra output
+    float* d_spec = nullptr;
     std::vector<double> Iscale, Ibg;
     // results
     std::vector<double> x, spectra;
 };
 
 struct Layout {
-    size_t mol, R, bimp, area, shellv, ke, acc, x, xn, nH2, Tk, q, nmolLb, Ibg, total;
+    size_t mol, steps, roff, kmin, R, b, vrdv, area, shellv, ke, acc, x, xn, nH2, Tk, q, nmolLb, Ibg, Ibg64, spec,
+        total;
 };
 
 Layout layout_of(const Request& r)
@@ -140,8 +144,12 @@ Layout layout_of(const Request& r)
     size_t o = 0;
     auto take = [&](size_t n) { const size_t at = o; o += (n + 255) & ~(size_t)255; return at; };
     l.mol = take(sizeof(MolDev));
+    l.steps = take((size_t)r.n_steps * sizeof(float2));
+    l.roff = take((size_t)(r.nrays + 1) * sizeof(int64_t));
+    l.kmin = take((size_t)(r.nrays + 1) * sizeof(int));
     l.R = take(r.n * sizeof(double));
-    l.bimp = take(r.nrays * sizeof(double));
+    l.b = take((size_t)(r.nrays + 1) * sizeof(double));
+    l.vrdv = take(r.n * sizeof(double));
     l.area = take(r.nrays * sizeof(double));
     l.shellv = take(r.n * sizeof(float2));
     l.ke = take((size_t)r.n * r.T * sizeof(float2));
@@ -153,6 +161,8 @@ Layout layout_of(const Request& r)
     l.q = take(r.n * sizeof(double));
     l.nmolLb = take(r.n * sizeof(double));
     l.Ibg = take(r.T * sizeof(float));
+    l.Ibg64 = take(r.T * sizeof(double));
+    l.spec = take((size_t)r.T * r.nch * sizeof(float));
     l.total = o;
     return l;
 }
@@ -189,7 +199,6 @@ struct miloc_server {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     float* d_zero = nullptr;
-    double* d_impact0 = nullptr;
 
     std::mutex mu;
     std::mutex err_mu;                   // guards err (set from caller and worker threads)
@@ -250,13 +259,24 @@ bool admit_upload(miloc_server* S, Request* r)
         const double e1 = j == r->nrays - 1 ? 1.0 : 0.5 * (bn[j] + bn[j + 1]);
         an[j] = kPi * (e1 * e1 - e0 * e0);
     }
-    int64_t steps = 0;
-    shell_weights(n, Rn.data(), r->nrays, bn.data(), an.data(), W.data(), &steps);
+    // ray layout of the model's rays and of the centre line of sight (spectra);
+    // the step records themselves are computed on the device below
+    std::vector<double> b_all(bn);
+    b_all.push_back(0.0);
+    std::vector<int64_t> roff;
+    std::vector<int> kmin;
+    if (shell_ray_layout(n, Rn.data(), (int)b_all.size(), b_all.data(), roff, kmin) != r->n_steps) {
+        r->error = "ray step count mismatch";
+        return false;
+    }
+    std::vector<double> vrdv(n);
+    for (int k = 0; k < n; ++k) vrdv[k] = r->vr[k] / r->dv;
     std::vector<float2> sv(n);
+    std::vector<double> bsq(n);
     for (int k = 0; k < n; ++k) {
         const double b = std::sqrt(2.0 * kK * r->Tk[k] / (r->mass * kAmu) + r->bt[k] * r->bt[k]);
         const double bs = b * std::sqrt(kPi);
-        q[k] = W[k] > 0 ? r->dv / (bs * W[k]) : 0.0;
+        bsq[k] = bs;
         nmolLb[k] = r->nH2[k] * r->X[k] * Rout / bs;
         sv[k] = make_float2((float)(r->vr[k] / r->dv), (float)(r->dv * kSqrtLog2e / b));
         // LTE start at the local kinetic temperature (Sect. 3.3.2)
@@ -276,24 +296,46 @@ bool admit_upload(miloc_server* S, Request* r)
     struct Up { size_t o; const void* src; size_t bytes; };
     const Up ups[] = {
         {lay.mol, &m, sizeof(MolDev)},
+        {lay.roff, roff.data(), roff.size() * sizeof(int64_t)},
+        {lay.kmin, kmin.data(), kmin.size() * sizeof(int)},
         {lay.R, Rn.data(), n * sizeof(double)},
-        {lay.bimp, bn.data(), r->nrays * sizeof(double)},
+        {lay.b, b_all.data(), b_all.size() * sizeof(double)},
+        {lay.vrdv, vrdv.data(), n * sizeof(double)},
         {lay.area, an.data(), r->nrays * sizeof(double)},
         {lay.shellv, sv.data(), n * sizeof(float2)},
         {lay.x, xs.data(), xs.size() * sizeof(double)},
         {lay.nH2, r->nH2.data(), n * sizeof(double)},
         {lay.Tk, r->Tk.data(), n * sizeof(double)},
-        {lay.q, q.data(), n * sizeof(double)},
         {lay.nmolLb, nmolLb.data(), n * sizeof(double)},
         {lay.Ibg, ibf.data(), r->T * sizeof(float)},
+        {lay.Ibg64, r->Ibg.data(), r->T * sizeof(double)},
     };
     for (const Up& u : ups)
         if (hipMemcpyAsync(dptr(u.o), u.src, u.bytes, hipMemcpyHostToDevice, S->stream) != hipSuccess) {
             r->error = "upload failed";
             return false;
         }
+    if (launch_ray_steps(S->stream, n, static_cast<const double*>(dptr(lay.R)), (int)b_all.size(),
+                         static_cast<const double*>(dptr(lay.b)), static_cast<const int*>(dptr(lay.kmin)),
+                         static_cast<const long long*>(dptr(lay.roff)), static_cast<const double*>(dptr(lay.vrdv)),
+                         dptr(lay.steps), false) != hipSuccess) {
+        r->error = "ray step kernel failed";
+        return false;
+    }
+    // ray-sampled shell volumes W on the device (into the q slot), then q
+    double* dq = static_cast<double*>(dptr(lay.q));
+    if (launch_shell_weights(S->stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays,
+                             static_cast<const double*>(dptr(lay.b)), static_cast<const double*>(dptr(lay.area)),
+                             dq) != hipSuccess ||
+        hipMemcpyAsync(W.data(), dq, n * sizeof(double), hipMemcpyDeviceToHost, S->stream) != hipSuccess ||
+        hipStreamSynchronize(S->stream) != hipSuccess) {
+        r->error = "upload failed";
+        return false;
+    }
+    for (int k = 0; k < n; ++k) q[k] = W[k] > 0 ? r->dv / (bsq[k] * W[k]) : 0.0;
     // the host vectors must outlive the asynchronous copies
-    if (hipStreamSynchronize(S->stream) != hipSuccess) {
+    if (hipMemcpyAsync(dq, q.data(), n * sizeof(double), hipMemcpyHostToDevice, S->stream) != hipSuccess ||
+        hipStreamSynchronize(S->stream) != hipSuccess) {
         r->error = "upload failed";
         return false;
     }
@@ -304,8 +346,9 @@ bool admit_upload(miloc_server* S, Request* r)
     a.nrays = r->nrays;
     a.nch = r->nch;
     a.ntr = r->T;
-    a.R = static_cast<const double*>(dptr(lay.R));
-    a.bimp = static_cast<const double*>(dptr(lay.bimp));
+    a.steps = static_cast<const float2*>(dptr(lay.steps));
+    a.ray_off = static_cast<const long long*>(dptr(lay.roff));
+    a.kmin = static_cast<const int*>(dptr(lay.kmin));
     a.area = static_cast<const double*>(dptr(lay.area));
     a.shellv = static_cast<const float2*>(dptr(lay.shellv));
     a.ke = static_cast<const float2*>(dptr(lay.ke));
@@ -332,6 +375,8 @@ bool admit_upload(miloc_server* S, Request* r)
     d.nc = n;
     d.L = r->L;
     d.T = r->T;
+    r->d_ibg64 = static_cast<double*>(dptr(lay.Ibg64));
+    r->d_spec = static_cast<float*>(dptr(lay.spec));
     return true;
 }
 
@@ -370,27 +415,22 @@ bool rebuild_tables(miloc_server* S)
 bool finish_model(miloc_server* S, Request* r)
 {
     const int T = r->T;
-    float* Iout = nullptr;
-    double* ibg64 = nullptr;
-    bool ok = hipMallocAsync(reinterpret_cast<void**>(&Iout), (size_t)T * r->nch * sizeof(float), S->stream) == hipSuccess &&
-              hipMallocAsync(reinterpret_cast<void**>(&ibg64), T * sizeof(double), S->stream) == hipSuccess;
-    ok = ok && hipMemcpyAsync(ibg64, r->Ibg.data(), T * sizeof(double), hipMemcpyHostToDevice, S->stream) == hipSuccess;
-    ok = ok && launch_prepare(S->stream, r->n, r->desc.mol, T, r->desc.x, r->desc.nmolLb, ibg64, r->desc.ke_w,
-                              false) == hipSuccess;
+    float* Iout = r->d_spec;
+    bool ok = launch_prepare(S->stream, r->n, r->desc.mol, T, r->desc.x, r->desc.nmolLb, r->d_ibg64,
+                             r->desc.ke_w, false) == hipSuccess;
+    // the centre line of sight is the ray after the model's own rays
     March1DArgs<float> a = r->desc.m;
+    a.ray_off += r->nrays;
+    a.kmin += r->nrays;
     a.nrays = 1;
-    a.bimp = S->d_impact0;
-    a.area = S->d_impact0;
     a.Ibg = S->d_zero;
     a.Iout = Iout;
-    ok = ok && launch_march1d(S->stream, a, 64, false) == hipSuccess;
+    ok = ok && launch_march1d(S->stream, a, 16, false) == hipSuccess;
     std::vector<float> sp((size_t)T * r->nch);
     r->x.resize((size_t)r->n * r->L);
     ok = ok && hipMemcpyAsync(sp.data(), Iout, sp.size() * sizeof(float), hipMemcpyDeviceToHost, S->stream) == hipSuccess;
     ok = ok && hipMemcpyAsync(r->x.data(), r->desc.x, r->x.size() * sizeof(double), hipMemcpyDeviceToHost,
                               S->stream) == hipSuccess;
-    if (Iout) (void)hipFreeAsync(Iout, S->stream);
-    if (ibg64) (void)hipFreeAsync(ibg64, S->stream);
     ok = ok && hipStreamSynchronize(S->stream) == hipSuccess;
     r->spectra.resize(sp.size());
     for (int t = 0; t < T; ++t)
@@ -566,7 +606,6 @@ miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int ma
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_counts), 4 * sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_flags), 2 * max_slots * sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_zero), kMaxTrans * sizeof(float)) == hipSuccess;
-    ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_impact0), sizeof(double)) == hipSuccess;
     if (!ok) {
         miloc_server_destroy(S.release());
         return MILOC_ENOMEM;
@@ -574,7 +613,6 @@ miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int ma
     (void)hipMemset(S->d_counts, 0, 4 * sizeof(int));
     (void)hipMemset(S->d_flags, 0, 2 * max_slots * sizeof(unsigned long long));
     (void)hipMemset(S->d_zero, 0, kMaxTrans * sizeof(float));
-    (void)hipMemset(S->d_impact0, 0, sizeof(double));
     (void)hipMemset(S->d_models, 0, max_slots * sizeof(ServeModel));
     S->arena.init(hbm_budget_bytes);
     // grid of the persistent kernels and the captured tick graph
@@ -622,7 +660,7 @@ void miloc_server_destroy(miloc_server* S)
     if (S->graph_exec) (void)hipGraphExecDestroy(S->graph_exec);
     if (S->graph) (void)hipGraphDestroy(S->graph);
     void* bufs[] = {S->arena_mem, S->d_models, S->d_march, S->d_cell, S->d_se, S->d_counts, S->d_flags,
-                    S->d_zero, S->d_impact0};
+                    S->d_zero};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (S->stream) (void)hipStreamDestroy(S->stream);
@@ -689,7 +727,7 @@ miloc_status parse_request(miloc_server* S, const miloc_molecule* mol, const mil
     }
     if (n_channels < 8 || n_channels > kMaxServeChannels || !(dv_cms > 0) || !std::isfinite(v_min_cms) ||
         !std::isfinite(dv_cms))
-        return sfail(S, MILOC_EINVAL, "bad channel grid (8..1024 channels)");
+        return sfail(S, MILOC_EINVAL, "bad channel grid (8..512 channels)");
     if (!(T_bg_K >= 0) || !std::isfinite(T_bg_K) || !std::isfinite(tol) || max_iter < 1)
         return sfail(S, MILOC_EINVAL, "bad background, tolerance or iteration cap");
     r->n = n;
@@ -706,6 +744,18 @@ miloc_status parse_request(miloc_server* S, const miloc_molecule* mol, const mil
         r->impact[j] = m->impact_cm ? m->impact_cm[j] : (j + 0.5) * Rout / r->nrays;
         if (!(r->impact[j] > 0 && r->impact[j] < Rout) || (j > 0 && !(r->impact[j] > r->impact[j - 1])))
             return sfail(S, MILOC_EINVAL, "impact parameters must increase inside (0, R)");
+    }
+    // ray steps: 2 (n - 1 - kmin) + 2 per ray, plus the centre line of sight
+    {
+        std::vector<double> Rn(n);
+        for (int k = 0; k < n; ++k) Rn[k] = r->R[k] / Rout;
+        Rn[n - 1] = 1.0;
+        r->n_steps = 2 * (int64_t)n;
+        for (int j = 0; j < r->nrays; ++j) {
+            const double bj = r->impact[j] / Rout;
+            const int km = std::min<int>(n - 1, (int)(std::upper_bound(Rn.begin(), Rn.end(), bj) - Rn.begin()));
+            r->n_steps += 2 * (int64_t)(n - 1 - km) + 2;
+        }
     }
     // band must hold every line out to 5 Doppler widths
     double maxu = 0;
