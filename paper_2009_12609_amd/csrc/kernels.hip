@@ -102,24 +102,6 @@ __device__ __forceinline__ double group_sum(double v)
 // Radiative update of one step over the channel window.  Lanes take channels
 // clo + lane, clo + lane + LANES, ...  Returns the partial sums
 // sum e_c I_c beta_c and sum e_c (1 - beta_c) of this lane.
-template <int LANES, typename T>
-__device__ __forceinline__ void step_channels(T* __restrict__ I, int lane, int clo, int chi,
-                                              T frac, T ibs, T kl, T el, T& sj, T& sl)
-{
-    for (int c = clo + lane; c <= chi; c += LANES) {
-        const T xs = ((T)(c - clo) + frac) * ibs;
-        const T ec = fast_exp2(-xs * xs);
-        const T tau = kl * ec;
-        T omb, e;
-        escape_terms(tau, omb, e);
-        const T Iin = I[c];
-        const T u = ec - ec * omb;          // e_c beta_c
-        sj += Iin * u;
-        sl += ec * omb;
-        I[c] = Iin * e + el * u;
-    }
-}
-
 // Channel window [clo, chi] of a step: channels with |c - c*| <= Kw/ibs,
 // c* = -(chalf + w), clipped to the band.  frac = clo - c*.
 template <typename T>
@@ -262,13 +244,60 @@ __device__ __forceinline__ double omb_thin(double tau)
     escape_terms(tau, omb, e);
     return omb;
 }
-// 1 - beta for any tau.
-template <typename T>
-__device__ __forceinline__ T omb_any(T tau)
+// 1 - beta for any tau.  FP32: both forms evaluated and one selected, so
+// that a wavefront with mixed optical depths does not diverge.
+__device__ __forceinline__ float omb_any(float tau)
 {
-    T omb, e;
+    const float d = 1.0f - (1.0f - fast_exp2(-tau * kLog2eF)) * __builtin_amdgcn_rcpf(tau);
+    float h = (1.0f / 720.0f) - tau * (1.0f / 5040.0f);
+    h = (1.0f / 120.0f) - tau * h;
+    h = (1.0f / 24.0f) - tau * h;
+    h = (1.0f / 6.0f) - tau * h;
+    h = 0.5f - tau * h;
+    return fabsf(tau) < 0.2f ? tau * h : d;
+}
+__device__ __forceinline__ double omb_any(double tau)
+{
+    double omb, e;
     escape_terms(tau, omb, e);
     return omb;
+}
+
+// The channel window of one step for one ray (Sect. 2: I e^-tau + S(1 -
+// e^-tau) per channel, absorbed counts and the diagonal operator summed):
+// channels clo .. clo + nwin - 1, profile argument x_j = x0 + j ibs (scaled
+// so that the profile is exp2(-x^2)), tau_j = kl e_j, emission el e_j beta_j.
+// Partial sums of this lane in sj, sl.  The series/exact choice for 1 - beta
+// is made once per step for the whole wavefront.
+template <int LANES, typename T>
+__device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
+                                                T kl, T el, T& sj, T& sl)
+{
+    const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
+    T* __restrict__ row = I + clo;
+    if (thin) {
+        for (int j = lane; j < nwin; j += LANES) {
+            const T xs = (T)j * ibs + x0;
+            const T ec = fast_exp2(-xs * xs);
+            const T omb = omb_thin(kl * ec);
+            const T Iin = row[j];
+            const T u = ec - ec * omb;                 // e_c beta_c
+            sj += Iin * u;
+            sl += ec * omb;
+            row[j] = Iin + u * (el - kl * Iin);        // e^-tau = 1 - tau beta
+        }
+    } else {
+        for (int j = lane; j < nwin; j += LANES) {
+            const T xs = (T)j * ibs + x0;
+            const T ec = fast_exp2(-xs * xs);
+            const T omb = omb_any(kl * ec);
+            const T Iin = row[j];
+            const T u = ec - ec * omb;
+            sj += Iin * u;
+            sl += ec * omb;
+            row[j] = Iin + u * (el - kl * Iin);
+        }
+    }
 }
 
 }  // namespace
@@ -322,7 +351,6 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
                              : nullptr;
     const T aw = (T)D.aw;
     const int ns = D.nsteps;
-    const T lanef = (T)lane;
     // Invalid channel slots read and write a private dummy word in the
     // ray's padding so that no lane touches another ray's channels.
     T* __restrict__ dummy = I + p.nch + lane;
@@ -375,21 +403,7 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         const T kl = kv.x * rec.len;      // tau at the line centre
         const T el = kv.y * rec.len;
         T sj = 0, sl = 0;
-        // thin steps everywhere in the wavefront: short series for 1 - beta
-        const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
-        for (int j = lane; j < nwin; j += LANES) {
-            T* __restrict__ cell = I + clo + j;
-            const T xs = (lanef + (T)(j - lane)) * wv.y + wv.x;
-            const T ec = fast_exp2(-xs * xs);
-            const T tau = kl * ec;
-            const T omb = thin ? omb_thin(tau) : omb_any(tau);
-            const T Iin = *cell;
-            const T u = ec - ec * omb;                 // e_c beta_c
-            sj += Iin * u;
-            sl += ec * omb;
-            // I e^-tau + el e_c beta with e^-tau = 1 - tau beta
-            *cell = Iin + u * (el - kl * Iin);
-        }
+        window_channels<LANES, T>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
         (void)dummy;
         if (ACCUM) {
             sj = group_sum<LANES>(sj);
@@ -482,7 +496,6 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
     extern __shared__ unsigned char smem_raw[];
     T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)grp * p.ich;
     T* __restrict__ stk = p.stack + gid * (size_t)p.depth * p.ich;
-    const T lanef = (T)lane;
     for (;;) {
         unsigned long long item = 0;
         if (lane == 0) item = atomicAdd(p.counter, 1ull);
@@ -545,19 +558,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
-            const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
-            for (int j = lane; j < nwin; j += LANES) {
-                T* __restrict__ cp = I + clo + j;
-                const T xs = (lanef + (T)(j - lane)) * wv.y + wv.x;
-                const T ec = fast_exp2(-xs * xs);
-                const T tau = kl * ec;
-                const T omb = thin ? omb_thin(tau) : omb_any(tau);
-                const T Iin = *cp;
-                const T u = ec - ec * omb;
-                sj += Iin * u;
-                sl += ec * omb;
-                *cp = Iin + u * (el - kl * Iin);
-            }
+            window_channels<LANES, T>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
@@ -595,13 +596,16 @@ __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); 
 // runs.  With p.lds_acc the per-step sums go to per-shell LDS accumulators
 // (LDS atomics do not stall the next step's loads), flushed to the FP64
 // global sums once per workgroup; otherwise each step issues two FP64 atomics.
-template <typename T, int LANES, bool ACCUM>
-__device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0, int t, unsigned char* smem_raw)
+template <typename T, int LANES, bool ACCUM, bool TRANS_GROUPS = false>
+__device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0, int t_in, unsigned char* smem_raw)
 {
     using T2 = typename V2<T>::type;
     const int lane = threadIdx.x % LANES;
     const int rib = threadIdx.x / LANES;
-    const int j = ray0 + rib;
+    // TRANS_GROUPS (lines of sight, no accumulation): the lane groups take
+    // transitions t_in, t_in + 1, ... of ray ray0 instead of consecutive rays
+    const int j = TRANS_GROUPS ? (t_in + rib < p.ntr_total ? ray0 : p.nrays) : ray0 + rib;
+    const int t = TRANS_GROUPS ? (t_in + rib < p.ntr_total ? t_in + rib : t_in) : t_in;
     const int n = p.n;
     const bool lds_acc = ACCUM && p.lds_acc;
     T* __restrict__ sacc = reinterpret_cast<T*>(smem_raw);                 // [n][2] when lds_acc
@@ -652,7 +656,7 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
             window<T>((double)r.y, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
             const T tl = r.x;
             T sj = 0, sl = 0;
-            step_channels<LANES, T>(I, lane, clo, chi, frac, sv.y, kev.x * tl, kev.y * tl, sj, sl);
+            window_channels<LANES, T>(I, lane, clo, chi - clo + 1, frac * sv.y, sv.y, kev.x * tl, kev.y * tl, sj, sl);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
@@ -909,7 +913,7 @@ __global__ __launch_bounds__(256) void serve_prepare_kernel(const ServeModel* __
         const ServeModel& M = models[it.x];
         const int k = it.y + threadIdx.x;
         if (k < M.nc) {
-            prepare_cell<float>(k, M.mol, M.T, M.x, M.nmolLb, nullptr, M.ke_w);
+            prepare_cell<float>(k, M.mol, M.T, M.x, M.nmolLb, M.mode ? M.ibg64 : nullptr, M.ke_w);
             for (int t = 0; t < M.T; ++t) M.acc_w[(size_t)k * M.T + t] = make_double2(0.0, 0.0);
         }
         if (it.y == 0 && threadIdx.x == 0) {
@@ -926,9 +930,21 @@ __global__ __launch_bounds__(256) void serve_march_kernel(const ServeModel* __re
     extern __shared__ unsigned char smem_raw[];
     const int n = *n_items;
     for (int w = blockIdx.x; w < n; w += gridDim.x) {
-        const int4 it = items[w];                  // model, transition, first ray
-        const March1DArgs<float> a = models[it.x].m;
-        march1d_block<float, 16, true>(a, it.z, it.y, smem_raw);
+        const int4 it = items[w];                  // model, transition, first ray, spectrum
+        const ServeModel& M = models[it.x];
+        if (it.w) {
+            // the centre line of sight (stored after the model's rays), I - I_bg
+            March1DArgs<float> a = M.m;
+            a.ray_off += a.nrays;
+            a.kmin += a.nrays;
+            a.nrays = 1;
+            a.Ibg = M.zero;
+            a.Iout = M.spec;
+            march1d_block<float, 64, false, true>(a, 0, it.y, smem_raw);
+        } else {
+            const March1DArgs<float> a = M.m;
+            march1d_block<float, 16, true>(a, it.z, it.y, smem_raw);
+        }
         __syncthreads();
     }
 }
@@ -1074,6 +1090,7 @@ hipError_t dispatch3d(hipStream_t s, const March3DArgs<T>& a, int lanes, bool ac
 template <typename T>
 hipError_t dispatch1d(hipStream_t s, const March1DArgs<T>& a, int lanes, bool accum)
 {
+    if (lanes == 8) return accum ? do_march1d<T, 8, true>(s, a) : do_march1d<T, 8, false>(s, a);
     if (lanes == 16) return accum ? do_march1d<T, 16, true>(s, a) : do_march1d<T, 16, false>(s, a);
     if (lanes == 32) return accum ? do_march1d<T, 32, true>(s, a) : do_march1d<T, 32, false>(s, a);
     return accum ? do_march1d<T, 64, true>(s, a) : do_march1d<T, 64, false>(s, a);

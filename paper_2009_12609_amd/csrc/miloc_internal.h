@@ -144,13 +144,16 @@ struct ServeModel {
     const double* q;
     unsigned long long* delta_bits;      // this model's max relative change of the tick
     unsigned int* bad;
-    int nc, L, T, pad;
+    const double* ibg64;                 // background per transition (spectra: march I - I_bg)
+    float* spec;                         // centre spectra [T][nch] (occupation units, I - I_bg)
+    const float* zero;                   // T zeros
+    int nc, L, T, mode;                  // mode 0: iterate, 1: final spectra this tick
 };
 
 // Device work lists of one tick.
 struct ServeTables {
     const ServeModel* models;
-    const int4* march_items;             // (model, transition, first ray, 0)
+    const int4* march_items;             // (model, transition, first ray, 1 = centre spectrum)
     const int* n_march;
     const int2* cell_items;              // (model, first cell), 256 cells each
     const int* n_cell;

@@ -114,6 +114,11 @@ struct miloc_ctx {
     int qcount[3] = {0, 0, 0}, qoff[3] = {0, 0, 0};
     std::vector<double> Iscale, Ibg;   // per transition: 2 h nu^3 / c^2, background (occupation)
     std::vector<double> Rn;            // 1D: outer radii / R_out
+    // 1D spectra: step tables of the last requested lines of sight (reused
+    // while the model, precision and impact parameters stay the same)
+    std::vector<double> los_b;
+    bool los_fp64 = false, los_valid = false;
+    DevBuf d_los_b, d_los_steps, d_los_off, d_los_kmin, d_los_out;
     std::vector<double> q_host;
     int lanes = 32;
     double steps_per_trans = 0;
@@ -428,6 +433,7 @@ miloc_status ensure_static(miloc_ctx* c)
     if (st != MILOC_OK) return st;
     if (!c->has_spec) return fail(c, MILOC_ESTATE, "spectral grid not set");
     if (!c->dirty) return MILOC_OK;
+    c->los_valid = false;
     const bool fp64 = c->precision == MILOC_MARCH_FP64;
     const int64_t nc = c->nc;
     CellView cv{c};
@@ -469,7 +475,7 @@ miloc_status ensure_static(miloc_ctx* c)
         c->lanes = 16;                    // octree and 1D marches: groups of 16, any window width
     if (const char* ev = std::getenv("MILOC_LANES")) {
         const int l = std::atoi(ev);
-        if ((c->kind == 1 && (l == 16 || l == 32 || l == 64)) ||
+        if ((c->kind == 1 && (l == 8 || l == 16 || l == 32 || l == 64)) ||
             (c->kind == 3 && (l == 8 || l == 16 || l == 32 || l == 64)))
             c->lanes = l;
     }
@@ -633,6 +639,7 @@ miloc_status ensure_static(miloc_ctx* c)
 
 void invalidate_model(miloc_ctx* c)
 {
+    c->los_valid = false;
     c->base_ready = false;
     c->dirty = true;
     c->has_pops = false;
@@ -693,7 +700,8 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.Kw = (TT)c->Kw;
         a.Iout = Iout;
         a.ntr_total = c->T;
-        e = launch_march1d(c->stream, a, c->lanes, accum);
+        // lines of sight run alone: 64 lanes shorten each step's channel loop
+        e = launch_march1d(c->stream, a, accum ? c->lanes : 64, accum);
     }
     HIPCHK(c, e);
     return MILOC_OK;
@@ -1311,20 +1319,29 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
             bn.resize(n_los);
             for (int j = 0; j < n_los; ++j) bn[j] = c->impact[j] / Rout;
         }
-        HIPCHK(c, extra.ensure(bn.size() * sizeof(double)));
-        HIPCHK(c, hipMemcpy(extra.p, bn.data(), bn.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
-        DevBuf rs, ro, rk;
-        s = upload_ray_steps(c, bn, fp64, rs, ro, rk);
-        if (s) return s;
-        s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los, nullptr, &rs, &ro, &rk)
-                 : launch_march<float>(c, 1, trans, false, out.as<float>(), false, nullptr, nullptr, 0, extra.as<double>(), n_los, nullptr, &rs, &ro, &rk);
-        if (s) return s;
+        if (!(c->los_valid && c->los_fp64 == fp64 && c->los_b == bn)) {
+            c->los_valid = false;
+            HIPCHK(c, c->d_los_b.ensure(bn.size() * sizeof(double)));
+            HIPCHK(c, hipMemcpy(c->d_los_b.p, bn.data(), bn.size() * sizeof(double), hipMemcpyHostToDevice));
+            s = upload_ray_steps(c, bn, fp64, c->d_los_steps, c->d_los_off, c->d_los_kmin);
+            if (s) return s;
+            c->los_b = bn;
+            c->los_fp64 = fp64;
+            c->los_valid = true;
+        }
+        HIPCHK(c, c->d_los_out.ensure((size_t)n_los * c->nch * tsz));
+        s = fp64 ? launch_march<double>(c, 1, trans, false, c->d_los_out.as<double>(), false, nullptr, nullptr, 0,
+                                        c->d_los_b.as<double>(), n_los, nullptr, &c->d_los_steps, &c->d_los_off,
+                                        &c->d_los_kmin)
+                 : launch_march<float>(c, 1, trans, false, c->d_los_out.as<float>(), false, nullptr, nullptr, 0,
+                                       c->d_los_b.as<double>(), n_los, nullptr, &c->d_los_steps, &c->d_los_off,
+                                       &c->d_los_kmin);
         if (s) return s;
     }
     const size_t n = (size_t)n_los * c->nch;
     std::vector<char> h(n * tsz);
-    HIPCHK(c, hipMemcpyAsync(h.data(), out.p, n * tsz, hipMemcpyDeviceToHost, c->stream));
+    const DevBuf& res = c->kind == 1 ? c->d_los_out : out;
+    HIPCHK(c, hipMemcpyAsync(h.data(), res.p, n * tsz, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const double sc = c->Iscale[trans];
     for (size_t i = 0; i < n; ++i) {

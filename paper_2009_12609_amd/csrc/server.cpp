@@ -126,8 +126,10 @@ struct Request {
     size_t off = 0, bytes = 0;
     int slot = -1;
     ServeModel desc{};
-    double* d_ibg64 = nullptr;  // arena copies: background (FP64) and the spectra output
-    float* d_spec = nullptr;
+    int phase = 0;              // 0: iterating, 1: spectra in the next tick, then retired
+    std::vector<float> sp_host; // spectra copied back after the spectra tick
+    struct Staging;             // host copies of an admission in flight
+    std::shared_ptr<Staging> stage;
     std::vector<double> Iscale, Ibg;
     // results
     std::vector<double> x, spectra;
@@ -224,15 +226,29 @@ miloc_status sfail(miloc_server* s, miloc_status code, const std::string& m)
     return code;
 }
 
-// Host-side static preparation of an admitted request and upload into its
-// arena block.  Returns false with r->error set on failure.
-bool admit_upload(miloc_server* S, Request* r)
+struct Request::Staging {
+    MolDev m;
+    std::vector<double> Rn, bn, an, W, q, nmolLb, xs, b_all, vrdv, bsq;
+    std::vector<int64_t> roff;
+    std::vector<int> kmin;
+    std::vector<float2> sv;
+    std::vector<float> ibf;
+};
+
+// Admission, first half: host-side statics of a request, uploads into its
+// arena block, device-side ray steps and shell volumes, W back to the host.
+// Everything is queued on the server stream; the host copies live in
+// r->stage until the caller has synchronised.  False with r->error set on
+// failure.
+bool admit_stage1(miloc_server* S, Request* r)
 {
     const Layout lay = layout_of(*r);
+    r->stage = std::make_shared<Request::Staging>();
+    Request::Staging& G = *r->stage;
     char* base = static_cast<char*>(S->arena_mem) + r->off;
     auto dptr = [&](size_t o) { return static_cast<void*>(base + o); };
     // molecule
-    MolDev m;
+    MolDev& m = G.m;
     std::memset(&m, 0, sizeof(m));
     m.L = r->L;
     m.T = r->T;
@@ -250,7 +266,17 @@ bool admit_upload(miloc_server* S, Request* r)
     // geometry and per-shell statics
     const int n = r->n;
     const double Rout = r->R[n - 1];
-    std::vector<double> Rn(n), bn(r->nrays), an(r->nrays), W(n), q(n), nmolLb(n), xs((size_t)n * r->L);
+    std::vector<double>& Rn = G.Rn;
+    std::vector<double>& bn = G.bn;
+    std::vector<double>& an = G.an;
+    std::vector<double>& nmolLb = G.nmolLb;
+    std::vector<double>& xs = G.xs;
+    Rn.resize(n);
+    bn.resize(r->nrays);
+    an.resize(r->nrays);
+    nmolLb.resize(n);
+    xs.resize((size_t)n * r->L);
+    G.W.resize(n);
     for (int k = 0; k < n; ++k) Rn[k] = r->R[k] / Rout;
     Rn[n - 1] = 1.0;
     for (int j = 0; j < r->nrays; ++j) bn[j] = r->impact[j] / Rout;
@@ -261,18 +287,22 @@ bool admit_upload(miloc_server* S, Request* r)
     }
     // ray layout of the model's rays and of the centre line of sight (spectra);
     // the step records themselves are computed on the device below
-    std::vector<double> b_all(bn);
+    std::vector<double>& b_all = G.b_all;
+    b_all = bn;
     b_all.push_back(0.0);
-    std::vector<int64_t> roff;
-    std::vector<int> kmin;
+    std::vector<int64_t>& roff = G.roff;
+    std::vector<int>& kmin = G.kmin;
     if (shell_ray_layout(n, Rn.data(), (int)b_all.size(), b_all.data(), roff, kmin) != r->n_steps) {
         r->error = "ray step count mismatch";
         return false;
     }
-    std::vector<double> vrdv(n);
+    std::vector<double>& vrdv = G.vrdv;
+    vrdv.resize(n);
     for (int k = 0; k < n; ++k) vrdv[k] = r->vr[k] / r->dv;
-    std::vector<float2> sv(n);
-    std::vector<double> bsq(n);
+    std::vector<float2>& sv = G.sv;
+    sv.resize(n);
+    std::vector<double>& bsq = G.bsq;
+    bsq.resize(n);
     for (int k = 0; k < n; ++k) {
         const double b = std::sqrt(2.0 * kK * r->Tk[k] / (r->mass * kAmu) + r->bt[k] * r->bt[k]);
         const double bs = b * std::sqrt(kPi);
@@ -286,7 +316,8 @@ bool admit_upload(miloc_server* S, Request* r)
     }
     r->Iscale.resize(r->T);
     r->Ibg.resize(r->T);
-    std::vector<float> ibf(r->T);
+    std::vector<float>& ibf = G.ibf;
+    ibf.resize(r->T);
     for (int t = 0; t < r->T; ++t) {
         r->Iscale[t] = 2.0 * kH * std::pow(r->nu[t], 3) / (kC * kC);
         const double xx = r->Tbg > 0 ? kH * r->nu[t] / (kK * r->Tbg) : INFINITY;
@@ -322,20 +353,31 @@ bool admit_upload(miloc_server* S, Request* r)
         r->error = "ray step kernel failed";
         return false;
     }
-    // ray-sampled shell volumes W on the device (into the q slot), then q
+    // ray-sampled shell volumes W on the device (into the q slot), back to the host
     double* dq = static_cast<double*>(dptr(lay.q));
     if (launch_shell_weights(S->stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays,
                              static_cast<const double*>(dptr(lay.b)), static_cast<const double*>(dptr(lay.area)),
                              dq) != hipSuccess ||
-        hipMemcpyAsync(W.data(), dq, n * sizeof(double), hipMemcpyDeviceToHost, S->stream) != hipSuccess ||
-        hipStreamSynchronize(S->stream) != hipSuccess) {
+        hipMemcpyAsync(G.W.data(), dq, n * sizeof(double), hipMemcpyDeviceToHost, S->stream) != hipSuccess) {
         r->error = "upload failed";
         return false;
     }
-    for (int k = 0; k < n; ++k) q[k] = W[k] > 0 ? r->dv / (bsq[k] * W[k]) : 0.0;
-    // the host vectors must outlive the asynchronous copies
-    if (hipMemcpyAsync(dq, q.data(), n * sizeof(double), hipMemcpyHostToDevice, S->stream) != hipSuccess ||
-        hipStreamSynchronize(S->stream) != hipSuccess) {
+    return true;
+}
+
+// Admission, second half (after the stream has drained): q from W, its upload,
+// and the model descriptor.
+bool admit_stage2(miloc_server* S, Request* r)
+{
+    const Layout lay = layout_of(*r);
+    char* base = static_cast<char*>(S->arena_mem) + r->off;
+    auto dptr = [&](size_t o) { return static_cast<void*>(base + o); };
+    Request::Staging& G = *r->stage;
+    const int n = r->n;
+    G.q.resize(n);
+    for (int k = 0; k < n; ++k) G.q[k] = G.W[k] > 0 ? r->dv / (G.bsq[k] * G.W[k]) : 0.0;
+    double* dq = static_cast<double*>(dptr(lay.q));
+    if (hipMemcpyAsync(dq, G.q.data(), n * sizeof(double), hipMemcpyHostToDevice, S->stream) != hipSuccess) {
         r->error = "upload failed";
         return false;
     }
@@ -375,8 +417,10 @@ bool admit_upload(miloc_server* S, Request* r)
     d.nc = n;
     d.L = r->L;
     d.T = r->T;
-    r->d_ibg64 = static_cast<double*>(dptr(lay.Ibg64));
-    r->d_spec = static_cast<float*>(dptr(lay.spec));
+    d.ibg64 = static_cast<const double*>(dptr(lay.Ibg64));
+    d.spec = static_cast<float*>(dptr(lay.spec));
+    d.zero = S->d_zero;
+    d.mode = 0;
     return true;
 }
 
@@ -384,17 +428,25 @@ bool admit_upload(miloc_server* S, Request* r)
 bool rebuild_tables(miloc_server* S)
 {
     std::vector<ServeModel> models(S->max_slots);
-    std::vector<int4> march;
+    std::vector<int4> march, spectra;
     std::vector<int2> cell, se;
     for (int sl = 0; sl < S->max_slots; ++sl) {
         Request* r = S->active[sl];
         if (!r) continue;
         models[sl] = r->desc;
-        for (int t = 0; t < r->T; ++t)
-            for (int j = 0; j < r->nrays; j += kRaysPerBlock) march.push_back(make_int4(sl, t, j, 0));
+        models[sl].mode = r->phase;
+        if (r->phase == 0) {
+            for (int t = 0; t < r->T; ++t)
+                for (int j = 0; j < r->nrays; j += kRaysPerBlock) march.push_back(make_int4(sl, t, j, 0));
+            for (int k = 0; k < r->n; k += kSeBs) se.push_back(make_int2(sl, k));
+        } else {
+            // centre spectra, four transitions per item; first in the list so
+            // that these single-ray chains start at the beginning of the tick
+            for (int t = 0; t < r->T; t += 4) spectra.push_back(make_int4(sl, t, 0, 1));
+        }
         for (int k = 0; k < r->n; k += 256) cell.push_back(make_int2(sl, k));
-        for (int k = 0; k < r->n; k += kSeBs) se.push_back(make_int2(sl, k));
     }
+    march.insert(march.begin(), spectra.begin(), spectra.end());
     if (march.size() > S->cap_march || cell.size() > S->cap_cell || se.size() > S->cap_se) return false;
     const int counts[3] = {(int)march.size(), (int)cell.size(), (int)se.size()};
     bool ok = hipMemcpyAsync(S->d_models, models.data(), models.size() * sizeof(ServeModel),
@@ -410,33 +462,14 @@ bool rebuild_tables(miloc_server* S)
     return ok;
 }
 
-// Final spectra of every transition towards the centre (impact parameter 0),
-// then populations to the host.
-bool finish_model(miloc_server* S, Request* r)
+// Results of a model whose spectra ran in the last tick: host copies were
+// queued after the tick; convert the spectra to CGS.
+void take_results(Request* r, const std::vector<float>& sp)
 {
-    const int T = r->T;
-    float* Iout = r->d_spec;
-    bool ok = launch_prepare(S->stream, r->n, r->desc.mol, T, r->desc.x, r->desc.nmolLb, r->d_ibg64,
-                             r->desc.ke_w, false) == hipSuccess;
-    // the centre line of sight is the ray after the model's own rays
-    March1DArgs<float> a = r->desc.m;
-    a.ray_off += r->nrays;
-    a.kmin += r->nrays;
-    a.nrays = 1;
-    a.Ibg = S->d_zero;
-    a.Iout = Iout;
-    ok = ok && launch_march1d(S->stream, a, 16, false) == hipSuccess;
-    std::vector<float> sp((size_t)T * r->nch);
-    r->x.resize((size_t)r->n * r->L);
-    ok = ok && hipMemcpyAsync(sp.data(), Iout, sp.size() * sizeof(float), hipMemcpyDeviceToHost, S->stream) == hipSuccess;
-    ok = ok && hipMemcpyAsync(r->x.data(), r->desc.x, r->x.size() * sizeof(double), hipMemcpyDeviceToHost,
-                              S->stream) == hipSuccess;
-    ok = ok && hipStreamSynchronize(S->stream) == hipSuccess;
     r->spectra.resize(sp.size());
-    for (int t = 0; t < T; ++t)
+    for (int t = 0; t < r->T; ++t)
         for (int c = 0; c < r->nch; ++c)
             r->spectra[(size_t)t * r->nch + c] = (double)sp[(size_t)t * r->nch + c] * r->Iscale[t];
-    return ok;
 }
 
 void worker_loop(miloc_server* S)
@@ -478,8 +511,9 @@ void worker_loop(miloc_server* S)
                 continue;
             }
         }
-        for (Request* r : to_admit) {
-            if (!admit_upload(S, r)) {
+        if (!to_admit.empty()) {
+            // all admissions of this round share two stream synchronisations
+            auto fail_admission = [&](Request* r) {
                 std::lock_guard<std::mutex> lk(S->mu);
                 r->state = 3;
                 r->status = MILOC_EDEVICE;
@@ -487,7 +521,28 @@ void worker_loop(miloc_server* S)
                 S->arena.release(r->off, r->bytes);
                 S->active[r->slot] = nullptr;
                 S->stats.failed++;
+            };
+            std::vector<Request*> staged;
+            for (Request* r : to_admit) {
+                if (admit_stage1(S, r)) staged.push_back(r);
+                else fail_admission(r);
             }
+            bool ok = hipStreamSynchronize(S->stream) == hipSuccess;
+            for (Request* r : staged)
+                if (ok && !admit_stage2(S, r)) fail_admission(r);
+            ok = ok && hipStreamSynchronize(S->stream) == hipSuccess;
+            for (Request* r : to_admit) r->stage.reset();
+            if (!ok) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->device_error = true;
+                sfail(S, MILOC_EDEVICE, "admission upload failed");
+                for (Request*& r : S->active)
+                    if (r) { r->state = 3; r->status = MILOC_EDEVICE; r->t_done = now_s(); r = nullptr; }
+                S->stop = true;
+                S->cv.notify_all();
+                return;
+            }
+            S->cv.notify_all();
             dirty = true;
         }
         if (dirty) {
@@ -500,12 +555,23 @@ void worker_loop(miloc_server* S)
             }
             dirty = false;
         }
-        // one tick = one ALI iteration of every resident model
+        // one tick = one ALI iteration of every iterating model and the centre
+        // spectra of every model that finished in the previous tick
         const double t0 = now_s();
         hipError_t e = hipGraphLaunch(S->graph_exec, S->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(flags.data(), S->d_flags, flags.size() * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, S->stream);
+        for (Request* r : S->active) {
+            if (!r || r->phase != 1 || e != hipSuccess) continue;
+            r->sp_host.resize((size_t)r->T * r->nch);
+            r->x.resize((size_t)r->n * r->L);
+            e = hipMemcpyAsync(r->sp_host.data(), r->desc.spec, r->sp_host.size() * sizeof(float),
+                               hipMemcpyDeviceToHost, S->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->x.data(), r->desc.x, r->x.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                   S->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
         if (e != hipSuccess) {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -517,56 +583,52 @@ void worker_loop(miloc_server* S)
             S->cv.notify_all();
             return;
         }
-        std::vector<Request*> finished;
+        bool retired = false;
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->stats.ticks++;
             S->stats.busy_s += now_s() - t0;
+            auto retire = [&](Request* r) {
+                r->t_done = now_s();
+                if (r->cancel_req) {
+                    r->state = 4;
+                    S->stats.cancelled++;
+                } else {
+                    const bool good = r->status == MILOC_OK || r->status == MILOC_ENOTCONV;
+                    if (good) take_results(r, r->sp_host);
+                    r->state = good ? 2 : 3;
+                    if (good) S->stats.completed++; else S->stats.failed++;
+                }
+                S->arena.release(r->off, r->bytes);
+                S->active[r->slot] = nullptr;
+                dirty = true;
+                retired = true;
+            };
             for (int sl = 0; sl < S->max_slots; ++sl) {
                 Request* r = S->active[sl];
                 if (!r) continue;
+                if (r->phase == 1) {               // its spectra ran in this tick
+                    retire(r);
+                    continue;
+                }
                 r->iters++;
                 double d;
                 std::memcpy(&d, &flags[2 * sl], sizeof(double));
                 r->last_delta = d;
                 const unsigned bad = (unsigned)(flags[2 * sl + 1] & 0xffffffffu);
-                if (bad) {
+                if (r->cancel_req) {
+                    retire(r);
+                } else if (bad) {
                     r->status = MILOC_ENUMERIC;
-                    finished.push_back(r);
-                } else if (r->tol > 0 && d < r->tol) {
-                    r->status = MILOC_OK;
-                    finished.push_back(r);
-                } else if (r->iters >= r->max_iter) {
-                    r->status = r->tol > 0 ? MILOC_ENOTCONV : MILOC_OK;
-                    finished.push_back(r);
-                } else if (r->cancel_req) {
-                    finished.push_back(r);
+                    retire(r);
+                } else if ((r->tol > 0 && d < r->tol) || r->iters >= r->max_iter) {
+                    r->status = (r->tol > 0 && !(d < r->tol)) ? MILOC_ENOTCONV : MILOC_OK;
+                    r->phase = 1;
+                    dirty = true;
                 }
             }
         }
-        for (Request* r : finished) {
-            bool cancelled;
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                cancelled = r->cancel_req;
-            }
-            const bool ok = cancelled || r->status == MILOC_ENUMERIC || finish_model(S, r);
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (!ok) r->status = MILOC_EDEVICE;
-            r->t_done = now_s();
-            if (!cancelled) {
-                const bool good = r->status == MILOC_OK || r->status == MILOC_ENOTCONV;
-                r->state = good ? 2 : 3;
-                if (good) S->stats.completed++; else S->stats.failed++;
-            } else {
-                r->state = 4;
-                S->stats.cancelled++;
-            }
-            S->arena.release(r->off, r->bytes);
-            S->active[r->slot] = nullptr;
-            dirty = true;
-        }
-        if (!finished.empty()) S->cv.notify_all();
+        if (retired) S->cv.notify_all();
     }
 }
 

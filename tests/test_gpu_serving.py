@@ -112,3 +112,30 @@ def test_bad_requests_are_isolated_and_cancel_works():
     st = srv.stats()
     assert st["cancelled"] == 1 and st["completed"] == 2
     srv.close()
+
+
+def test_cancel_while_resident():
+    """A request cancelled while it is on the device leaves at the next tick;
+    the slot is reused by the next request, whose result is unaffected."""
+    import time
+    reqs = small_stream(2, seed=16)
+    srv = miloc.Server(hbm_budget_bytes=1 << 30, max_slots=1)
+    t_long = srv.submit(reqs[0].mol, reqs[0].model, reqs[0].spec, reqs[0].T_bg, tol=1e-300, max_iter=100000)
+    for _ in range(2000):
+        if srv.stats()["active"] == 1:
+            break
+        time.sleep(0.005)
+    assert srv.stats()["active"] == 1
+    srv.cancel(t_long)
+    assert srv.wait(t_long, 60.0)
+    _, _, info, rc = srv.take(t_long)
+    assert rc == miloc.ESTATE
+    t2 = srv.submit(reqs[1].mol, reqs[1].model, reqs[1].spec, reqs[1].T_bg, tol=1e-6, max_iter=200)
+    assert srv.wait(t2, 60.0)
+    x, _, info, rc = srv.take(t2)
+    assert rc == miloc.OK
+    xa, _ = alone(reqs[1], info["iterations"])
+    assert rel(x, xa) < 1e-5
+    st = srv.stats()
+    assert st["cancelled"] == 1 and st["completed"] == 1 and st["arena_used"] == 0
+    srv.close()
