@@ -26,11 +26,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 # Algorithmic bytes per ray-cell step of one transition: read the cell's
 # {kappa, eta} (8 B) and {u/dv, dv/b} (16 B), read-modify-write the FP64
 # {J, Lambda} accumulator pair (16 B, counted once).
 BYTES_PER_STEP = 40.0
+# Algorithmic FP32 operations per in-window channel update: profile argument
+# (FMA, 2), its square (1), the exponential (1), tau (1), the escape series
+# (3 FMA + 1, 7), e_c beta (FMA, 2), the two absorbed-count sums (2 FMA, 4),
+# the intensity update (2 FMA, 4).
+FLOPS_PER_CHANNEL = 22.0
+WINDOW_K = 5.0                # Doppler widths on each side (FP32 march)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march3d_regular_128_traffic.json")
+
+
+def mean_window_channels(w) -> float:
+    """Mean number of channels in a step's window: 2 K b / dv per cell,
+    clipped to the band (every cell is crossed about equally often)."""
+    import numpy as np
+    m = w.model
+    AMU, KB = 1.66053906660e-24, 1.380649e-16
+    b = np.sqrt(2 * KB * m.T_kin.astype(float) / (w.mol.mass_amu * AMU) + m.b_turb.astype(float) ** 2)
+    return float(np.mean(np.minimum(w.spec.n_channels, 2 * WINDOW_K * b / w.spec.dv)))
 
 
 def kernel_source_hash() -> str:
@@ -295,7 +312,10 @@ def main():
     march_ms = cnt["march_ms"] / launches
     steps_per_launch = cnt["ray_steps"] / launches
     bytes_per_launch = steps_per_launch * BYTES_PER_STEP
-    achieved = bytes_per_launch / (march_ms * 1e-3) / 1e9
+    hbm_gbs = bytes_per_launch / (march_ms * 1e-3) / 1e9
+    nwin = mean_window_channels(w)
+    flops_per_launch = steps_per_launch * nwin * FLOPS_PER_CHANNEL
+    achieved = flops_per_launch / (march_ms * 1e-3) / 1e12
     src_hash = kernel_source_hash()
     traffic = measured_traffic(src_hash)
 
@@ -326,13 +346,17 @@ def main():
             "march_updates_per_s": updates / (cnt["march_ms"] * 1e-3),
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": traffic,
             "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true>",
+            "flops_per_channel_update": FLOPS_PER_CHANNEL,
+            "window_channels_mean": nwin,
+            "hbm_algorithmic_gbs": hbm_gbs,
+            "hbm_algorithmic_frac": hbm_gbs / HBM_PEAK_GBS,
             "bytes_per_step": BYTES_PER_STEP,
             "kernel_source_hash": src_hash,
         },

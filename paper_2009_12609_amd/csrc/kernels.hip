@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
 }
 
 // ---------------------------------------------------------------- octree march
-// Persistent lane groups of 16 take work units (one root line's rays for one
+// Persistent lane groups (8 or 16 lanes) take work units (one root line's rays for one
 // transition) from a global counter, largest units first.  Each unit replays
 // its host-built step list: a record names the leaf and the step length and
 // says how the ray's intensity starts (continue, background, or the top saved
@@ -484,10 +484,9 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
 // in a per-group stack in device memory.  The step itself is the regular
 // grid's: channel window of the (direction, leaf) pair, I e^-tau + S(1 -
 // e^-tau), absorbed-count and Lambda sums folded into FP64 accumulators.
-template <typename T, bool ACCUM>
+template <typename T, int LANES, bool ACCUM>
 __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
 {
-    constexpr int LANES = 16;
     using T2 = typename V2<T>::type;
     using T4 = typename V4<T>::type;
     const int lane = threadIdx.x % LANES;
@@ -511,7 +510,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         const T Ibg = p.Ibg[t];
         const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
         int sp = -1;
-        // records arrive 16 at a time, one per lane, and are broadcast with
+        // records arrive LANES at a time, one per lane, and are broadcast with
         // shuffles; the next step's cell data are loaded before this step runs
         uint2 mine = rec[lane < tr.n ? lane : 0];
         double mine64 = (sizeof(T) == 8 && rec64) ? rec64[lane < tr.n ? lane : 0] : 0.0;
@@ -1146,29 +1145,35 @@ hipError_t do_gather3d(hipStream_t s, const Gather3DArgs<T>& a)
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a) { return do_gather3d(s, a); }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a) { return do_gather3d(s, a); }
 
-template <typename T>
+template <typename T, int LANES>
 hipError_t do_march_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, bool accum)
 {
-    constexpr int kGroupsPerBlock = 16;
+    constexpr int kGroupsPerBlock = 256 / LANES;
     const int blocks = (groups + kGroupsPerBlock - 1) / kGroupsPerBlock;
     const size_t shm = (size_t)kGroupsPerBlock * a.ich * sizeof(T);
     if (shm > 64 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(a.counter, 0, sizeof(unsigned long long), s);
     if (e != hipSuccess) return e;
     if (accum)
-        hipLaunchKernelGGL((march_oct_kernel<T, true>), dim3(blocks), dim3(kGroupsPerBlock * 16), shm, s, a);
+        hipLaunchKernelGGL((march_oct_kernel<T, LANES, true>), dim3(blocks), dim3(256), shm, s, a);
     else
-        hipLaunchKernelGGL((march_oct_kernel<T, false>), dim3(blocks), dim3(kGroupsPerBlock * 16), shm, s, a);
+        hipLaunchKernelGGL((march_oct_kernel<T, LANES, false>), dim3(blocks), dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum)
+template <typename T>
+hipError_t dispatch_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, bool accum, int lanes)
 {
-    return do_march_oct(s, a, groups, accum);
+    return lanes == 8 ? do_march_oct<T, 8>(s, a, groups, accum) : do_march_oct<T, 16>(s, a, groups, accum);
 }
-hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<double>& a, int groups, bool accum)
+
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum, int lanes)
 {
-    return do_march_oct(s, a, groups, accum);
+    return dispatch_oct(s, a, groups, accum, lanes);
+}
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<double>& a, int groups, bool accum, int lanes)
+{
+    return dispatch_oct(s, a, groups, accum, lanes);
 }
 
 hipError_t launch_serve_tick(hipStream_t s, const ServeTables& tb, const ServeGrid& g)

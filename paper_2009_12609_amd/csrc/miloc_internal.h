@@ -231,8 +231,9 @@ hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes
 hipError_t launch_se(hipStream_t s, const SEArgs& a);
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a);
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a);
-// groups: lane groups of 16 (the persistent grid); the counter is cleared here.
-hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum);
-hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<double>& a, int groups, bool accum);
+// groups: lane groups (8 or 16 lanes) of the persistent grid, a multiple of
+// 256 / lanes; the work counter is cleared here.
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum, int lanes);
+hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<double>& a, int groups, bool accum, int lanes);
 
 }  // namespace miloc

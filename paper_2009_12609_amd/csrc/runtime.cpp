@@ -387,10 +387,11 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
     HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
     const size_t tsz = c->precision == MILOC_MARCH_FP64 ? sizeof(double) : sizeof(float);
     const size_t per_group = (size_t)std::max(1, c->oct_depth) * c->nch * tsz;
-    int64_t groups = (int64_t)prop.multiProcessorCount * 8 * 16;
-    groups = std::min<int64_t>(groups, std::max<int64_t>(16, (int64_t)((2ull << 30) / per_group)));
-    groups = std::min<int64_t>(groups, std::max<int64_t>(16, c->oct_trees * c->T));
-    groups = (groups + 15) / 16 * 16;
+    const int gpb = 256 / c->lanes;       // lane groups per 256-thread block
+    int64_t groups = (int64_t)prop.multiProcessorCount * 8 * gpb;
+    groups = std::min<int64_t>(groups, std::max<int64_t>(gpb, (int64_t)((2ull << 30) / per_group)));
+    groups = std::min<int64_t>(groups, std::max<int64_t>(gpb, c->oct_trees * c->T));
+    groups = (groups + gpb - 1) / gpb * gpb;
     c->oct_groups = (int)groups;
     HIPCHK(c, c->d_ostack.ensure((size_t)groups * per_group));
     HIPCHK(c, c->d_ocounter.ensure(sizeof(unsigned long long)));
@@ -422,7 +423,7 @@ miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, c
     a.counter = c->d_ocounter.as<unsigned long long>();
     a.stack = c->d_ostack.as<TT>();
     a.depth = accum ? c->oct_depth : 0;
-    HIPCHK(c, launch_march_oct(c->stream, a, groups, accum));
+    HIPCHK(c, launch_march_oct(c->stream, a, groups, accum, c->lanes));
     return MILOC_OK;
 }
 
@@ -470,12 +471,14 @@ miloc_status ensure_static(miloc_ctx* c)
     // one to three passes of the ray's lane group
     const double wmax = 2.0 * Kd * maxb / c->dv + 2.0;
     if (c->kind == 3)
-        c->lanes = wmax <= 32.0 ? 16 : (wmax <= 64.0 ? 32 : 64);
+        c->lanes = wmax <= 32.0 ? 8 : (wmax <= 64.0 ? 16 : 32);
+    else if (c->kind == 4)
+        c->lanes = 16;                    // octree: groups of 16 (8 measured slower), any window width
     else
-        c->lanes = 16;                    // octree and 1D marches: groups of 16, any window width
+        c->lanes = 16;                    // 1D: groups of 16, any window width
     if (const char* ev = std::getenv("MILOC_LANES")) {
         const int l = std::atoi(ev);
-        if ((c->kind == 1 && (l == 8 || l == 16 || l == 32 || l == 64)) ||
+        if ((c->kind == 1 && (l == 8 || l == 16 || l == 32 || l == 64)) || (c->kind == 4 && (l == 8 || l == 16)) ||
             (c->kind == 3 && (l == 8 || l == 16 || l == 32 || l == 64)))
             c->lanes = l;
     }
@@ -1265,7 +1268,8 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
                                       c->d_bD.as<double>(), c->dv, c->chalf,
                                       fp64 ? kWindowK64 : kWindowK32, c->nch, zwin.p, fp64));
         HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
-        const int groups = (int)std::min<int64_t>(c->oct_groups, ((int64_t)n_los + 15) / 16 * 16);
+        const int gpb = 256 / c->lanes;
+        const int groups = (int)std::min<int64_t>(c->oct_groups, ((int64_t)n_los + gpb - 1) / gpb * gpb);
         s = fp64 ? launch_oct<double>(c, 1, trans, false, out.as<double>(), steps, trees, (int64_t)S.trees.size(),
                                       zaw.as<double>(), zwin.p, groups, zlen.as<double>())
                  : launch_oct<float>(c, 1, trans, false, out.as<float>(), steps, trees, (int64_t)S.trees.size(),
