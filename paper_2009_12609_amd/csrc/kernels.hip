@@ -269,12 +269,52 @@ __device__ __forceinline__ double omb_any(double tau)
 // so that the profile is exp2(-x^2)), tau_j = kl e_j, emission el e_j beta_j.
 // Partial sums of this lane in sj, sl.  The series/exact choice for 1 - beta
 // is made once per step for the whole wavefront.
-template <int LANES, typename T>
+template <int LANES, typename T, bool THIN>
+__device__ __forceinline__ void channel_pair(T* __restrict__ row, int j, bool second, T x0, T ibs, T kl, T el,
+                                             T& sj, T& sl)
+{
+    // two channels, j and j + LANES: both LDS reads are issued before either
+    // update, which halves the dependent LDS round trips of a step
+    const T xa = (T)j * ibs + x0;
+    const T xb = (T)(j + LANES) * ibs + x0;
+    const T ia = row[j];
+    const T ib = second ? row[j + LANES] : (T)0;
+    const T ea = fast_exp2(-xa * xa);
+    const T eb = second ? fast_exp2(-xb * xb) : (T)0;
+    const T oa = THIN ? omb_thin(kl * ea) : omb_any(kl * ea);
+    const T ob = THIN ? omb_thin(kl * eb) : omb_any(kl * eb);
+    const T ua = ea - ea * oa;                 // e_c beta_c
+    const T ub = eb - eb * ob;
+    sj += ia * ua + ib * ub;
+    sl += ea * oa + eb * ob;
+    row[j] = ia + ua * (el - kl * ia);         // e^-tau = 1 - tau beta
+    if (second) row[j + LANES] = ib + ub * (el - kl * ib);
+}
+
+// The channel window of one step for one ray (Sect. 2: I e^-tau + S(1 -
+// e^-tau) per channel, absorbed counts and the diagonal operator summed):
+// channels clo .. clo + nwin - 1, profile argument x_j = x0 + j ibs (scaled
+// so that the profile is exp2(-x^2)), tau_j = kl e_j, emission el e_j beta_j.
+// Partial sums of this lane in sj, sl.  The series/exact choice for 1 - beta
+// is made once per step for the whole wavefront.
+template <int LANES, typename T, bool PAIRS = false>
 __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
                                                 T kl, T el, T& sj, T& sl)
 {
     const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
     T* __restrict__ row = I + clo;
+    if (PAIRS) {
+        // latency-bound callers (a few long rays in flight): two channels per
+        // pass, see channel_pair
+        if (thin) {
+            for (int j = lane; j < nwin; j += 2 * LANES)
+                channel_pair<LANES, T, true>(row, j, j + LANES < nwin, x0, ibs, kl, el, sj, sl);
+        } else {
+            for (int j = lane; j < nwin; j += 2 * LANES)
+                channel_pair<LANES, T, false>(row, j, j + LANES < nwin, x0, ibs, kl, el, sj, sl);
+        }
+        return;
+    }
     if (thin) {
         for (int j = lane; j < nwin; j += LANES) {
             const T xs = (T)j * ibs + x0;
@@ -474,6 +514,36 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
     *a = v;
 }
 
+// Per-cell sums of the octree march's per-step partial sums, one thread per
+// cell and all transitions of the launch: FP64 sums over the cell's steps
+// (listed by the host), written to the accumulators.
+template <typename T>
+__global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= p.nc) return;
+    const long long a = p.cell_off[k], b = p.cell_off[k + 1];
+    double2* acc = p.acc + (size_t)k * p.ntr_total + p.trans_offset;
+    // transitions in register tiles of four
+    for (int t0 = 0; t0 < p.ntr; t0 += 4) {
+        double sj[4] = {0.0, 0.0, 0.0, 0.0}, sl[4] = {0.0, 0.0, 0.0, 0.0};
+        for (long long i = a; i < b; ++i) {
+            const typename V2<T>::type* e = p.E + (size_t)p.cell_steps[i] * p.ntr + t0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (t0 + q < p.ntr) {
+                    const typename V2<T>::type v = e[q];
+                    sj[q] += (double)v.x;
+                    sl[q] += (double)v.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (t0 + q < p.ntr) acc[t0 + q] = make_double2(sj[q], sl[q]);
+    }
+}
+
 // ---------------------------------------------------------------- octree march
 // Persistent lane groups (8 or 16 lanes) take work units (one root line's rays for one
 // transition) from a global counter, largest units first.  Each unit replays
@@ -493,7 +563,12 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
     const int grp = threadIdx.x / LANES;
     const size_t gid = (size_t)blockIdx.x * (blockDim.x / LANES) + grp;
     extern __shared__ unsigned char smem_raw[];
+    using T2q = typename V2<T>::type;
     T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)grp * p.ich;
+    // per-step sums queued in LDS and written LANES at a time (plain stores,
+    // gathered per cell afterwards): no device atomics in the march
+    T2q* __restrict__ queue = reinterpret_cast<T2q*>(smem_raw + (size_t)(blockDim.x / LANES) * p.ich * sizeof(T)) +
+                              (size_t)grp * LANES;
     T* __restrict__ stk = p.stack + gid * (size_t)p.depth * p.ich;
     for (;;) {
         unsigned long long item = 0;
@@ -509,34 +584,49 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         const T aw = (T)p.aw[tr.q];
         const T Ibg = p.Ibg[t];
         const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
+        T2q* __restrict__ Et = p.E ? p.E + (size_t)tr.off * p.ntr + (t - p.trans_offset) : nullptr;
+        int qn = 0, qs0 = 0;
         int sp = -1;
-        // records arrive LANES at a time, one per lane, and are broadcast with
-        // shuffles; the next step's cell data are loaded before this step runs
-        uint2 mine = rec[lane < tr.n ? lane : 0];
-        double mine64 = (sizeof(T) == 8 && rec64) ? rec64[lane < tr.n ? lane : 0] : 0.0;
-        unsigned w0_n = __shfl(mine.x, 0, LANES);
-        T len_n = (T)__uint_as_float(__shfl(mine.y, 0, LANES));
-        if (sizeof(T) == 8 && rec64) len_n = (T)__shfl(mine64, 0, LANES);
-        T4 wv_n = win[w0_n & kOctCellMask];
-        T2 kv_n = ke[(size_t)(w0_n & kOctCellMask) * p.ntr_total];
+        // Records arrive LANES at a time, one per lane, and each lane also loads
+        // the window and {khat, ehat} of its record's cell: the cell data of a
+        // whole chunk are fetched in parallel instead of one dependent load per
+        // step (the cells of a ray's steps are scattered over the tree), then
+        // broadcast step by step with shuffles.
+        // The next chunk is loaded while the current one is processed.
+        uint2 mine, nx;
+        double mine64 = 0.0, nx64 = 0.0;
+        T4 mywv, nxwv{};
+        T2 mykv, nxkv{};
+        auto load_chunk = [&](int s0, uint2& r, double& r64, T4& wvv, T2& kvv) {
+            const int si = s0 + lane < tr.n ? s0 + lane : s0;
+            r = rec[si];
+            if (sizeof(T) == 8 && rec64) r64 = rec64[si];
+            const unsigned c = r.x & kOctCellMask;
+            wvv = win[c];
+            kvv = ke[(size_t)c * p.ntr_total];
+        };
+        load_chunk(0, mine, mine64, mywv, mykv);
+        if (LANES < tr.n) load_chunk(LANES, nx, nx64, nxwv, nxkv);
         for (int s = 0; s < tr.n; ++s) {
-            const unsigned w0 = w0_n;
-            const T len = len_n;
-            const T4 wv = wv_n;
-            const T2 kv = kv_n;
-            if (s + 1 < tr.n) {
-                const int k = (s + 1) & (LANES - 1);
-                if (k == 0) {
-                    const int si = s + 1 + lane < tr.n ? s + 1 + lane : s + 1;
-                    mine = rec[si];
-                    if (sizeof(T) == 8 && rec64) mine64 = rec64[si];
-                }
-                w0_n = __shfl(mine.x, k, LANES);
-                len_n = (T)__uint_as_float(__shfl(mine.y, k, LANES));
-                if (sizeof(T) == 8 && rec64) len_n = (T)__shfl(mine64, k, LANES);
-                wv_n = win[w0_n & kOctCellMask];
-                kv_n = ke[(size_t)(w0_n & kOctCellMask) * p.ntr_total];
+            const int k = s & (LANES - 1);
+            if (k == 0 && s > 0) {
+                mine = nx;
+                mine64 = nx64;
+                mywv = nxwv;
+                mykv = nxkv;
+                if (s + LANES < tr.n) load_chunk(s + LANES, nx, nx64, nxwv, nxkv);
             }
+            const unsigned w0 = __shfl(mine.x, k, LANES);
+            T len = (T)__uint_as_float(__shfl(mine.y, k, LANES));
+            if (sizeof(T) == 8 && rec64) len = (T)__shfl(mine64, k, LANES);
+            T4 wv;
+            wv.x = __shfl(mywv.x, k, LANES);
+            wv.y = __shfl(mywv.y, k, LANES);
+            wv.z = __shfl(mywv.z, k, LANES);
+            wv.w = __shfl(mywv.w, k, LANES);
+            T2 kv;
+            kv.x = __shfl(mykv.x, k, LANES);
+            kv.y = __shfl(mykv.y, k, LANES);
             const int cell = (int)(w0 & kOctCellMask);
             const unsigned mode = w0 >> kOctModeShift;
             if (mode == kOctModeBg) {
@@ -557,11 +647,26 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
-            window_channels<LANES, T>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
+            window_channels<LANES, T, true>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
-                if (lane == LANES - 1) {
+                if (Et) {
+                    if (lane == LANES - 1) {
+                        const T wgt = aw * len;
+                        T2q v;
+                        v.x = wgt * sj;
+                        v.y = wgt * sl;
+                        queue[qn] = v;
+                    }
+                    ++qn;
+                    __builtin_amdgcn_wave_barrier();
+                    if (qn == LANES || s == tr.n - 1) {
+                        if (lane < qn) Et[(size_t)(qs0 + lane) * p.ntr] = queue[lane];
+                        qs0 += qn;
+                        qn = 0;
+                    }
+                } else if (lane == LANES - 1) {
                     const double wgt = (double)(aw * len);
                     double2* a = p.acc + (size_t)cell * p.ntr_total + t;
                     unsafeAtomicAdd(&a->x, wgt * (double)sj);
@@ -1150,7 +1255,8 @@ hipError_t do_march_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, boo
 {
     constexpr int kGroupsPerBlock = 256 / LANES;
     const int blocks = (groups + kGroupsPerBlock - 1) / kGroupsPerBlock;
-    const size_t shm = (size_t)kGroupsPerBlock * a.ich * sizeof(T);
+    const size_t shm = (size_t)kGroupsPerBlock * a.ich * sizeof(T) +
+                       (size_t)kGroupsPerBlock * LANES * sizeof(typename V2<T>::type);
     if (shm > 64 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(a.counter, 0, sizeof(unsigned long long), s);
     if (e != hipSuccess) return e;
@@ -1166,6 +1272,16 @@ hipError_t dispatch_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, boo
 {
     return lanes == 8 ? do_march_oct<T, 8>(s, a, groups, accum) : do_march_oct<T, 16>(s, a, groups, accum);
 }
+
+template <typename T>
+hipError_t do_gather_oct(hipStream_t s, const GatherOctArgs<T>& a)
+{
+    const long long blocks = (a.nc + 255) / 256;
+    hipLaunchKernelGGL(gather_oct_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_gather_oct(hipStream_t s, const GatherOctArgs<float>& a) { return do_gather_oct(s, a); }
+hipError_t launch_gather_oct(hipStream_t s, const GatherOctArgs<double>& a) { return do_gather_oct(s, a); }
 
 hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum, int lanes)
 {

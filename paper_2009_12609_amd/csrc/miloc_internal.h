@@ -176,6 +176,17 @@ constexpr uint32_t kOctModeBg = 1;             //   background (ray start or sid
 constexpr uint32_t kOctModePeek = 2;           //   copy of the top saved vector
 constexpr uint32_t kOctModePop = 3;            //   copy of the top saved vector, then drop it
 
+// Per-cell sums of the octree march's per-step partial sums.
+template <typename T>
+struct GatherOctArgs {
+    long long nc;
+    int ntr, trans_offset, ntr_total;
+    const long long* cell_off;           // [nc + 1]
+    const unsigned* cell_steps;          // step indices grouped by cell
+    const typename V2<T>::type* E;       // [step][ntr]
+    double2* acc;                        // [nc][ntr_total]
+};
+
 // One work unit: every ray one root line gives rise to, in processing order.
 struct OctTreeRec {
     int64_t off;     // first step record
@@ -197,7 +208,8 @@ struct OctMarchArgs {
     const typename V4<T>::type* win;     // [n_dir][nc]
     const typename V2<T>::type* ke;      // [nc][ntr_total]
     const T* Ibg;                        // [ntr_total]
-    double2* acc;                        // [nc][ntr_total] {J, Lambda} raw sums
+    double2* acc;                        // [nc][ntr_total] {J, Lambda} raw sums (when E is null)
+    typename V2<T>::type* E;             // per-step sums [step][ntr] of this launch, or null
     T* Iout;                             // no accumulation: [trees][nch] leaving intensity
     unsigned long long* counter;         // work counter, zero at launch
     T* stack;                            // [groups][depth][ich] saved vectors
@@ -235,5 +247,7 @@ hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a);
 // 256 / lanes; the work counter is cleared here.
 hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<float>& a, int groups, bool accum, int lanes);
 hipError_t launch_march_oct(hipStream_t s, const OctMarchArgs<double>& a, int groups, bool accum, int lanes);
+hipError_t launch_gather_oct(hipStream_t s, const GatherOctArgs<float>& a);
+hipError_t launch_gather_oct(hipStream_t s, const GatherOctArgs<double>& a);
 
 }  // namespace miloc

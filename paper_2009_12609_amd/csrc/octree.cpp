@@ -46,6 +46,7 @@
 #include "octree.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <thread>
@@ -355,7 +356,7 @@ bool DirTracer::tree(int i, int j, bool plain, std::vector<uint32_t>& rec, std::
 }  // namespace
 
 std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, bool plain, int n_threads,
-                            OctSchedule& out, bool want_len64)
+                            OctSchedule& out, bool want_len64, int64_t n_cells)
 {
     const int nd = (int)dirs.size() / 3;
     const int N = M.N;
@@ -424,6 +425,31 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
     out.n_steps = total;
     std::stable_sort(out.trees.begin(), out.trees.end(),
                      [](const OctTreeRec& a, const OctTreeRec& b) { return a.n > b.n; });
+    out.cell_off.clear();
+    out.cell_steps.clear();
+    if (n_cells > 0) {
+        if (total > (int64_t)UINT32_MAX) return "octree: more than 2^32 steps";
+        // counting sort of the steps by cell; each thread fills a contiguous
+        // range of steps through per-cell atomic cursors
+        std::vector<int64_t>& off = out.cell_off;
+        off.assign(n_cells + 1, 0);
+        for (int64_t i = 0; i < total; ++i) ++off[(out.rec[2 * i] & kOctCellMask) + 1];
+        for (int64_t k = 0; k < n_cells; ++k) off[k + 1] += off[k];
+        out.cell_steps.resize(total);
+        std::vector<std::atomic<int64_t>> cur(n_cells);
+        for (int64_t k = 0; k < n_cells; ++k) cur[k].store(off[k], std::memory_order_relaxed);
+        std::vector<std::thread> fill;
+        const int nf = std::max(1, n_threads);
+        for (int w = 0; w < nf; ++w)
+            fill.emplace_back([&, w]() {
+                const int64_t a = total * w / nf, b = total * (w + 1) / nf;
+                for (int64_t i = a; i < b; ++i) {
+                    const uint32_t c = out.rec[2 * i] & kOctCellMask;
+                    out.cell_steps[cur[c].fetch_add(1, std::memory_order_relaxed)] = (uint32_t)i;
+                }
+            });
+        for (auto& t : fill) t.join();
+    }
     return std::string();
 }
 

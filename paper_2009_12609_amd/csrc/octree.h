@@ -30,6 +30,8 @@ std::string octree_from_levels(int N, int n_levels, const int64_t* n_cells_per_l
 struct OctSchedule {
     std::vector<uint32_t> rec;        // 2 words per step
     std::vector<double> len64;        // FP64 step lengths (only when asked for)
+    std::vector<int64_t> cell_off;    // per cell: first entry of its steps in cell_steps (+ total)
+    std::vector<uint32_t> cell_steps; // step indices grouped by cell (only when asked for)
     std::vector<OctTreeRec> trees;
     int max_depth = 0;
     int64_t n_steps = 0;
@@ -40,8 +42,10 @@ struct OctSchedule {
 // traces single lines (no new rays, no termination: lines of sight).  Trees
 // are ordered by decreasing length.  Uses up to n_threads host threads.
 // want_len64 also keeps the FP64 step lengths (for the FP64 march).
+// n_cells > 0 also lists, per cell, the steps that cross it (at most 2^32
+// steps in all).
 // Returns an empty string on success, else the reason.
 std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, bool plain, int n_threads,
-                            OctSchedule& out, bool want_len64 = false);
+                            OctSchedule& out, bool want_len64 = false, int64_t n_cells = 0);
 
 }  // namespace miloc

@@ -106,7 +106,7 @@ struct miloc_ctx {
     bool has_rad = false;
     DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
         d_zero, d_dirs, d_steps, d_flags, d_R, d_vrdv, d_area, d_vel, d_bD, d_win, d_lstart, d_moves,
-        d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter, d_1steps, d_1off, d_1kmin;
+        d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter, d_ocell_off, d_ocell_steps, d_oE, d_1steps, d_1off, d_1kmin;
     int64_t oct_trees = 0;
     int oct_depth = 0, oct_groups = 0;
     int64_t total_steps = 0;
@@ -345,8 +345,26 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
     const int nd = (int)c->dirs.size() / 3;
     OctSchedule S;
     const bool fp64 = c->precision == MILOC_MARCH_FP64;
-    const std::string e = octree_schedule(c->oct, c->dirs, false, host_threads(), S, fp64);
+    const std::string e = octree_schedule(c->oct, c->dirs, false, host_threads(), S, fp64, c->nc);
     if (!e.empty()) return fail(c, MILOC_EINVAL, e);
+    HIPCHK(c, c->d_ocell_off.ensure(S.cell_off.size() * sizeof(int64_t)));
+    HIPCHK(c, hipMemcpy(c->d_ocell_off.p, S.cell_off.data(), S.cell_off.size() * sizeof(int64_t),
+                        hipMemcpyHostToDevice));
+    HIPCHK(c, c->d_ocell_steps.ensure(std::max<size_t>(1, S.cell_steps.size()) * sizeof(uint32_t)));
+    HIPCHK(c, hipMemcpy(c->d_ocell_steps.p, S.cell_steps.data(), S.cell_steps.size() * sizeof(uint32_t),
+                        hipMemcpyHostToDevice));
+    std::vector<uint32_t>().swap(S.cell_steps);
+    // per-step sums: as many transitions per launch as fit the budget
+    {
+        // a launch lasts at least as long as its longest tree, so all
+        // transitions go in one launch when they fit
+        double budget_gb = 160.0;
+        if (const char* ev = std::getenv("MILOC_STEP_BUFFER_GB")) budget_gb = std::atof(ev);
+        const size_t per_t = (size_t)std::max<int64_t>(1, S.n_steps) * 2 * (fp64 ? sizeof(double) : sizeof(float));
+        const int tc = (int)std::min<double>((double)c->T, std::floor(budget_gb * 1e9 / (double)per_t));
+        c->trans_chunk = tc < 1 ? 1 : tc;
+        HIPCHK(c, c->d_oE.ensure(per_t * c->trans_chunk));
+    }
     if (fp64) {
         HIPCHK(c, c->d_olen64.ensure(std::max<size_t>(1, S.len64.size()) * sizeof(double)));
         HIPCHK(c, hipMemcpy(c->d_olen64.p, S.len64.data(), S.len64.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -419,6 +437,7 @@ miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, c
     a.ke = c->d_ke.as<typename V2<TT>::type>();
     a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
     a.acc = c->d_acc.as<double2>();
+    a.E = accum ? c->d_oE.as<typename V2<TT>::type>() : nullptr;
     a.Iout = Iout;
     a.counter = c->d_ocounter.as<unsigned long long>();
     a.stack = c->d_ostack.as<TT>();
@@ -1106,15 +1125,36 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
                 c->ctr.march_launches += 1;
             }
         } else if (c->kind == 4) {
-            s = fp64 ? launch_oct<double>(c, c->T, 0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
-                                          c->d_oaw.as<double>(), c->d_win.p, c->oct_groups, c->d_olen64.as<double>())
-                     : launch_oct<float>(c, c->T, 0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
-                                         c->d_oaw.as<double>(), c->d_win.p, c->oct_groups, nullptr);
-            if (s) return s;
-            HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
-            HIPCHK(c, hipEventSynchronize(c->ev[4]));
-            HIPCHK(c, hipEventElapsedTime(&t_march, c->ev[1], c->ev[4]));
-            c->ctr.march_launches += 1;
+            for (int t0 = 0; t0 < c->T; t0 += c->trans_chunk) {
+                const int nt = std::min(c->trans_chunk, c->T - t0);
+                if (t0 > 0) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+                s = fp64 ? launch_oct<double>(c, nt, t0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
+                                              c->d_oaw.as<double>(), c->d_win.p, c->oct_groups,
+                                              c->d_olen64.as<double>())
+                         : launch_oct<float>(c, nt, t0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
+                                             c->d_oaw.as<double>(), c->d_win.p, c->oct_groups, nullptr);
+                if (s) return s;
+                HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+                if (fp64) {
+                    GatherOctArgs<double> g{c->nc, nt, t0, c->T, c->d_ocell_off.as<long long>(),
+                                            c->d_ocell_steps.as<unsigned>(), c->d_oE.as<double2>(),
+                                            c->d_acc.as<double2>()};
+                    HIPCHK(c, launch_gather_oct(c->stream, g));
+                } else {
+                    GatherOctArgs<float> g{c->nc, nt, t0, c->T, c->d_ocell_off.as<long long>(),
+                                           c->d_ocell_steps.as<unsigned>(), c->d_oE.as<float2>(),
+                                           c->d_acc.as<double2>()};
+                    HIPCHK(c, launch_gather_oct(c->stream, g));
+                }
+                HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
+                HIPCHK(c, hipEventSynchronize(c->ev[5]));
+                float a = 0, b = 0;
+                HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[4]));
+                HIPCHK(c, hipEventElapsedTime(&b, c->ev[4], c->ev[5]));
+                t_march += a;
+                t_gather += b;
+                c->ctr.march_launches += 1;
+            }
         } else {
             s = fp64 ? launch_march<double>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
                      : launch_march<float>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
