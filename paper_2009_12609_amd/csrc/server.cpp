@@ -235,18 +235,13 @@ struct Request::Staging {
     std::vector<float> ibf;
 };
 
-// Admission, first half: host-side statics of a request, uploads into its
-// arena block, device-side ray steps and shell volumes, W back to the host.
-// Everything is queued on the server stream; the host copies live in
-// r->stage until the caller has synchronised.  False with r->error set on
-// failure.
-bool admit_stage1(miloc_server* S, Request* r)
+// Admission, host part: the statics of a request (molecule table, ray layout,
+// LTE start, per-shell values) in r->stage; independent per request.  False
+// with r->error set on failure.
+bool admit_host(Request* r)
 {
-    const Layout lay = layout_of(*r);
     r->stage = std::make_shared<Request::Staging>();
     Request::Staging& G = *r->stage;
-    char* base = static_cast<char*>(S->arena_mem) + r->off;
-    auto dptr = [&](size_t o) { return static_cast<void*>(base + o); };
     // molecule
     MolDev& m = G.m;
     std::memset(&m, 0, sizeof(m));
@@ -324,6 +319,30 @@ bool admit_stage1(miloc_server* S, Request* r)
         r->Ibg[t] = std::isfinite(xx) ? 1.0 / std::expm1(xx) : 0.0;
         ibf[t] = (float)r->Ibg[t];
     }
+    return true;
+}
+
+// Admission, first device part: uploads into the request's arena block,
+// device-side ray steps and shell volumes, W back to the host -- all queued on
+// the server stream; r->stage lives until the caller has synchronised.
+bool admit_stage1(miloc_server* S, Request* r)
+{
+    const Layout lay = layout_of(*r);
+    char* base = static_cast<char*>(S->arena_mem) + r->off;
+    auto dptr = [&](size_t o) { return static_cast<void*>(base + o); };
+    Request::Staging& G = *r->stage;
+    const int n = r->n;
+    const MolDev& m = G.m;
+    const std::vector<double>& Rn = G.Rn;
+    const std::vector<double>& an = G.an;
+    const std::vector<double>& nmolLb = G.nmolLb;
+    const std::vector<double>& xs = G.xs;
+    const std::vector<double>& b_all = G.b_all;
+    const std::vector<int64_t>& roff = G.roff;
+    const std::vector<int>& kmin = G.kmin;
+    const std::vector<double>& vrdv = G.vrdv;
+    const std::vector<float2>& sv = G.sv;
+    const std::vector<float>& ibf = G.ibf;
     struct Up { size_t o; const void* src; size_t bytes; };
     const Up ups[] = {
         {lay.mol, &m, sizeof(MolDev)},
@@ -522,9 +541,22 @@ void worker_loop(miloc_server* S)
                 S->active[r->slot] = nullptr;
                 S->stats.failed++;
             };
+            // host statics of all new requests in parallel, then the uploads
+            std::vector<char> host_ok(to_admit.size(), 0);
+            {
+                const size_t nw = std::min<size_t>(to_admit.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+                std::vector<std::thread> pool;
+                std::atomic<size_t> next{0};
+                for (size_t w = 0; w < nw; ++w)
+                    pool.emplace_back([&]() {
+                        for (size_t i = next++; i < to_admit.size(); i = next++) host_ok[i] = admit_host(to_admit[i]) ? 1 : 0;
+                    });
+                for (auto& t : pool) t.join();
+            }
             std::vector<Request*> staged;
-            for (Request* r : to_admit) {
-                if (admit_stage1(S, r)) staged.push_back(r);
+            for (size_t i = 0; i < to_admit.size(); ++i) {
+                Request* r = to_admit[i];
+                if (host_ok[i] && admit_stage1(S, r)) staged.push_back(r);
                 else fail_admission(r);
             }
             bool ok = hipStreamSynchronize(S->stream) == hipSuccess;
