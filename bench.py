@@ -13,7 +13,12 @@ Prints one JSON line.  ``value`` = nominal ray-cell-channel updates per second
 of the whole timed region (every channel counted, including those outside
 each step's profile window).  ``roofline`` describes the dominant kernel (the
 3D march) from its HIP-event durations; ``cpu_baseline`` is the FP64 oracle
-timed on this host's cores on a bounded sample of the same workload.
+timed on this host's cores on a bounded sample of the same workload.  Two more
+objects by default: ``octree`` (64^3 root refined four levels, 2 timed ALI
+iterations, same per-step measures) and ``serving`` (a 192-request 1D stream:
+model solves/s with all requests queued at once, p50/p99 latency under Poisson
+arrivals at 0.5x and 0.8x of that rate, and the same requests solved one at a
+time through a single-model context).
 """
 import argparse
 import hashlib
@@ -135,7 +140,9 @@ def octree_bench(steps=2, warmup=1):
     launches = max(1, cnt["march_launches"])
     march_ms = cnt["march_ms"] / launches
     steps_per_launch = cnt["ray_steps"] / launches
-    achieved = steps_per_launch * OCT_BYTES_PER_STEP / (march_ms * 1e-3) / 1e9
+    hbm_gbs = steps_per_launch * OCT_BYTES_PER_STEP / (march_ms * 1e-3) / 1e9
+    nwin = mean_window_channels(w)
+    achieved = steps_per_launch * nwin * FLOPS_PER_CHANNEL / (march_ms * 1e-3) / 1e12
     return {
         "metric": "ray-cell-channel updates/s (3D octree)",
         "value": cnt["channel_updates"] / elapsed,
@@ -149,9 +156,12 @@ def octree_bench(steps=2, warmup=1):
         "solve_ms_per_step": cnt["solve_ms"] / max(1, cnt["iterations"]),
         "setup_s": t_setup,
         "generate_s": t_gen,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "march_oct_kernel<float,true>", "bytes_per_step": OCT_BYTES_PER_STEP},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": f"march_oct_kernel<float,{cnt['march_lanes']},true>",
+                     "flops_per_channel_update": FLOPS_PER_CHANNEL, "window_channels_mean": nwin,
+                     "hbm_algorithmic_gbs": hbm_gbs, "hbm_algorithmic_frac": hbm_gbs / HBM_PEAK_GBS,
+                     "bytes_per_step": OCT_BYTES_PER_STEP},
     }
 
 
@@ -160,7 +170,7 @@ def _pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
-def serve_bench(n_req=48, seed=5001, tol=1e-6, max_iter=500):
+def serve_bench(n_req=192, seed=5001, tol=1e-6, max_iter=500):
     """1D request stream (50-2000 shells, 2/5/10/20 levels, 64/128/256
     channels): model solves/s with every request queued at once (arrival rate
     far above capacity), p50/p99 latency at 0.5x and 0.8x of that capacity
@@ -261,10 +271,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128, help="grid size (128 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", type=int, default=0, metavar="N_REQ",
-                    help="also run the 1D request stream with N_REQ requests (adds a 'serving' object)")
-    ap.add_argument("--octree", type=int, default=0, metavar="STEPS",
-                    help="also time STEPS iterations of the octree workload (adds an 'octree' object)")
+    ap.add_argument("--serve", type=int, default=192, metavar="N_REQ",
+                    help="run the 1D request stream with N_REQ requests ('serving' object; 0 = skip)")
+    ap.add_argument("--octree", type=int, default=2, metavar="STEPS",
+                    help="time STEPS iterations of the octree workload ('octree' object; 0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()

@@ -842,26 +842,32 @@ __global__ __launch_bounds__(256) void ray_steps_kernel(int n, const double* __r
     }
 }
 
-// Ray-sampled shell volumes W_k = sum_j a_j (path of ray j in shell k), one
-// thread per shell: a ray with b_j < R_{k-1} crosses shell k twice, one with
-// R_{k-1} <= b_j < R_k has it as its tangent shell (full chord).
+// Ray-sampled shell volumes W_k = sum_j a_j (path of ray j in shell k): a ray
+// with b_j < R_{k-1} crosses shell k twice, one with R_{k-1} <= b_j < R_k has
+// it as its tangent shell (full chord).  With bsq given, the output is
+// q_k = dv / (bsq_k W_k) instead (0 where W_k = 0).
 __global__ __launch_bounds__(256) void shell_weights_kernel(int n, const double* __restrict__ R, int nrays,
                                                             const double* __restrict__ b,
                                                             const double* __restrict__ area,
-                                                            double* __restrict__ W)
+                                                            const double* __restrict__ bsq, double dv,
+                                                            double* __restrict__ out)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wavefront per shell, its lanes over the rays; the lane sums are
+    // combined in a fixed order, so W does not depend on the launch
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (k >= n) return;
     const double ro = R[k], ri = k > 0 ? R[k - 1] : 0.0;
     double w = 0.0;
-    for (int j = 0; j < nrays; ++j) {
+    for (int j = lane; j < nrays; j += 64) {
         const double bj = b[j];
         if (!(ro > bj)) continue;
         const double zo = sqrt((ro - bj) * (ro + bj));
         const double zi = ri > bj ? sqrt((ri - bj) * (ri + bj)) : 0.0;
         w += area[j] * 2.0 * (zo - zi);
     }
-    W[k] = w;
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+    if (lane == 0) out[k] = bsq ? (w > 0 ? dv / (bsq[k] * w) : 0.0) : w;
 }
 
 template <typename T, int LANES, bool ACCUM>
@@ -1212,9 +1218,10 @@ hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes
     return dispatch3d<double>(s, a, lanes, accum, max_steps);
 }
 hipError_t launch_shell_weights(hipStream_t s, int n, const double* R, int nrays, const double* b,
-                                const double* area, double* W)
+                                const double* area, double* W, const double* bsq, double dv)
 {
-    hipLaunchKernelGGL(shell_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, R, nrays, b, area, W);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shell_weights_kernel, dim3((n + 3) / 4), dim3(256), 0, s, n, R, nrays, b, area, bsq, dv, W);
     return hipGetLastError();
 }
 

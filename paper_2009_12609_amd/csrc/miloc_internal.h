@@ -231,9 +231,10 @@ hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes,
                           int max_steps);
 hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum,
                           int max_steps);
-// W_k = sum_j area_j * (path of ray j in shell k), normalised units.
+// W_k = sum_j area_j * (path of ray j in shell k), normalised units; with
+// bsq set, q_k = dv / (bsq_k W_k) is written instead of W_k.
 hipError_t launch_shell_weights(hipStream_t s, int n, const double* R, int nrays, const double* b,
-                                const double* area, double* W);
+                                const double* area, double* W, const double* bsq = nullptr, double dv = 0.0);
 // Step records of 1D rays (see ray_steps_kernel); R, b normalised to R_out,
 // off[j] = first record of ray j, kmin[j] its innermost shell.
 hipError_t launch_ray_steps(hipStream_t s, int n, const double* R, int nrays, const double* b, const int* kmin,

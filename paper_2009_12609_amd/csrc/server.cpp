@@ -48,6 +48,23 @@ constexpr int kMaxServeChannels = 512;
 constexpr int kMaxServeLevels = 20;
 constexpr int kRaysPerBlock = 16;          // 16 lanes per ray, 256 threads
 constexpr int kSeBs = 16;
+constexpr size_t kStageBytes = (size_t)64 << 20;   // pinned admission staging per round
+constexpr size_t kResBytes = (size_t)64 << 20;     // pinned result area per tick
+constexpr size_t kNoRes = ~(size_t)0;
+// LDS tiers of the tick's march kernel (one captured graph each): the largest
+// holds the per-shell accumulators of 2048 shells and 16 rays of 512
+// channels; the smaller ones let more workgroups share a CU (160 KB of LDS)
+// when the resident models are smaller.
+constexpr int kLdsTiers = 5;
+constexpr int kTierLds[kLdsTiers] = {20480, 27136, 32768, 40960, 49152};
+
+// LDS bytes the tick's march kernel needs for one resident model.
+constexpr int march_lds_need(int n, int nch)
+{
+    return (int)((((size_t)n * 2 * sizeof(float)) + 15) & ~(size_t)15) + kRaysPerBlock * nch * (int)sizeof(float);
+}
+static_assert(march_lds_need(kMaxServeShells, kMaxServeChannels) <= kTierLds[kLdsTiers - 1],
+              "the largest LDS tier must hold the largest served model");
 
 double now_s()
 {
@@ -127,17 +144,18 @@ struct Request {
     int slot = -1;
     ServeModel desc{};
     int phase = 0;              // 0: iterating, 1: spectra in the next tick, then retired
-    std::vector<float> sp_host; // spectra copied back after the spectra tick
-    struct Staging;             // host copies of an admission in flight
-    std::shared_ptr<Staging> stage;
+    std::vector<float> sp_host; // spectra copied back after the spectra tick (no room in the pinned area)
+    size_t res_off = 0;         // offset of its results in the pinned result area, or kNoRes
     std::vector<double> Iscale, Ibg;
     // results
     std::vector<double> x, spectra;
 };
 
+// Arena block of one request: the regions filled from the host come first
+// (one upload of [0, up_end)), then those the kernels fill.
 struct Layout {
-    size_t mol, steps, roff, kmin, R, b, vrdv, area, shellv, ke, acc, x, xn, nH2, Tk, q, nmolLb, Ibg, Ibg64, spec,
-        total;
+    size_t mol, roff, kmin, R, b, vrdv, area, shellv, x, nH2, Tk, nmolLb, Ibg, Ibg64, bsq, up_end;
+    size_t steps, ke, acc, xn, q, spec, total;
 };
 
 Layout layout_of(const Request& r)
@@ -146,7 +164,6 @@ Layout layout_of(const Request& r)
     size_t o = 0;
     auto take = [&](size_t n) { const size_t at = o; o += (n + 255) & ~(size_t)255; return at; };
     l.mol = take(sizeof(MolDev));
-    l.steps = take((size_t)r.n_steps * sizeof(float2));
     l.roff = take((size_t)(r.nrays + 1) * sizeof(int64_t));
     l.kmin = take((size_t)(r.nrays + 1) * sizeof(int));
     l.R = take(r.n * sizeof(double));
@@ -154,19 +171,28 @@ Layout layout_of(const Request& r)
     l.vrdv = take(r.n * sizeof(double));
     l.area = take(r.nrays * sizeof(double));
     l.shellv = take(r.n * sizeof(float2));
-    l.ke = take((size_t)r.n * r.T * sizeof(float2));
-    l.acc = take((size_t)r.n * r.T * sizeof(double2));
     l.x = take((size_t)r.n * r.L * sizeof(double));
-    l.xn = take((size_t)r.n * r.L * sizeof(double));
     l.nH2 = take(r.n * sizeof(double));
     l.Tk = take(r.n * sizeof(double));
-    l.q = take(r.n * sizeof(double));
     l.nmolLb = take(r.n * sizeof(double));
     l.Ibg = take(r.T * sizeof(float));
     l.Ibg64 = take(r.T * sizeof(double));
+    l.bsq = take(r.n * sizeof(double));
+    l.up_end = o;
+    l.steps = take((size_t)r.n_steps * sizeof(float2));
+    l.ke = take((size_t)r.n * r.T * sizeof(float2));
+    l.acc = take((size_t)r.n * r.T * sizeof(double2));
+    l.xn = take((size_t)r.n * r.L * sizeof(double));
+    l.q = take(r.n * sizeof(double));
     l.spec = take((size_t)r.T * r.nch * sizeof(float));
     l.total = o;
     return l;
+}
+
+// Bytes of a request's results in the pinned result area (spectra, populations).
+size_t result_bytes(const Request& r)
+{
+    return (((size_t)r.T * r.nch * sizeof(float) + 255) & ~(size_t)255) + (size_t)r.n * r.L * sizeof(double);
 }
 
 bool finite_pos(const double* a, int n, bool allow_zero)
@@ -198,9 +224,15 @@ struct miloc_server {
     unsigned long long* d_flags = nullptr;   // per slot: delta bits, bad
     size_t cap_march = 0, cap_cell = 0, cap_se = 0;
     ServeGrid grid{};
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph[kLdsTiers] = {};
+    hipGraphExec_t graph_exec[kLdsTiers] = {};
+    int tier = kLdsTiers - 1;            // LDS tier of the current resident set
     float* d_zero = nullptr;
+    // pinned host areas: admission uploads, results of retiring models
+    char* h_stage = nullptr;
+    size_t stage_cap = 0;
+    char* h_res = nullptr;
+    size_t res_cap = 0;
 
     std::mutex mu;
     std::mutex err_mu;                   // guards err (set from caller and worker threads)
@@ -226,24 +258,15 @@ miloc_status sfail(miloc_server* s, miloc_status code, const std::string& m)
     return code;
 }
 
-struct Request::Staging {
-    MolDev m;
-    std::vector<double> Rn, bn, an, W, q, nmolLb, xs, b_all, vrdv, bsq;
-    std::vector<int64_t> roff;
-    std::vector<int> kmin;
-    std::vector<float2> sv;
-    std::vector<float> ibf;
-};
-
 // Admission, host part: the statics of a request (molecule table, ray layout,
-// LTE start, per-shell values) in r->stage; independent per request.  False
-// with r->error set on failure.
-bool admit_host(Request* r)
+// LTE start, per-shell values) written at their arena offsets into img, the
+// host image of the block's first up_end bytes; independent per request.
+// False with r->error set on failure.
+bool admit_host(Request* r, char* img)
 {
-    r->stage = std::make_shared<Request::Staging>();
-    Request::Staging& G = *r->stage;
+    const Layout lay = layout_of(*r);
     // molecule
-    MolDev& m = G.m;
+    MolDev m;
     std::memset(&m, 0, sizeof(m));
     m.L = r->L;
     m.T = r->T;
@@ -258,47 +281,39 @@ bool admit_host(Request* r)
         m.gratio[t] = r->g[r->up[t]] / r->g[r->lo[t]];
         m.Ct[t] = kC * kC * kC * r->A[t] / (8.0 * kPi * r->nu[t] * r->nu[t] * r->nu[t]);
     }
-    // geometry and per-shell statics
+    std::memcpy(img + lay.mol, &m, sizeof(m));
+    // geometry and per-shell statics, in normalised radius units
     const int n = r->n;
     const double Rout = r->R[n - 1];
-    std::vector<double>& Rn = G.Rn;
-    std::vector<double>& bn = G.bn;
-    std::vector<double>& an = G.an;
-    std::vector<double>& nmolLb = G.nmolLb;
-    std::vector<double>& xs = G.xs;
-    Rn.resize(n);
-    bn.resize(r->nrays);
-    an.resize(r->nrays);
-    nmolLb.resize(n);
-    xs.resize((size_t)n * r->L);
-    G.W.resize(n);
+    double* Rn = reinterpret_cast<double*>(img + lay.R);
+    double* b_all = reinterpret_cast<double*>(img + lay.b);   // the rays' impacts, then the centre line of sight
+    double* an = reinterpret_cast<double*>(img + lay.area);
     for (int k = 0; k < n; ++k) Rn[k] = r->R[k] / Rout;
     Rn[n - 1] = 1.0;
-    for (int j = 0; j < r->nrays; ++j) bn[j] = r->impact[j] / Rout;
+    for (int j = 0; j < r->nrays; ++j) b_all[j] = r->impact[j] / Rout;
+    b_all[r->nrays] = 0.0;
     for (int j = 0; j < r->nrays; ++j) {
-        const double e0 = j == 0 ? 0.0 : 0.5 * (bn[j] + bn[j - 1]);
-        const double e1 = j == r->nrays - 1 ? 1.0 : 0.5 * (bn[j] + bn[j + 1]);
+        const double e0 = j == 0 ? 0.0 : 0.5 * (b_all[j] + b_all[j - 1]);
+        const double e1 = j == r->nrays - 1 ? 1.0 : 0.5 * (b_all[j] + b_all[j + 1]);
         an[j] = kPi * (e1 * e1 - e0 * e0);
     }
     // ray layout of the model's rays and of the centre line of sight (spectra);
-    // the step records themselves are computed on the device below
-    std::vector<double>& b_all = G.b_all;
-    b_all = bn;
-    b_all.push_back(0.0);
-    std::vector<int64_t>& roff = G.roff;
-    std::vector<int>& kmin = G.kmin;
-    if (shell_ray_layout(n, Rn.data(), (int)b_all.size(), b_all.data(), roff, kmin) != r->n_steps) {
+    // the step records themselves are computed on the device
+    std::vector<int64_t> roff;
+    std::vector<int> kmin;
+    if (shell_ray_layout(n, Rn, r->nrays + 1, b_all, roff, kmin) != r->n_steps) {
         r->error = "ray step count mismatch";
         return false;
     }
-    std::vector<double>& vrdv = G.vrdv;
-    vrdv.resize(n);
-    for (int k = 0; k < n; ++k) vrdv[k] = r->vr[k] / r->dv;
-    std::vector<float2>& sv = G.sv;
-    sv.resize(n);
-    std::vector<double>& bsq = G.bsq;
-    bsq.resize(n);
+    std::memcpy(img + lay.roff, roff.data(), roff.size() * sizeof(int64_t));
+    std::memcpy(img + lay.kmin, kmin.data(), kmin.size() * sizeof(int));
+    double* vrdv = reinterpret_cast<double*>(img + lay.vrdv);
+    float2* sv = reinterpret_cast<float2*>(img + lay.shellv);
+    double* xs = reinterpret_cast<double*>(img + lay.x);
+    double* nmolLb = reinterpret_cast<double*>(img + lay.nmolLb);
+    double* bsq = reinterpret_cast<double*>(img + lay.bsq);
     for (int k = 0; k < n; ++k) {
+        vrdv[k] = r->vr[k] / r->dv;
         const double b = std::sqrt(2.0 * kK * r->Tk[k] / (r->mass * kAmu) + r->bt[k] * r->bt[k]);
         const double bs = b * std::sqrt(kPi);
         bsq[k] = bs;
@@ -309,95 +324,44 @@ bool admit_host(Request* r)
         for (int i = 0; i < r->L; ++i) z += m.g[i] * std::exp(-m.E[i] / r->Tk[k]);
         for (int i = 0; i < r->L; ++i) xs[(size_t)k * r->L + i] = m.g[i] * std::exp(-m.E[i] / r->Tk[k]) / z;
     }
+    std::memcpy(img + lay.nH2, r->nH2.data(), n * sizeof(double));
+    std::memcpy(img + lay.Tk, r->Tk.data(), n * sizeof(double));
     r->Iscale.resize(r->T);
     r->Ibg.resize(r->T);
-    std::vector<float>& ibf = G.ibf;
-    ibf.resize(r->T);
+    float* ibf = reinterpret_cast<float*>(img + lay.Ibg);
     for (int t = 0; t < r->T; ++t) {
         r->Iscale[t] = 2.0 * kH * std::pow(r->nu[t], 3) / (kC * kC);
         const double xx = r->Tbg > 0 ? kH * r->nu[t] / (kK * r->Tbg) : INFINITY;
         r->Ibg[t] = std::isfinite(xx) ? 1.0 / std::expm1(xx) : 0.0;
         ibf[t] = (float)r->Ibg[t];
     }
+    std::memcpy(img + lay.Ibg64, r->Ibg.data(), r->T * sizeof(double));
     return true;
 }
 
-// Admission, first device part: uploads into the request's arena block,
-// device-side ray steps and shell volumes, W back to the host -- all queued on
-// the server stream; r->stage lives until the caller has synchronised.
-bool admit_stage1(miloc_server* S, Request* r)
+// Admission, device part, queued on the server stream: one upload of the
+// host image into the request's arena block, the ray steps and q (from the
+// ray-sampled shell volumes) computed on the device, and the model
+// descriptor.  img must stay untouched until the stream has drained.
+bool admit_device(miloc_server* S, Request* r, const char* img)
 {
     const Layout lay = layout_of(*r);
     char* base = static_cast<char*>(S->arena_mem) + r->off;
     auto dptr = [&](size_t o) { return static_cast<void*>(base + o); };
-    Request::Staging& G = *r->stage;
     const int n = r->n;
-    const MolDev& m = G.m;
-    const std::vector<double>& Rn = G.Rn;
-    const std::vector<double>& an = G.an;
-    const std::vector<double>& nmolLb = G.nmolLb;
-    const std::vector<double>& xs = G.xs;
-    const std::vector<double>& b_all = G.b_all;
-    const std::vector<int64_t>& roff = G.roff;
-    const std::vector<int>& kmin = G.kmin;
-    const std::vector<double>& vrdv = G.vrdv;
-    const std::vector<float2>& sv = G.sv;
-    const std::vector<float>& ibf = G.ibf;
-    struct Up { size_t o; const void* src; size_t bytes; };
-    const Up ups[] = {
-        {lay.mol, &m, sizeof(MolDev)},
-        {lay.roff, roff.data(), roff.size() * sizeof(int64_t)},
-        {lay.kmin, kmin.data(), kmin.size() * sizeof(int)},
-        {lay.R, Rn.data(), n * sizeof(double)},
-        {lay.b, b_all.data(), b_all.size() * sizeof(double)},
-        {lay.vrdv, vrdv.data(), n * sizeof(double)},
-        {lay.area, an.data(), r->nrays * sizeof(double)},
-        {lay.shellv, sv.data(), n * sizeof(float2)},
-        {lay.x, xs.data(), xs.size() * sizeof(double)},
-        {lay.nH2, r->nH2.data(), n * sizeof(double)},
-        {lay.Tk, r->Tk.data(), n * sizeof(double)},
-        {lay.nmolLb, nmolLb.data(), n * sizeof(double)},
-        {lay.Ibg, ibf.data(), r->T * sizeof(float)},
-        {lay.Ibg64, r->Ibg.data(), r->T * sizeof(double)},
-    };
-    for (const Up& u : ups)
-        if (hipMemcpyAsync(dptr(u.o), u.src, u.bytes, hipMemcpyHostToDevice, S->stream) != hipSuccess) {
-            r->error = "upload failed";
-            return false;
-        }
-    if (launch_ray_steps(S->stream, n, static_cast<const double*>(dptr(lay.R)), (int)b_all.size(),
+    if (hipMemcpyAsync(base, img, lay.up_end, hipMemcpyHostToDevice, S->stream) != hipSuccess) {
+        r->error = "upload failed";
+        return false;
+    }
+    if (launch_ray_steps(S->stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays + 1,
                          static_cast<const double*>(dptr(lay.b)), static_cast<const int*>(dptr(lay.kmin)),
                          static_cast<const long long*>(dptr(lay.roff)), static_cast<const double*>(dptr(lay.vrdv)),
-                         dptr(lay.steps), false) != hipSuccess) {
-        r->error = "ray step kernel failed";
-        return false;
-    }
-    // ray-sampled shell volumes W on the device (into the q slot), back to the host
-    double* dq = static_cast<double*>(dptr(lay.q));
-    if (launch_shell_weights(S->stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays,
+                         dptr(lay.steps), false) != hipSuccess ||
+        launch_shell_weights(S->stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays,
                              static_cast<const double*>(dptr(lay.b)), static_cast<const double*>(dptr(lay.area)),
-                             dq) != hipSuccess ||
-        hipMemcpyAsync(G.W.data(), dq, n * sizeof(double), hipMemcpyDeviceToHost, S->stream) != hipSuccess) {
-        r->error = "upload failed";
-        return false;
-    }
-    return true;
-}
-
-// Admission, second half (after the stream has drained): q from W, its upload,
-// and the model descriptor.
-bool admit_stage2(miloc_server* S, Request* r)
-{
-    const Layout lay = layout_of(*r);
-    char* base = static_cast<char*>(S->arena_mem) + r->off;
-    auto dptr = [&](size_t o) { return static_cast<void*>(base + o); };
-    Request::Staging& G = *r->stage;
-    const int n = r->n;
-    G.q.resize(n);
-    for (int k = 0; k < n; ++k) G.q[k] = G.W[k] > 0 ? r->dv / (G.bsq[k] * G.W[k]) : 0.0;
-    double* dq = static_cast<double*>(dptr(lay.q));
-    if (hipMemcpyAsync(dq, G.q.data(), n * sizeof(double), hipMemcpyHostToDevice, S->stream) != hipSuccess) {
-        r->error = "upload failed";
+                             static_cast<double*>(dptr(lay.q)), static_cast<const double*>(dptr(lay.bsq)),
+                             r->dv) != hipSuccess) {
+        r->error = "admission kernel failed";
         return false;
     }
     ServeModel& d = r->desc;
@@ -449,9 +413,11 @@ bool rebuild_tables(miloc_server* S)
     std::vector<ServeModel> models(S->max_slots);
     std::vector<int4> march, spectra;
     std::vector<int2> cell, se;
+    int need = 0;
     for (int sl = 0; sl < S->max_slots; ++sl) {
         Request* r = S->active[sl];
         if (!r) continue;
+        need = std::max(need, march_lds_need(r->n, r->nch));
         models[sl] = r->desc;
         models[sl].mode = r->phase;
         if (r->phase == 0) {
@@ -466,6 +432,8 @@ bool rebuild_tables(miloc_server* S)
         for (int k = 0; k < r->n; k += 256) cell.push_back(make_int2(sl, k));
     }
     march.insert(march.begin(), spectra.begin(), spectra.end());
+    S->tier = kLdsTiers - 1;
+    for (int t = kLdsTiers - 1; t >= 0 && kTierLds[t] >= need; --t) S->tier = t;
     if (march.size() > S->cap_march || cell.size() > S->cap_cell || se.size() > S->cap_se) return false;
     const int counts[3] = {(int)march.size(), (int)cell.size(), (int)se.size()};
     bool ok = hipMemcpyAsync(S->d_models, models.data(), models.size() * sizeof(ServeModel),
@@ -483,9 +451,9 @@ bool rebuild_tables(miloc_server* S)
 
 // Results of a model whose spectra ran in the last tick: host copies were
 // queued after the tick; convert the spectra to CGS.
-void take_results(Request* r, const std::vector<float>& sp)
+void take_results(Request* r, const float* sp)
 {
-    r->spectra.resize(sp.size());
+    r->spectra.resize((size_t)r->T * r->nch);
     for (int t = 0; t < r->T; ++t)
         for (int c = 0; c < r->nch; ++c)
             r->spectra[(size_t)t * r->nch + c] = (double)sp[(size_t)t * r->nch + c] * r->Iscale[t];
@@ -498,9 +466,12 @@ void worker_loop(miloc_server* S)
     std::vector<unsigned long long> flags(2 * (size_t)S->max_slots);
     for (;;) {
         std::vector<Request*> to_admit;
+        std::vector<size_t> img_off;              // host images in the pinned staging area
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // admission: a free slot and room in the arena, first fit in arrival order
+            // admission: a free slot and room in the arena, first fit in arrival
+            // order, as many as the staging area holds this round
+            size_t staged_bytes = 0;
             for (auto it = S->queue.begin(); it != S->queue.end();) {
                 Request* r = *it;
                 if (r->state == 4) { it = S->queue.erase(it); continue; }
@@ -509,7 +480,11 @@ void worker_loop(miloc_server* S)
                     if (!S->active[i]) { slot = i; break; }
                 size_t off = 0;
                 if (slot < 0) break;
+                const size_t up = (layout_of(*r).up_end + 255) & ~(size_t)255;
+                if (staged_bytes + up > S->stage_cap) break;
                 if (!S->arena.alloc(r->bytes, &off)) { ++it; continue; }
+                img_off.push_back(staged_bytes);
+                staged_bytes += up;
                 r->off = off;
                 r->slot = slot;
                 r->state = 1;
@@ -541,29 +516,26 @@ void worker_loop(miloc_server* S)
                 S->active[r->slot] = nullptr;
                 S->stats.failed++;
             };
-            // host statics of all new requests in parallel, then the uploads
+            // host images of all new requests in parallel, then one upload and
+            // two kernels each, and a single synchronisation
             std::vector<char> host_ok(to_admit.size(), 0);
             {
-                const size_t nw = std::min<size_t>(to_admit.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+                const size_t nw = std::min<size_t>(to_admit.size(),
+                                                   std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
                 std::vector<std::thread> pool;
                 std::atomic<size_t> next{0};
                 for (size_t w = 0; w < nw; ++w)
                     pool.emplace_back([&]() {
-                        for (size_t i = next++; i < to_admit.size(); i = next++) host_ok[i] = admit_host(to_admit[i]) ? 1 : 0;
+                        for (size_t i = next++; i < to_admit.size(); i = next++)
+                            host_ok[i] = admit_host(to_admit[i], S->h_stage + img_off[i]) ? 1 : 0;
                     });
                 for (auto& t : pool) t.join();
             }
-            std::vector<Request*> staged;
             for (size_t i = 0; i < to_admit.size(); ++i) {
                 Request* r = to_admit[i];
-                if (host_ok[i] && admit_stage1(S, r)) staged.push_back(r);
-                else fail_admission(r);
+                if (!host_ok[i] || !admit_device(S, r, S->h_stage + img_off[i])) fail_admission(r);
             }
-            bool ok = hipStreamSynchronize(S->stream) == hipSuccess;
-            for (Request* r : staged)
-                if (ok && !admit_stage2(S, r)) fail_admission(r);
-            ok = ok && hipStreamSynchronize(S->stream) == hipSuccess;
-            for (Request* r : to_admit) r->stage.reset();
+            const bool ok = hipStreamSynchronize(S->stream) == hipSuccess;
             if (!ok) {
                 std::lock_guard<std::mutex> lk(S->mu);
                 S->device_error = true;
@@ -590,19 +562,33 @@ void worker_loop(miloc_server* S)
         // one tick = one ALI iteration of every iterating model and the centre
         // spectra of every model that finished in the previous tick
         const double t0 = now_s();
-        hipError_t e = hipGraphLaunch(S->graph_exec, S->stream);
+        hipError_t e = hipGraphLaunch(S->graph_exec[S->tier], S->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(flags.data(), S->d_flags, flags.size() * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, S->stream);
+        // results of the models whose spectra run in this tick: into the
+        // pinned result area while it has room, else into the request
+        size_t res_used = 0;
         for (Request* r : S->active) {
             if (!r || r->phase != 1 || e != hipSuccess) continue;
-            r->sp_host.resize((size_t)r->T * r->nch);
-            r->x.resize((size_t)r->n * r->L);
-            e = hipMemcpyAsync(r->sp_host.data(), r->desc.spec, r->sp_host.size() * sizeof(float),
-                               hipMemcpyDeviceToHost, S->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(r->x.data(), r->desc.x, r->x.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                   S->stream);
+            const size_t sp_bytes = (size_t)r->T * r->nch * sizeof(float);
+            const size_t x_bytes = (size_t)r->n * r->L * sizeof(double);
+            void* sp_dst;
+            void* x_dst;
+            if (res_used + result_bytes(*r) <= S->res_cap) {
+                r->res_off = res_used;
+                sp_dst = S->h_res + res_used;
+                x_dst = S->h_res + res_used + ((sp_bytes + 255) & ~(size_t)255);
+                res_used += (result_bytes(*r) + 255) & ~(size_t)255;
+            } else {
+                r->res_off = kNoRes;
+                r->sp_host.resize((size_t)r->T * r->nch);
+                r->x.resize((size_t)r->n * r->L);
+                sp_dst = r->sp_host.data();
+                x_dst = r->x.data();
+            }
+            e = hipMemcpyAsync(sp_dst, r->desc.spec, sp_bytes, hipMemcpyDeviceToHost, S->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(x_dst, r->desc.x, x_bytes, hipMemcpyDeviceToHost, S->stream);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
         if (e != hipSuccess) {
@@ -627,7 +613,17 @@ void worker_loop(miloc_server* S)
                     S->stats.cancelled++;
                 } else {
                     const bool good = r->status == MILOC_OK || r->status == MILOC_ENOTCONV;
-                    if (good) take_results(r, r->sp_host);
+                    if (good) {
+                        if (r->res_off != kNoRes) {
+                            const char* src = S->h_res + r->res_off;
+                            const size_t sp_bytes = (size_t)r->T * r->nch * sizeof(float);
+                            const double* xs = reinterpret_cast<const double*>(src + ((sp_bytes + 255) & ~(size_t)255));
+                            r->x.assign(xs, xs + (size_t)r->n * r->L);
+                            take_results(r, reinterpret_cast<const float*>(src));
+                        } else {
+                            take_results(r, r->sp_host.data());
+                        }
+                    }
                     r->state = good ? 2 : 3;
                     if (good) S->stats.completed++; else S->stats.failed++;
                 }
@@ -700,6 +696,12 @@ miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int ma
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_counts), 4 * sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_flags), 2 * max_slots * sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_zero), kMaxTrans * sizeof(float)) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&S->h_stage), kStageBytes) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&S->h_res), kResBytes) == hipSuccess;
+    if (ok) {
+        S->stage_cap = kStageBytes;
+        S->res_cap = kResBytes;
+    }
     if (!ok) {
         miloc_server_destroy(S.release());
         return MILOC_ENOMEM;
@@ -714,19 +716,22 @@ miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int ma
     S->grid.cell_blocks = 512;
     S->grid.se_blocks = 2048;
     S->grid.se_bs = kSeBs;
-    S->grid.march_lds = (int)((((size_t)kMaxServeShells * 2 * sizeof(float)) + 15) & ~(size_t)15) +
-                        kRaysPerBlock * kMaxServeChannels * (int)sizeof(float);
+    S->grid.march_lds = kTierLds[kLdsTiers - 1];
     S->grid.se_lds = kSeBs * (kMaxServeLevels * (kMaxServeLevels + 1) + kMaxServeLevels) * (int)sizeof(double);
     ServeTables tb{S->d_models, S->d_march, S->d_counts, S->d_cell, S->d_counts + 1, S->d_se, S->d_counts + 2};
     ok = serve_set_attributes(S->grid) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
-    ok = ok && hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-        const hipError_t le = launch_serve_tick(S->stream, tb, S->grid);
-        const hipError_t ce = hipStreamEndCapture(S->stream, &S->graph);
-        ok = le == hipSuccess && ce == hipSuccess;
+    for (int t = 0; t < kLdsTiers && ok; ++t) {
+        ServeGrid g = S->grid;
+        g.march_lds = kTierLds[t];
+        ok = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const hipError_t le = launch_serve_tick(S->stream, tb, g);
+            const hipError_t ce = hipStreamEndCapture(S->stream, &S->graph[t]);
+            ok = le == hipSuccess && ce == hipSuccess;
+        }
+        ok = ok && hipGraphInstantiate(&S->graph_exec[t], S->graph[t], nullptr, nullptr, 0) == hipSuccess;
     }
-    ok = ok && hipGraphInstantiate(&S->graph_exec, S->graph, nullptr, nullptr, 0) == hipSuccess;
     if (!ok) {
         miloc_server_destroy(S.release());
         return MILOC_EDEVICE;
@@ -751,12 +756,16 @@ void miloc_server_destroy(miloc_server* S)
     if (S->worker.joinable()) S->worker.join();
     (void)hipSetDevice(S->device);
     if (S->stream) (void)hipStreamSynchronize(S->stream);
-    if (S->graph_exec) (void)hipGraphExecDestroy(S->graph_exec);
-    if (S->graph) (void)hipGraphDestroy(S->graph);
+    for (int t = 0; t < kLdsTiers; ++t) {
+        if (S->graph_exec[t]) (void)hipGraphExecDestroy(S->graph_exec[t]);
+        if (S->graph[t]) (void)hipGraphDestroy(S->graph[t]);
+    }
     void* bufs[] = {S->arena_mem, S->d_models, S->d_march, S->d_cell, S->d_se, S->d_counts, S->d_flags,
                     S->d_zero};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    if (S->h_stage) (void)hipHostFree(S->h_stage);
+    if (S->h_res) (void)hipHostFree(S->h_res);
     if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
 }
@@ -867,7 +876,9 @@ miloc_status parse_request(miloc_server* S, const miloc_molecule* mol, const mil
     r->max_iter = max_iter;
     if ((size_t)T * ((r->nrays + kRaysPerBlock - 1) / kRaysPerBlock) > S->cap_march / (size_t)S->max_slots)
         return sfail(S, MILOC_EINVAL, "too many transitions x rays for one serving slot");
-    r->bytes = layout_of(*r).total;
+    const Layout lay = layout_of(*r);
+    if (lay.up_end > kStageBytes) return sfail(S, MILOC_EINVAL, "request too large for the staging area");
+    r->bytes = lay.total;
     return MILOC_OK;
 }
 
