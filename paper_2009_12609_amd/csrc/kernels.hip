@@ -516,21 +516,24 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
 
 // Per-cell sums of the octree march's per-step partial sums, one thread per
 // cell and all transitions of the launch: FP64 sums over the cell's steps
-// (listed by the host), written to the accumulators.
-template <typename T>
+// (listed by the host), written to the accumulators.  A step's TILE
+// transitions are contiguous in E, so with ntr <= TILE each step row is read
+// once; wider launches take the transitions TILE at a time.
+template <typename T, int TILE>
 __global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
 {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= p.nc) return;
     const long long a = p.cell_off[k], b = p.cell_off[k + 1];
     double2* acc = p.acc + (size_t)k * p.ntr_total + p.trans_offset;
-    // transitions in register tiles of four
-    for (int t0 = 0; t0 < p.ntr; t0 += 4) {
-        double sj[4] = {0.0, 0.0, 0.0, 0.0}, sl[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < p.ntr; t0 += TILE) {
+        double sj[TILE], sl[TILE];
+#pragma unroll
+        for (int q = 0; q < TILE; ++q) sj[q] = sl[q] = 0.0;
         for (long long i = a; i < b; ++i) {
             const typename V2<T>::type* e = p.E + (size_t)p.cell_steps[i] * p.ntr + t0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < TILE; ++q) {
                 if (t0 + q < p.ntr) {
                     const typename V2<T>::type v = e[q];
                     sj[q] += (double)v.x;
@@ -539,7 +542,7 @@ __global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < TILE; ++q)
             if (t0 + q < p.ntr) acc[t0 + q] = make_double2(sj[q], sl[q]);
     }
 }
@@ -1283,8 +1286,13 @@ hipError_t dispatch_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, boo
 template <typename T>
 hipError_t do_gather_oct(hipStream_t s, const GatherOctArgs<T>& a)
 {
-    const long long blocks = (a.nc + 255) / 256;
-    hipLaunchKernelGGL(gather_oct_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const dim3 grid((unsigned)((a.nc + 255) / 256));
+    if (a.ntr <= 4)
+        hipLaunchKernelGGL((gather_oct_kernel<T, 4>), grid, dim3(256), 0, s, a);
+    else if (a.ntr <= 8)
+        hipLaunchKernelGGL((gather_oct_kernel<T, 8>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((gather_oct_kernel<T, 12>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_gather_oct(hipStream_t s, const GatherOctArgs<float>& a) { return do_gather_oct(s, a); }
