@@ -548,6 +548,37 @@ __global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
 }
 
 // ---------------------------------------------------------------- octree march
+namespace {
+
+// Copies the first n elements of a channel vector between LDS and device
+// memory in 16-byte pieces (both vectors 16-byte aligned and padded to whole
+// pieces): each lane issues all of its loads of a round before its first
+// store, so a copy costs one memory round trip per 4 LANES pieces rather
+// than one per element.
+template <int LANES, typename T>
+__device__ __forceinline__ void copy_channels(T* __restrict__ dst, const T* __restrict__ src, int n, int lane)
+{
+    constexpr int PER = 16 / (int)sizeof(T);
+    const int nq = (n + PER - 1) / PER;
+    const int4* __restrict__ s4 = reinterpret_cast<const int4*>(src);
+    int4* __restrict__ d4 = reinterpret_cast<int4*>(dst);
+    for (int q0 = lane; q0 < nq; q0 += 4 * LANES) {
+        // lanes past the end load the last piece again (always in range) and
+        // store nothing
+        const int qa = q0, qb = q0 + LANES, qc = q0 + 2 * LANES, qd = q0 + 3 * LANES;
+        const int4 va = s4[qa];
+        const int4 vb = s4[qb < nq ? qb : nq - 1];
+        const int4 vc = s4[qc < nq ? qc : nq - 1];
+        const int4 vd = s4[qd < nq ? qd : nq - 1];
+        d4[qa] = va;
+        if (qb < nq) d4[qb] = vb;
+        if (qc < nq) d4[qc] = vc;
+        if (qd < nq) d4[qd] = vd;
+    }
+}
+
+}  // namespace
+
 // Persistent lane groups (8 or 16 lanes) take work units (one root line's rays for one
 // transition) from a global counter, largest units first.  Each unit replays
 // its host-built step list: a record names the leaf and the step length and
@@ -635,14 +666,13 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             if (mode == kOctModeBg) {
                 for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
             } else if (mode != kOctModeKeep && sp >= 0) {
-                const T* __restrict__ src = stk + (size_t)sp * p.ich;
-                for (int c = lane; c < p.nch; c += LANES) I[c] = src[c];
+                copy_channels<LANES, T>(I, stk + (size_t)sp * p.ich, p.nch, lane);
                 if (mode == kOctModePop) --sp;
             }
             if ((w0 & kOctSave) && sp + 1 < p.depth) {
                 ++sp;
-                T* __restrict__ dst = stk + (size_t)sp * p.ich;
-                for (int c = lane; c < p.nch; c += LANES) dst[c] = I[c];
+                __builtin_amdgcn_wave_barrier();
+                copy_channels<LANES, T>(stk + (size_t)sp * p.ich, I, p.nch, lane);
             }
             __builtin_amdgcn_wave_barrier();
             const int clo = as_int(wv.z);

@@ -198,7 +198,7 @@ struct OctTreeRec {
 
 template <typename T>
 struct OctMarchArgs {
-    int nc, nch, ich;                    // cells, channels, LDS stride of a channel vector
+    int nc, nch, ich;                    // cells, channels, stride of a channel vector (oct_stride)
     int ntr, trans_offset, ntr_total;    // transitions of this launch / in ke and acc
     long long n_items;                   // trees x ntr (transitions vary fastest)
     const OctTreeRec* trees;
@@ -215,6 +215,16 @@ struct OctMarchArgs {
     T* stack;                            // [groups][depth][ich] saved vectors
     int depth;
 };
+
+// Stride (elements) of an octree march channel vector, in LDS and in the
+// saved-vector stacks: whole 16-byte units plus 64 bytes, so that vectors
+// copy in 16-byte pieces and the lane groups of a wavefront start in
+// different LDS banks.
+inline int oct_stride(int nch, int elem_bytes)
+{
+    const int per = 16 / elem_bytes;
+    return (nch + per - 1) / per * per + 64 / elem_bytes;
+}
 
 // Kernel launchers (kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_serve_tick(hipStream_t s, const ServeTables& tb, const ServeGrid& g);

@@ -404,7 +404,7 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
     hipDeviceProp_t prop;
     HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
     const size_t tsz = c->precision == MILOC_MARCH_FP64 ? sizeof(double) : sizeof(float);
-    const size_t per_group = (size_t)std::max(1, c->oct_depth) * c->nch * tsz;
+    const size_t per_group = (size_t)std::max(1, c->oct_depth) * oct_stride(c->nch, (int)tsz) * tsz;
     const int gpb = 256 / c->lanes;       // lane groups per 256-thread block
     int64_t groups = (int64_t)prop.multiProcessorCount * 8 * gpb;
     groups = std::min<int64_t>(groups, std::max<int64_t>(gpb, (int64_t)((2ull << 30) / per_group)));
@@ -424,7 +424,7 @@ miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, c
     OctMarchArgs<TT> a{};
     a.nc = (int)c->nc;
     a.nch = c->nch;
-    a.ich = c->nch;
+    a.ich = oct_stride(c->nch, (int)sizeof(TT));
     a.ntr = ntr;
     a.trans_offset = toff;
     a.ntr_total = c->T;
