@@ -492,7 +492,7 @@ miloc_status ensure_static(miloc_ctx* c)
     if (c->kind == 3)
         c->lanes = wmax <= 32.0 ? 8 : (wmax <= 64.0 ? 16 : 32);
     else if (c->kind == 4)
-        c->lanes = 16;                    // octree: groups of 16 (8 measured slower), any window width
+        c->lanes = 8;                     // octree: groups of 8 (measured faster than 16), any window width
     else
         c->lanes = 16;                    // 1D: groups of 16, any window width
     if (const char* ev = std::getenv("MILOC_LANES")) {
