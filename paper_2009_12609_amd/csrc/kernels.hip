@@ -269,52 +269,12 @@ __device__ __forceinline__ double omb_any(double tau)
 // so that the profile is exp2(-x^2)), tau_j = kl e_j, emission el e_j beta_j.
 // Partial sums of this lane in sj, sl.  The series/exact choice for 1 - beta
 // is made once per step for the whole wavefront.
-template <int LANES, typename T, bool THIN>
-__device__ __forceinline__ void channel_pair(T* __restrict__ row, int j, bool second, T x0, T ibs, T kl, T el,
-                                             T& sj, T& sl)
-{
-    // two channels, j and j + LANES: both LDS reads are issued before either
-    // update, which halves the dependent LDS round trips of a step
-    const T xa = (T)j * ibs + x0;
-    const T xb = (T)(j + LANES) * ibs + x0;
-    const T ia = row[j];
-    const T ib = second ? row[j + LANES] : (T)0;
-    const T ea = fast_exp2(-xa * xa);
-    const T eb = second ? fast_exp2(-xb * xb) : (T)0;
-    const T oa = THIN ? omb_thin(kl * ea) : omb_any(kl * ea);
-    const T ob = THIN ? omb_thin(kl * eb) : omb_any(kl * eb);
-    const T ua = ea - ea * oa;                 // e_c beta_c
-    const T ub = eb - eb * ob;
-    sj += ia * ua + ib * ub;
-    sl += ea * oa + eb * ob;
-    row[j] = ia + ua * (el - kl * ia);         // e^-tau = 1 - tau beta
-    if (second) row[j + LANES] = ib + ub * (el - kl * ib);
-}
-
-// The channel window of one step for one ray (Sect. 2: I e^-tau + S(1 -
-// e^-tau) per channel, absorbed counts and the diagonal operator summed):
-// channels clo .. clo + nwin - 1, profile argument x_j = x0 + j ibs (scaled
-// so that the profile is exp2(-x^2)), tau_j = kl e_j, emission el e_j beta_j.
-// Partial sums of this lane in sj, sl.  The series/exact choice for 1 - beta
-// is made once per step for the whole wavefront.
-template <int LANES, typename T, bool PAIRS = false>
+template <int LANES, typename T>
 __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
                                                 T kl, T el, T& sj, T& sl)
 {
     const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
     T* __restrict__ row = I + clo;
-    if (PAIRS) {
-        // latency-bound callers (a few long rays in flight): two channels per
-        // pass, see channel_pair
-        if (thin) {
-            for (int j = lane; j < nwin; j += 2 * LANES)
-                channel_pair<LANES, T, true>(row, j, j + LANES < nwin, x0, ibs, kl, el, sj, sl);
-        } else {
-            for (int j = lane; j < nwin; j += 2 * LANES)
-                channel_pair<LANES, T, false>(row, j, j + LANES < nwin, x0, ibs, kl, el, sj, sl);
-        }
-        return;
-    }
     if (thin) {
         for (int j = lane; j < nwin; j += LANES) {
             const T xs = (T)j * ibs + x0;
@@ -680,7 +640,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
-            window_channels<LANES, T, true>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
+            window_channels<LANES, T>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
