@@ -43,6 +43,7 @@ BYTES_PER_STEP = 40.0
 FLOPS_PER_CHANNEL = 22.0
 WINDOW_K = 5.0                # Doppler widths on each side (FP32 march)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march3d_regular_128_traffic.json")
+OCT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_oct_64root_L4_traffic.json")
 
 
 def mean_window_channels(w) -> float:
@@ -63,11 +64,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(src_hash):
+def measured_traffic(src_hash, path=TRAFFIC_FILE):
     """HBM bytes per march launch from the committed rocprofv3 counter runs,
     only if they were taken on the current kernel source."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -157,7 +158,8 @@ def octree_bench(steps=2, warmup=1):
         "setup_s": t_setup,
         "generate_s": t_gen,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic(kernel_source_hash(), OCT_TRAFFIC_FILE),
                      "kernel": f"march_oct_kernel<float,{cnt['march_lanes']},true>",
                      "flops_per_channel_update": FLOPS_PER_CHANNEL, "window_channels_mean": nwin,
                      "hbm_algorithmic_gbs": hbm_gbs, "hbm_algorithmic_frac": hbm_gbs / HBM_PEAK_GBS,
