@@ -980,6 +980,141 @@ __device__ double se_cell(const SEArgs& p, int k, int tid, int bs, double* __res
     return dmax;
 }
 
+// The same solve with the matrix in registers, for L known at compile time
+// (every index below is a constant after unrolling).  Rates are entered per
+// level pair u > l: all collisions, then the radiative transition of each
+// pair (MolDev::pair_t); the pivot row exchange of partial pivoting is done
+// with selects.  Same equations and pivot choice as se_cell; the radiative
+// terms of a diagonal entry are summed in pair rather than transition order.
+template <int L>
+__device__ double se_cell_reg(const SEArgs& p, int k)
+{
+    constexpr int W = L + 1;
+    const MolDev* __restrict__ mol = p.mol;
+    const double* xo = p.x_old + (size_t)k * L;
+    double* xn = p.x_new + (size_t)k * L;
+    double x[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) x[i] = xo[i];
+    const double q = p.q[k];
+    if (q < 0.0) {
+        // a refined octree cell: no rays cross it, its populations are kept
+#pragma unroll
+        for (int i = 0; i < L; ++i) xn[i] = x[i];
+        return 0.0;
+    }
+    const double nH2 = p.nH2[k];
+    const double T = p.Tkin[k];
+    double bz[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) bz[i] = mol->g[i] * exp(-mol->E[i] / T);
+    double M[L][W];
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int j = 0; j < W; ++j) M[i][j] = 0.0;
+    // collisions, every pair u > l; upward rate by detailed balance
+#pragma unroll
+    for (int u = 1; u < L; ++u) {
+#pragma unroll
+        for (int l = 0; l < u; ++l) {
+            const double gam = mol->gamma[u * L + l];
+            if (gam != 0.0) {
+                const double Cul = nH2 * gam;
+                const double Clu = Cul * bz[u] / bz[l];
+                M[l][u] += Cul;  M[u][u] -= Cul;
+                M[u][l] += Clu;  M[l][l] -= Clu;
+            }
+        }
+    }
+    // radiative rates, by level pair; ALI: A scaled by 1 - Lambda
+#pragma unroll
+    for (int u = 1; u < L; ++u) {
+#pragma unroll
+        for (int l = 0; l < u; ++l) {
+            const int t = mol->pair_t[u * kMaxLevels + l];
+            if (t >= 0) {
+                const double A = mol->A[t];
+                const double2 a = p.acc[(size_t)k * p.ntr + t];
+                double J = a.x * q;
+                const double Lam = a.y * q;
+                double Rul;
+                if (p.use_ali) {
+                    Rul = A * (1.0 - Lam) + A * J;
+                } else {
+                    const double den = x[l] * mol->gratio[t] - x[u];
+                    const double S = den != 0.0 ? x[u] / den : 0.0;
+                    J += S * Lam;
+                    Rul = A + A * J;
+                }
+                const double Rlu = mol->gratio[t] * A * J;
+                M[l][u] += Rul;  M[u][u] -= Rul;
+                M[u][l] += Rlu;  M[l][l] -= Rlu;
+            }
+        }
+    }
+    // replace the equation of the most populated level by sum x = 1
+    int r = 0;
+#pragma unroll
+    for (int i = 1; i < L; ++i) r = x[i] > (r == 0 ? x[0] : x[r]) ? i : r;
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int j = 0; j < W; ++j) M[i][j] = i == r ? 1.0 : M[i][j];
+    // Gaussian elimination with partial pivoting
+#pragma unroll
+    for (int c = 0; c < L; ++c) {
+        int piv = c;
+        double best = fabs(M[c][c]);
+#pragma unroll
+        for (int i = c + 1; i < L; ++i) {
+            const double v = fabs(M[i][c]);
+            piv = v > best ? i : piv;
+            best = v > best ? v : best;
+        }
+#pragma unroll
+        for (int j = c; j < W; ++j) {
+            const double rc = M[c][j];
+            double rp = rc;
+#pragma unroll
+            for (int i = c + 1; i < L; ++i) rp = piv == i ? M[i][j] : rp;
+#pragma unroll
+            for (int i = c + 1; i < L; ++i) M[i][j] = piv == i ? rc : M[i][j];
+            M[c][j] = rp;
+        }
+        const double inv = 1.0 / M[c][c];
+#pragma unroll
+        for (int i = c + 1; i < L; ++i) {
+            const double f = M[i][c] * inv;
+            if (f != 0.0) {
+#pragma unroll
+                for (int j = c + 1; j < W; ++j) M[i][j] -= f * M[c][j];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+        double sacc = M[i][L];
+#pragma unroll
+        for (int j = i + 1; j < L; ++j) sacc -= M[i][j] * M[j][L];
+        M[i][L] = sacc / M[i][i];
+    }
+    bool bad = false;
+    double dmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const double xi = M[i][L];
+        xn[i] = xi;
+        if (!(xi == xi) || xi < -1.0e-12 || fabs(xi) > 2.0) bad = true;
+        if (xi >= 1.0e-10) {
+            const double d = fabs(xi - x[i]) / xi;
+            dmax = d > dmax ? d : dmax;
+        }
+    }
+    if (bad) atomicAdd(p.bad, 1u);
+    return dmax;
+}
+
 // Maximum over the block of a non-negative double (bit-pattern order), folded
 // into *dst with one atomic per wavefront (or partial wavefront).
 __device__ __forceinline__ void block_max_to(double v, int bs, unsigned long long* dst)
@@ -991,6 +1126,14 @@ __device__ __forceinline__ void block_max_to(double v, int bs, unsigned long lon
         bits = other > bits ? other : bits;
     }
     if (((int)threadIdx.x % width) == 0 && bits != 0ull) atomicMax(dst, bits);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void se_reg_kernel(SEArgs p)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const double dmax = k < p.nc ? se_cell_reg<L>(p, k) : 0.0;
+    block_max_to(dmax, (int)blockDim.x, p.delta_bits);
 }
 
 __global__ void se_kernel(SEArgs p)
@@ -1331,6 +1474,22 @@ hipError_t serve_set_attributes(const ServeGrid& g)
 hipError_t launch_se(hipStream_t s, const SEArgs& a0)
 {
     SEArgs a = a0;
+    // up to 12 levels: the matrix in registers, 256 threads per workgroup
+    const dim3 rg((a.nc + 255) / 256), rb(256);
+    switch (a.L) {
+    case 2: hipLaunchKernelGGL(se_reg_kernel<2>, rg, rb, 0, s, a); return hipGetLastError();
+    case 3: hipLaunchKernelGGL(se_reg_kernel<3>, rg, rb, 0, s, a); return hipGetLastError();
+    case 4: hipLaunchKernelGGL(se_reg_kernel<4>, rg, rb, 0, s, a); return hipGetLastError();
+    case 5: hipLaunchKernelGGL(se_reg_kernel<5>, rg, rb, 0, s, a); return hipGetLastError();
+    case 6: hipLaunchKernelGGL(se_reg_kernel<6>, rg, rb, 0, s, a); return hipGetLastError();
+    case 7: hipLaunchKernelGGL(se_reg_kernel<7>, rg, rb, 0, s, a); return hipGetLastError();
+    case 8: hipLaunchKernelGGL(se_reg_kernel<8>, rg, rb, 0, s, a); return hipGetLastError();
+    case 9: hipLaunchKernelGGL(se_reg_kernel<9>, rg, rb, 0, s, a); return hipGetLastError();
+    case 10: hipLaunchKernelGGL(se_reg_kernel<10>, rg, rb, 0, s, a); return hipGetLastError();
+    case 11: hipLaunchKernelGGL(se_reg_kernel<11>, rg, rb, 0, s, a); return hipGetLastError();
+    case 12: hipLaunchKernelGGL(se_reg_kernel<12>, rg, rb, 0, s, a); return hipGetLastError();
+    default: break;
+    }
     // LDS per thread: (L*(L+1) + L) doubles; block size = the largest power
     // of two (<= 256) that keeps the block within 64 KB.
     const size_t per = (size_t)(a.L * (a.L + 1) + a.L) * sizeof(double);

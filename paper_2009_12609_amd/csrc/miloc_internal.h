@@ -32,7 +32,15 @@ struct MolDev {
     double A[kMaxTrans];
     double gratio[kMaxTrans];    // g_u / g_l
     double Ct[kMaxTrans];        // c^3 A / (8 pi nu^3) [cm^3 s^-1 ... per unit n_mol]
+    int pair_t[kMaxLevels * kMaxLevels];   // [u*kMaxLevels + l]: the transition u -> l, -1 if none
 };
+
+// Fills MolDev::pair_t from up/lo (the caller has rejected duplicate pairs).
+inline void mol_pair_table(MolDev& m)
+{
+    for (int i = 0; i < kMaxLevels * kMaxLevels; ++i) m.pair_t[i] = -1;
+    for (int t = 0; t < m.T; ++t) m.pair_t[m.up[t] * kMaxLevels + m.lo[t]] = t;
+}
 
 // One 3D ray direction of the regular-grid march.  All N*N rays of a
 // direction share one crossing pattern (same fractional transverse offset),

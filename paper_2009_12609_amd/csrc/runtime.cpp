@@ -210,6 +210,7 @@ miloc_status ensure_base(miloc_ctx* c)
         m.gratio[t] = c->g[c->up[t]] / c->g[c->lo[t]];
         m.Ct[t] = kC * kC * kC * c->A[t] / (8.0 * kPi * c->nu[t] * c->nu[t] * c->nu[t]);
     }
+    mol_pair_table(m);
     HIPCHK(c, c->d_mol.ensure(sizeof(MolDev)));
     HIPCHK(c, hipMemcpy(c->d_mol.p, &m, sizeof(MolDev), hipMemcpyHostToDevice));
     const int64_t nc = c->nc;

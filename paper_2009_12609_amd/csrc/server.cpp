@@ -281,6 +281,7 @@ bool admit_host(Request* r, char* img)
         m.gratio[t] = r->g[r->up[t]] / r->g[r->lo[t]];
         m.Ct[t] = kC * kC * kC * r->A[t] / (8.0 * kPi * r->nu[t] * r->nu[t] * r->nu[t]);
     }
+    mol_pair_table(m);
     std::memcpy(img + lay.mol, &m, sizeof(m));
     // geometry and per-shell statics, in normalised radius units
     const int n = r->n;
