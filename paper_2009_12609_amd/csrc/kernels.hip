@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
 // the cell's transverse coordinates (ia, ib) vary fastest so that neighbouring
 // threads read neighbouring rays.  For a step s of direction q the ray that was
 // in the cell started at ((ia - sa na_s) mod N, (ib - sb nb_s) mod N).
-template <typename T>
+template <typename T, int TILE>
 __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
 {
     using T2 = typename V2<T>::type;
@@ -445,10 +445,15 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
     if (pos >= N * N) return;
     const int ia = pos % N, ib = pos / N;
     const int cm = blockIdx.y;
-    const int tl = blockIdx.z;
+    // up to TILE transitions per thread: their loads of one step are
+    // independent, and the cell's accumulator row is updated in one piece
+    const int t0 = blockIdx.z * TILE;
+    const int nt = p.ntr - t0 < TILE ? p.ntr - t0 : TILE;
     const int NN = N * N;
-    const T2* __restrict__ E = p.E + (size_t)tl * p.e_tstride;
-    double sj = 0.0, sl = 0.0;
+    const T2* __restrict__ E = p.E + (size_t)t0 * p.e_tstride;
+    double sj[TILE], sl[TILE];
+#pragma unroll
+    for (int q = 0; q < TILE; ++q) sj[q] = sl[q] = 0.0;
     for (int k = 0; k < p.nq; ++k) {
         const DirDev& D = p.dirs[p.qlist[k]];
         const int l = D.fwd ? cm : N - 1 - cm;
@@ -461,17 +466,28 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
             i0 -= i0 >= N ? N : 0;
             j0 += j0 < 0 ? N : 0;
             j0 -= j0 >= N ? N : 0;
-            const T2 e = E[(size_t)(D.step0 + s) * NN + j0 * N + i0];
-            sj += (double)e.x;
-            sl += (double)e.y;
+            const size_t off = (size_t)(D.step0 + s) * NN + j0 * N + i0;
+#pragma unroll
+            for (int q = 0; q < TILE; ++q) {
+                if (q < nt) {
+                    const T2 e = E[(size_t)q * p.e_tstride + off];
+                    sj[q] += (double)e.x;
+                    sl[q] += (double)e.y;
+                }
+            }
         }
     }
     const size_t idx = (size_t)ia * p.st_a + (size_t)ib * p.st_b + (size_t)cm * p.st_m;
-    double2* a = p.acc + idx * p.ntr_total + p.trans_offset + tl;
-    double2 v = *a;
-    v.x += sj;
-    v.y += sl;
-    *a = v;
+    double2* a = p.acc + idx * p.ntr_total + p.trans_offset + t0;
+#pragma unroll
+    for (int q = 0; q < TILE; ++q) {
+        if (q < nt) {
+            double2 v = a[q];
+            v.x += sj[q];
+            v.y += sl[q];
+            a[q] = v;
+        }
+    }
 }
 
 // Per-cell sums of the octree march's per-step partial sums, one thread per
@@ -1385,9 +1401,10 @@ hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes
 template <typename T>
 hipError_t do_gather3d(hipStream_t s, const Gather3DArgs<T>& a)
 {
+    constexpr int kTile = 12;
     const int bs = 256;
-    const dim3 grid((a.N * a.N + bs - 1) / bs, a.N, a.ntr);
-    hipLaunchKernelGGL(gather3d_kernel<T>, grid, dim3(bs), 0, s, a);
+    const dim3 grid((a.N * a.N + bs - 1) / bs, a.N, (a.ntr + kTile - 1) / kTile);
+    hipLaunchKernelGGL((gather3d_kernel<T, kTile>), grid, dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a) { return do_gather3d(s, a); }
