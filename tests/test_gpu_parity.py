@@ -102,6 +102,20 @@ def test_1d_small_fp64_iteration_by_iteration():
     assert_spectra(sp, ref_sp, 1e-9, "1d-small fp64")
 
 
+@pytest.mark.parametrize("n_levels", [3, 7, 12, 13])
+def test_1d_level_counts_fp64(n_levels):
+    """Equilibrium solves of every size class: up to 12 levels the matrix is
+    held in registers (one compiled solver per level count), above that in
+    LDS.  Rotor species on the small shell cloud, FP64 march, 6 iterations."""
+    w = synth.workload_1d_small()
+    w.mol = synth.rotor_molecule(n_levels)
+    print(f"[case] 1d-small fp64 L={n_levels}", flush=True)
+    ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, 6)
+    ctx = make_ctx(w, fp64=True)
+    ctx.run(6)
+    assert_pops(ctx.populations(), ref.x, 1e-10, f"1d-small L={n_levels}")
+
+
 def test_1d_small_fp32():
     w = synth.workload_1d_small()
     ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, 20)
