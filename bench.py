@@ -64,17 +64,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(src_hash, path=TRAFFIC_FILE):
-    """HBM bytes per march launch from the committed rocprofv3 counter runs,
-    only if they were taken on the current kernel source."""
+def measured_counters(src_hash, path=TRAFFIC_FILE):
+    """From the committed rocprofv3 counter runs of a march kernel, only if
+    they were taken on the current kernel source: (HBM bytes per launch,
+    VALU-busy fraction of the launch), else (None, None)."""
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return None, None
     if d.get("kernel_source_hash") != src_hash:
-        return None
-    return d.get("bytes_per_launch")
+        return None, None
+    return d.get("bytes_per_launch"), d.get("valu_busy")
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -143,6 +144,7 @@ def octree_bench(steps=2, warmup=1):
     steps_per_launch = cnt["ray_steps"] / launches
     hbm_gbs = steps_per_launch * OCT_BYTES_PER_STEP / (march_ms * 1e-3) / 1e9
     nwin = mean_window_channels(w)
+    traffic, valu_busy = measured_counters(kernel_source_hash(), OCT_TRAFFIC_FILE)
     achieved = steps_per_launch * nwin * FLOPS_PER_CHANNEL / (march_ms * 1e-3) / 1e12
     return {
         "metric": "ray-cell-channel updates/s (3D octree)",
@@ -159,7 +161,7 @@ def octree_bench(steps=2, warmup=1):
         "generate_s": t_gen,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": measured_traffic(kernel_source_hash(), OCT_TRAFFIC_FILE),
+                     "traffic": traffic, "valu_busy": valu_busy,
                      "kernel": f"march_oct_kernel<float,{cnt['march_lanes']},true>",
                      "flops_per_channel_update": FLOPS_PER_CHANNEL, "window_channels_mean": nwin,
                      "hbm_algorithmic_gbs": hbm_gbs, "hbm_algorithmic_frac": hbm_gbs / HBM_PEAK_GBS,
@@ -329,7 +331,7 @@ def main():
     flops_per_launch = steps_per_launch * nwin * FLOPS_PER_CHANNEL
     achieved = flops_per_launch / (march_ms * 1e-3) / 1e12
     src_hash = kernel_source_hash()
-    traffic = measured_traffic(src_hash)
+    traffic, valu_busy = measured_counters(src_hash)
 
     out = {
         "metric": "ray-cell-channel updates/s (3D)",
@@ -364,6 +366,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": traffic,
+            "valu_busy": valu_busy,
             "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true>",
             "flops_per_channel_update": FLOPS_PER_CHANNEL,
             "window_channels_mean": nwin,
