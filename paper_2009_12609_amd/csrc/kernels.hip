@@ -526,32 +526,58 @@ __global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
 // ---------------------------------------------------------------- octree march
 namespace {
 
-// Copies the first n elements of a channel vector between LDS and device
-// memory in 16-byte pieces (both vectors 16-byte aligned and padded to whole
-// pieces): each lane issues all of its loads of a round before its first
-// store, so a copy costs one memory round trip per 4 LANES pieces rather
-// than one per element.
+// Copies 16-byte pieces qa .. qb - 1 of a channel vector between LDS and
+// device memory (both vectors 16-byte aligned and padded to whole pieces):
+// each lane issues all of its loads of a round before its first store, so a
+// copy costs one memory round trip per 4 LANES pieces rather than one per
+// element.
 template <int LANES, typename T>
-__device__ __forceinline__ void copy_channels(T* __restrict__ dst, const T* __restrict__ src, int n, int lane)
+__device__ __forceinline__ void copy_pieces(T* __restrict__ dst, const T* __restrict__ src, int qa, int qb, int lane)
 {
-    constexpr int PER = 16 / (int)sizeof(T);
-    const int nq = (n + PER - 1) / PER;
     const int4* __restrict__ s4 = reinterpret_cast<const int4*>(src);
     int4* __restrict__ d4 = reinterpret_cast<int4*>(dst);
-    for (int q0 = lane; q0 < nq; q0 += 4 * LANES) {
+    for (int q0 = qa + lane; q0 < qb; q0 += 4 * LANES) {
         // lanes past the end load the last piece again (always in range) and
         // store nothing
-        const int qa = q0, qb = q0 + LANES, qc = q0 + 2 * LANES, qd = q0 + 3 * LANES;
-        const int4 va = s4[qa];
-        const int4 vb = s4[qb < nq ? qb : nq - 1];
-        const int4 vc = s4[qc < nq ? qc : nq - 1];
-        const int4 vd = s4[qd < nq ? qd : nq - 1];
-        d4[qa] = va;
-        if (qb < nq) d4[qb] = vb;
-        if (qc < nq) d4[qc] = vc;
-        if (qd < nq) d4[qd] = vd;
+        const int q1 = q0 + LANES, q2 = q0 + 2 * LANES, q3 = q0 + 3 * LANES;
+        const int4 v0 = s4[q0];
+        const int4 v1 = s4[q1 < qb ? q1 : qb - 1];
+        const int4 v2 = s4[q2 < qb ? q2 : qb - 1];
+        const int4 v3 = s4[q3 < qb ? q3 : qb - 1];
+        d4[q0] = v0;
+        if (q1 < qb) d4[q1] = v1;
+        if (q2 < qb) d4[q2] = v2;
+        if (q3 < qb) d4[q3] = v3;
     }
 }
+
+// Per-group stack of channel spans [lo, hi) in registers: entry e lives in
+// lane e % LANES, slot e / LANES.
+template <int LANES, int SLOTS>
+struct SpanStack {
+    int lo[SLOTS], hi[SLOTS];
+    __device__ __forceinline__ void set(int e, int lane, int l, int h)
+    {
+        const bool mine = lane == e % LANES;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const bool at = mine && s == e / LANES;
+            lo[s] = at ? l : lo[s];
+            hi[s] = at ? h : hi[s];
+        }
+    }
+    __device__ __forceinline__ void get(int e, int& l, int& h) const
+    {
+        int a = 0, b = 0;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            a = s == e / LANES ? lo[s] : a;
+            b = s == e / LANES ? hi[s] : b;
+        }
+        l = __shfl(a, e % LANES, LANES);
+        h = __shfl(b, e % LANES, LANES);
+    }
+};
 
 }  // namespace
 
@@ -580,11 +606,19 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
     T2q* __restrict__ queue = reinterpret_cast<T2q*>(smem_raw + (size_t)(blockDim.x / LANES) * p.ich * sizeof(T)) +
                               (size_t)grp * LANES;
     T* __restrict__ stk = p.stack + gid * (size_t)p.depth * p.ich;
+    constexpr int kPer = 16 / (int)sizeof(T);   // channels per 16-byte piece
+    constexpr int kSpanSlots = 8;
+    SpanStack<LANES, kSpanSlots> spans;
+    // deeper stacks than the span registers hold copy whole vectors
+    const bool use_spans = p.depth <= kSpanSlots * LANES;
+    int lo = 0, hi = p.nch;                       // LDS contents unknown: a full reset first
     for (;;) {
         unsigned long long item = 0;
         if (lane == 0) item = atomicAdd(p.counter, 1ull);
         item = __shfl(item, 0, LANES);
         if (item >= (unsigned long long)p.n_items) break;
+        lo = 0;                                   // a new transition's background everywhere
+        hi = p.nch;
         const long long tree = (long long)(item / (unsigned long long)p.ntr);
         const int t = p.trans_offset + (int)(item % (unsigned long long)p.ntr);
         const OctTreeRec tr = p.trees[tree];
@@ -639,20 +673,44 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             kv.y = __shfl(mykv.y, k, LANES);
             const int cell = (int)(w0 & kOctCellMask);
             const unsigned mode = w0 >> kOctModeShift;
+            // Channels outside the span [lo, hi) hold the background: the
+            // span grows with each step's window, a new ray takes the span of
+            // its saved vector, and only the span is reset or copied.
             if (mode == kOctModeBg) {
-                for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+                for (int c = lo + lane; c < hi; c += LANES) I[c] = Ibg;
+                lo = p.nch;
+                hi = 0;
             } else if (mode != kOctModeKeep && sp >= 0) {
-                copy_channels<LANES, T>(I, stk + (size_t)sp * p.ich, p.nch, lane);
+                int slo = 0, shi = p.nch;
+                if (use_spans) spans.get(sp, slo, shi);
+                // reset what the saved vector does not cover, then copy it
+                const int r0 = hi < slo ? hi : slo, r1 = lo > shi ? lo : shi;
+                for (int c = lo + lane; c < r0; c += LANES) I[c] = Ibg;
+                for (int c = r1 + lane; c < hi; c += LANES) I[c] = Ibg;
+                if (shi > slo)
+                    copy_pieces<LANES, T>(I, stk + (size_t)sp * p.ich, slo / kPer, (shi + kPer - 1) / kPer, lane);
+                lo = slo;
+                hi = shi;
                 if (mode == kOctModePop) --sp;
             }
             if ((w0 & kOctSave) && sp + 1 < p.depth) {
                 ++sp;
+                if (!use_spans) {
+                    lo = 0;
+                    hi = p.nch;
+                }
                 __builtin_amdgcn_wave_barrier();
-                copy_channels<LANES, T>(stk + (size_t)sp * p.ich, I, p.nch, lane);
+                if (hi > lo)
+                    copy_pieces<LANES, T>(stk + (size_t)sp * p.ich, I, lo / kPer, (hi + kPer - 1) / kPer, lane);
+                if (use_spans) spans.set(sp, lane, lo, hi);
             }
             __builtin_amdgcn_wave_barrier();
             const int clo = as_int(wv.z);
             const int nwin = as_int(wv.w);
+            if (nwin > 0) {
+                lo = clo < lo ? clo : lo;
+                hi = clo + nwin > hi ? clo + nwin : hi;
+            }
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
