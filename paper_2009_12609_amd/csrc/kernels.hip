@@ -492,9 +492,10 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
 
 // Per-cell sums of the octree march's per-step partial sums, one thread per
 // cell and all transitions of the launch: FP64 sums over the cell's steps
-// (listed by the host), written to the accumulators.  A step's TILE
-// transitions are contiguous in E, so with ntr <= TILE each step row is read
-// once; wider launches take the transitions TILE at a time.
+// (listed by the host), written to the accumulators.  TILE transitions of a
+// step's row are read with unconditional wide loads (FP32 rows are 16-byte
+// aligned), all issued before any is used; columns past the launch's
+// transitions are read but never stored (E carries slack past its last row).
 template <typename T, int TILE>
 __global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
 {
@@ -506,14 +507,32 @@ __global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
         double sj[TILE], sl[TILE];
 #pragma unroll
         for (int q = 0; q < TILE; ++q) sj[q] = sl[q] = 0.0;
+        // the next step's index is loaded with the current step's row
+        unsigned idx_n = a < b ? p.cell_steps[a] : 0u;
         for (long long i = a; i < b; ++i) {
-            const typename V2<T>::type* e = p.E + (size_t)p.cell_steps[i] * p.ntr + t0;
+            const unsigned idx = idx_n;
+            if (i + 1 < b) idx_n = p.cell_steps[i + 1];
+            const typename V2<T>::type* e = p.E + (size_t)idx * p.estride + t0;
+            if constexpr (sizeof(T) == 4) {
+                const float4* __restrict__ e4 = reinterpret_cast<const float4*>(e);
+                float4 v[TILE / 2];
 #pragma unroll
-            for (int q = 0; q < TILE; ++q) {
-                if (t0 + q < p.ntr) {
-                    const typename V2<T>::type v = e[q];
-                    sj[q] += (double)v.x;
-                    sl[q] += (double)v.y;
+                for (int q = 0; q < TILE / 2; ++q) v[q] = e4[q];
+#pragma unroll
+                for (int q = 0; q < TILE / 2; ++q) {
+                    sj[2 * q] += (double)v[q].x;
+                    sl[2 * q] += (double)v[q].y;
+                    sj[2 * q + 1] += (double)v[q].z;
+                    sl[2 * q + 1] += (double)v[q].w;
+                }
+            } else {
+                typename V2<T>::type v[TILE];
+#pragma unroll
+                for (int q = 0; q < TILE; ++q) v[q] = e[q];
+#pragma unroll
+                for (int q = 0; q < TILE; ++q) {
+                    sj[q] += (double)v[q].x;
+                    sl[q] += (double)v[q].y;
                 }
             }
         }
@@ -628,7 +647,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         const T aw = (T)p.aw[tr.q];
         const T Ibg = p.Ibg[t];
         const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
-        T2q* __restrict__ Et = p.E ? p.E + (size_t)tr.off * p.ntr + (t - p.trans_offset) : nullptr;
+        T2q* __restrict__ Et = p.E ? p.E + (size_t)tr.off * p.estride + (t - p.trans_offset) : nullptr;
         int qn = 0, qs0 = 0;
         int sp = -1;
         // Records arrive LANES at a time, one per lane, and each lane also loads
@@ -729,7 +748,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
                     ++qn;
                     __builtin_amdgcn_wave_barrier();
                     if (qn == LANES || s == tr.n - 1) {
-                        if (lane < qn) Et[(size_t)(qs0 + lane) * p.ntr] = queue[lane];
+                        if (lane < qn) Et[(size_t)(qs0 + lane) * p.estride] = queue[lane];
                         qs0 += qn;
                         qn = 0;
                     }
@@ -1129,8 +1148,12 @@ __device__ double se_cell_reg(const SEArgs& p, int k)
     }
     // replace the equation of the most populated level by sum x = 1
     int r = 0;
+    double xr = x[0];
 #pragma unroll
-    for (int i = 1; i < L; ++i) r = x[i] > (r == 0 ? x[0] : x[r]) ? i : r;
+    for (int i = 1; i < L; ++i) {
+        r = x[i] > xr ? i : r;
+        xr = x[i] > xr ? x[i] : xr;
+    }
 #pragma unroll
     for (int i = 0; i < L; ++i)
 #pragma unroll
@@ -1495,12 +1518,15 @@ template <typename T>
 hipError_t do_gather_oct(hipStream_t s, const GatherOctArgs<T>& a)
 {
     const dim3 grid((unsigned)((a.nc + 255) / 256));
-    if (a.ntr <= 4)
-        hipLaunchKernelGGL((gather_oct_kernel<T, 4>), grid, dim3(256), 0, s, a);
-    else if (a.ntr <= 8)
-        hipLaunchKernelGGL((gather_oct_kernel<T, 8>), grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((gather_oct_kernel<T, 12>), grid, dim3(256), 0, s, a);
+    // the smallest even tile that holds the launch's transitions, at most 12
+    switch (a.ntr <= 2 ? 2 : a.ntr <= 4 ? 4 : a.ntr <= 6 ? 6 : a.ntr <= 8 ? 8 : a.ntr <= 10 ? 10 : 12) {
+    case 2: hipLaunchKernelGGL((gather_oct_kernel<T, 2>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((gather_oct_kernel<T, 4>), grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((gather_oct_kernel<T, 6>), grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((gather_oct_kernel<T, 8>), grid, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((gather_oct_kernel<T, 10>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((gather_oct_kernel<T, 12>), grid, dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 hipError_t launch_gather_oct(hipStream_t s, const GatherOctArgs<float>& a) { return do_gather_oct(s, a); }

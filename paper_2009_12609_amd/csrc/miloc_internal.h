@@ -191,7 +191,8 @@ struct GatherOctArgs {
     int ntr, trans_offset, ntr_total;
     const long long* cell_off;           // [nc + 1]
     const unsigned* cell_steps;          // step indices grouped by cell
-    const typename V2<T>::type* E;       // [step][ntr]
+    const typename V2<T>::type* E;       // [step][estride]
+    int estride;                         // row stride of E (>= ntr; even for FP32: 16-byte rows)
     double2* acc;                        // [nc][ntr_total]
 };
 
@@ -217,7 +218,8 @@ struct OctMarchArgs {
     const typename V2<T>::type* ke;      // [nc][ntr_total]
     const T* Ibg;                        // [ntr_total]
     double2* acc;                        // [nc][ntr_total] {J, Lambda} raw sums (when E is null)
-    typename V2<T>::type* E;             // per-step sums [step][ntr] of this launch, or null
+    typename V2<T>::type* E;             // per-step sums [step][estride] of this launch, or null
+    int estride;                         // row stride of E (>= ntr; even for FP32: 16-byte rows)
     T* Iout;                             // no accumulation: [trees][nch] leaving intensity
     unsigned long long* counter;         // work counter, zero at launch
     T* stack;                            // [groups][depth][ich] saved vectors

@@ -111,6 +111,7 @@ struct miloc_ctx {
     int oct_depth = 0, oct_groups = 0;
     int64_t total_steps = 0;
     int trans_chunk = 1;
+    int oct_estride = 1;                 // row stride (transitions) of the octree per-step sums
     int qcount[3] = {0, 0, 0}, qoff[3] = {0, 0, 0};
     std::vector<double> Iscale, Ibg;   // per transition: 2 h nu^3 / c^2, background (occupation)
     std::vector<double> Rn;            // 1D: outer radii / R_out
@@ -362,9 +363,14 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
         double budget_gb = 160.0;
         if (const char* ev = std::getenv("MILOC_STEP_BUFFER_GB")) budget_gb = std::atof(ev);
         const size_t per_t = (size_t)std::max<int64_t>(1, S.n_steps) * 2 * (fp64 ? sizeof(double) : sizeof(float));
-        const int tc = (int)std::min<double>((double)c->T, std::floor(budget_gb * 1e9 / (double)per_t));
+        // FP32 rows padded to an even number of transitions (16-byte rows)
+        auto stride_of = [&](int tc) { return fp64 ? tc : (tc + 1) / 2 * 2; };
+        int tc = (int)std::min<double>((double)c->T, std::floor(budget_gb * 1e9 / (double)per_t));
+        while (tc > 1 && (double)stride_of(tc) * per_t > budget_gb * 1e9) --tc;
         c->trans_chunk = tc < 1 ? 1 : tc;
-        HIPCHK(c, c->d_oE.ensure(per_t * c->trans_chunk));
+        c->oct_estride = stride_of(c->trans_chunk);
+        // slack: the gather reads whole tiles of up to 12 transitions past the last row
+        HIPCHK(c, c->d_oE.ensure(per_t * c->oct_estride + 12 * 2 * sizeof(double)));
     }
     if (fp64) {
         HIPCHK(c, c->d_olen64.ensure(std::max<size_t>(1, S.len64.size()) * sizeof(double)));
@@ -439,6 +445,7 @@ miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, c
     a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
     a.acc = c->d_acc.as<double2>();
     a.E = accum ? c->d_oE.as<typename V2<TT>::type>() : nullptr;
+    a.estride = c->oct_estride;
     a.Iout = Iout;
     a.counter = c->d_ocounter.as<unsigned long long>();
     a.stack = c->d_ostack.as<TT>();
@@ -1139,12 +1146,12 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
                 if (fp64) {
                     GatherOctArgs<double> g{c->nc, nt, t0, c->T, c->d_ocell_off.as<long long>(),
                                             c->d_ocell_steps.as<unsigned>(), c->d_oE.as<double2>(),
-                                            c->d_acc.as<double2>()};
+                                            c->oct_estride, c->d_acc.as<double2>()};
                     HIPCHK(c, launch_gather_oct(c->stream, g));
                 } else {
                     GatherOctArgs<float> g{c->nc, nt, t0, c->T, c->d_ocell_off.as<long long>(),
                                            c->d_ocell_steps.as<unsigned>(), c->d_oE.as<float2>(),
-                                           c->d_acc.as<double2>()};
+                                           c->oct_estride, c->d_acc.as<double2>()};
                     HIPCHK(c, launch_gather_oct(c->stream, g));
                 }
                 HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
