@@ -467,13 +467,15 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
             j0 += j0 < 0 ? N : 0;
             j0 -= j0 >= N ? N : 0;
             const size_t off = (size_t)(D.step0 + s) * NN + j0 * N + i0;
+            // all loads of the step issued before any is used; columns past
+            // the launch's transitions re-read the last one and are not stored
+            T2 e[TILE];
+#pragma unroll
+            for (int q = 0; q < TILE; ++q) e[q] = E[(size_t)(q < nt ? q : nt - 1) * p.e_tstride + off];
 #pragma unroll
             for (int q = 0; q < TILE; ++q) {
-                if (q < nt) {
-                    const T2 e = E[(size_t)q * p.e_tstride + off];
-                    sj[q] += (double)e.x;
-                    sl[q] += (double)e.y;
-                }
+                sj[q] += (double)e[q].x;
+                sl[q] += (double)e[q].y;
             }
         }
     }
@@ -1482,10 +1484,25 @@ hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes
 template <typename T>
 hipError_t do_gather3d(hipStream_t s, const Gather3DArgs<T>& a)
 {
-    constexpr int kTile = 12;
+    // a tile of all the launch's transitions up to 12
+    const int tile = a.ntr < 12 ? a.ntr : 12;
     const int bs = 256;
-    const dim3 grid((a.N * a.N + bs - 1) / bs, a.N, (a.ntr + kTile - 1) / kTile);
-    hipLaunchKernelGGL((gather3d_kernel<T, kTile>), grid, dim3(bs), 0, s, a);
+    const dim3 grid((a.N * a.N + bs - 1) / bs, a.N, (a.ntr + tile - 1) / tile);
+    const dim3 block(bs);
+    switch (tile) {
+    case 1: hipLaunchKernelGGL((gather3d_kernel<T, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((gather3d_kernel<T, 2>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((gather3d_kernel<T, 3>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((gather3d_kernel<T, 4>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((gather3d_kernel<T, 5>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((gather3d_kernel<T, 6>), grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((gather3d_kernel<T, 7>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((gather3d_kernel<T, 8>), grid, block, 0, s, a); break;
+    case 9: hipLaunchKernelGGL((gather3d_kernel<T, 9>), grid, block, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((gather3d_kernel<T, 10>), grid, block, 0, s, a); break;
+    case 11: hipLaunchKernelGGL((gather3d_kernel<T, 11>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((gather3d_kernel<T, 12>), grid, block, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a) { return do_gather3d(s, a); }
