@@ -2,7 +2,8 @@
  * miloc.h -- C ABI of the MI355X ALI line radiative-transfer library (libmiloc.so).
  *
  * The library solves the non-LTE level populations of one molecular species
- * in a 1D spherical cloud (nested shells) or a 3D regular Cartesian grid by
+ * in a 1D spherical cloud (nested shells), a 3D regular Cartesian grid or a
+ * 3D octree (a regular root grid with nested refinement) by
  * alternating a deterministic ray march (radiative transfer) with per-cell
  * statistical-equilibrium solves, as in Juvela (2020), "LOC program for line
  * radiative transfer":
@@ -15,7 +16,8 @@
  *     the escape probability (Sect. 2);
  *   - 1D impact-parameter rays through shells (Sect. 2.1), 3D HEALPix ray
  *     directions with one ray per upstream surface element and side
- *     re-entry (Sect. 2.2).
+ *     re-entry, and in octrees rays split at refinement boundaries
+ *     (Sect. 2.2).
  *
  * Conventions (all calls):
  *   - Units are CGS and Kelvin.  Host arrays are row-major.
@@ -30,6 +32,15 @@
  *     the caller lends at creation and keeps alive until miloc_destroy).
  *   - Calls in the wrong order (run before a model, molecule and spectral
  *     grid are loaded; spectra before populations exist) return MILOC_ESTATE.
+ *
+ * Tuning (environment, read when a context prepares its first run):
+ *   - MILOC_LANES: lanes per ray of the march (1D and regular 3D: 8, 16, 32
+ *     or 64; octree: 8 or 16).  Default: by the widest channel window
+ *     (regular 3D), 16 (1D), 8 (octree).  Results do not depend on it beyond
+ *     FP32 summation order.
+ *   - MILOC_STEP_BUFFER_GB: device memory (GB, default 160) for the 3D
+ *     per-step partial sums; with less, the transitions of an iteration are
+ *     marched in several launches.
  */
 #ifndef MILOC_H
 #define MILOC_H

@@ -67,10 +67,11 @@ __device__ __forceinline__ void escape_terms(double tau, double& omb, double& e)
     }
 }
 
-// Sum over a group of LANES (32 or 64) consecutive lanes; the total is valid
-// in the group's last lane.  FP32 uses DPP row operations (no LDS traffic):
-// quad swaps, half-row and row mirrors give every lane its 16-lane row sum,
-// row_bcast15 / row_bcast31 then fold rows 0->1, 2->3 and (64) 1->3.
+// Sum over a group of LANES (8, 16, 32 or 64) consecutive lanes; the total is
+// valid in the group's last lane.  FP32 uses DPP row operations (no LDS
+// traffic): quad swaps and the half-row mirror give the last lane of every 8
+// its 8-lane sum, the row mirror its 16-lane row sum, row_bcast15 /
+// row_bcast31 then fold rows 0->1, 2->3 and (64) 1->3.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float v)
 {
@@ -175,7 +176,7 @@ __global__ void lte_kernel(int nc, const MolDev* __restrict__ mol, const double*
 // ---------------------------------------------------------------- 3D march
 // Per workgroup: rays of one direction (a block never straddles directions).
 // The direction's step list is staged in LDS once and read as a broadcast.
-// Several rays share a wavefront (16 lanes each for narrow lines), so each
+// Several rays share a wavefront (8 lanes each for narrow lines), so each
 // step issues the cell loads of several independent rays at once.
 namespace {
 
@@ -610,7 +611,8 @@ struct SpanStack {
 // them) and whether to save the incoming intensity first.  Saved vectors live
 // in a per-group stack in device memory.  The step itself is the regular
 // grid's: channel window of the (direction, leaf) pair, I e^-tau + S(1 -
-// e^-tau), absorbed-count and Lambda sums folded into FP64 accumulators.
+// e^-tau); with accumulation, the step's absorbed-count and Lambda sums go to
+// the per-step buffer E (required then), summed per cell by gather_oct_kernel.
 template <typename T, int LANES, bool ACCUM>
 __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
 {
@@ -692,7 +694,6 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             T2 kv;
             kv.x = __shfl(mykv.x, k, LANES);
             kv.y = __shfl(mykv.y, k, LANES);
-            const int cell = (int)(w0 & kOctCellMask);
             const unsigned mode = w0 >> kOctModeShift;
             // Channels outside the span [lo, hi) hold the background: the
             // span grows with each step's window, a new ray takes the span of
@@ -739,26 +740,19 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
-                if (Et) {
-                    if (lane == LANES - 1) {
-                        const T wgt = aw * len;
-                        T2q v;
-                        v.x = wgt * sj;
-                        v.y = wgt * sl;
-                        queue[qn] = v;
-                    }
-                    ++qn;
-                    __builtin_amdgcn_wave_barrier();
-                    if (qn == LANES || s == tr.n - 1) {
-                        if (lane < qn) Et[(size_t)(qs0 + lane) * p.estride] = queue[lane];
-                        qs0 += qn;
-                        qn = 0;
-                    }
-                } else if (lane == LANES - 1) {
-                    const double wgt = (double)(aw * len);
-                    double2* a = p.acc + (size_t)cell * p.ntr_total + t;
-                    unsafeAtomicAdd(&a->x, wgt * (double)sj);
-                    unsafeAtomicAdd(&a->y, wgt * (double)sl);
+                if (lane == LANES - 1) {
+                    const T wgt = aw * len;
+                    T2q v;
+                    v.x = wgt * sj;
+                    v.y = wgt * sl;
+                    queue[qn] = v;
+                }
+                ++qn;
+                __builtin_amdgcn_wave_barrier();
+                if (qn == LANES || s == tr.n - 1) {
+                    if (lane < qn) Et[(size_t)(qs0 + lane) * p.estride] = queue[lane];
+                    qs0 += qn;
+                    qn = 0;
                 }
             }
             __builtin_amdgcn_wave_barrier();

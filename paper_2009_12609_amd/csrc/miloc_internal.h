@@ -217,8 +217,7 @@ struct OctMarchArgs {
     const typename V4<T>::type* win;     // [n_dir][nc]
     const typename V2<T>::type* ke;      // [nc][ntr_total]
     const T* Ibg;                        // [ntr_total]
-    double2* acc;                        // [nc][ntr_total] {J, Lambda} raw sums (when E is null)
-    typename V2<T>::type* E;             // per-step sums [step][estride] of this launch, or null
+    typename V2<T>::type* E;             // per-step sums [step][estride] of this launch (with accumulation)
     int estride;                         // row stride of E (>= ntr; even for FP32: 16-byte rows)
     T* Iout;                             // no accumulation: [trees][nch] leaving intensity
     unsigned long long* counter;         // work counter, zero at launch

@@ -443,7 +443,6 @@ miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, c
     a.win = reinterpret_cast<const typename V4<TT>::type*>(win);
     a.ke = c->d_ke.as<typename V2<TT>::type>();
     a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
-    a.acc = c->d_acc.as<double2>();
     a.E = accum ? c->d_oE.as<typename V2<TT>::type>() : nullptr;
     a.estride = c->oct_estride;
     a.Iout = Iout;
@@ -490,12 +489,8 @@ miloc_status ensure_static(miloc_ctx* c)
     const double Kd = fp64 ? kWindowK64 : kWindowK32;
     c->Kw = Kd * kSqrtLog2e;
     c->chalf = 0.5 + c->vmin / c->dv;
-    // widest window over the cells decides lanes per ray
-    double minb = b[0];
-    for (int64_t k = 0; k < nc; ++k) minb = std::min(minb, b[k]);
-    (void)minb;
-    // lanes per ray: the channel window (at most wmax channels) is covered in
-    // one to three passes of the ray's lane group
+    // lanes per ray: the widest channel window over the cells (at most wmax
+    // channels) is covered in one to three passes of the ray's lane group
     const double wmax = 2.0 * Kd * maxb / c->dv + 2.0;
     if (c->kind == 3)
         c->lanes = wmax <= 32.0 ? 8 : (wmax <= 64.0 ? 16 : 32);
