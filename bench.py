@@ -15,7 +15,7 @@ each step's profile window).  ``roofline`` describes the dominant kernel (the
 3D march) from its HIP-event durations; ``cpu_baseline`` is the FP64 oracle
 timed on this host's cores on a bounded sample of the same workload.  Two more
 objects by default: ``octree`` (64^3 root refined four levels, 2 timed ALI
-iterations, same per-step measures) and ``serving`` (a 192-request 1D stream:
+iterations, same per-step measures) and ``serving`` (a 512-request 1D stream:
 model solves/s with all requests queued at once, p50/p99 latency under Poisson
 arrivals at 0.5x and 0.8x of that rate, and the same requests solved one at a
 time through a single-model context).
@@ -174,7 +174,7 @@ def _pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
-def serve_bench(n_req=192, seed=5001, tol=1e-6, max_iter=500):
+def serve_bench(n_req=512, seed=5001, tol=1e-6, max_iter=500):
     """1D request stream (50-2000 shells, 2/5/10/20 levels, 64/128/256
     channels): model solves/s with every request queued at once (arrival rate
     far above capacity), p50/p99 latency at 0.5x and 0.8x of that capacity
@@ -275,7 +275,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128, help="grid size (128 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", type=int, default=192, metavar="N_REQ",
+    ap.add_argument("--serve", type=int, default=512, metavar="N_REQ",
                     help="run the 1D request stream with N_REQ requests ('serving' object; 0 = skip)")
     ap.add_argument("--octree", type=int, default=2, metavar="STEPS",
                     help="time STEPS iterations of the octree workload ('octree' object; 0 = skip)")
