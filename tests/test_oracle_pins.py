@@ -117,6 +117,25 @@ def test_1d_shell_volume_sampling():
     assert errs[1] < errs[0] / 10.0
 
 
+def test_1d_power_law_ray_weights():
+    """Ray weights of any impact spacing tile the disc (sum = pi R^2, each one
+    the annulus between the mid-points of its neighbours) and still sample
+    the shell volumes: b_j = R ((j + 1/2)/N)^2."""
+    R = np.array([1.0, 2.0, 3.5])
+    V = 4.0 / 3.0 * np.pi * (R ** 3 - np.concatenate([[0.0], R[:-1]]) ** 3)
+    n = 4000
+    b = R[-1] * ((np.arange(n) + 0.5) / n) ** 2
+    a = oracle.ray_areas_1d(R[-1], b)
+    assert math.isclose(a.sum(), math.pi * R[-1] ** 2, rel_tol=1e-12)
+    edges = np.concatenate([[0.0], 0.5 * (b[1:] + b[:-1]), [R[-1]]])
+    assert np.allclose(a, np.pi * (edges[1:] ** 2 - edges[:-1] ** 2), rtol=1e-12, atol=0)
+    W = np.zeros(3)
+    for bj, aj in zip(b, a):
+        sh, s, mu = oracle.ray_steps_1d(R, bj)
+        np.add.at(W, sh, aj * s)
+    assert np.max(np.abs(W / V - 1)) < 2e-3
+
+
 def test_1d_ray_steps_geometry():
     """Chord pieces add up to 2 sqrt(R^2 - b^2); cosines at step starts."""
     R = np.array([1.0, 2.0, 4.0])
