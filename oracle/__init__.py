@@ -71,7 +71,8 @@ def lib():
         L.orc1d_march.restype = None
         L.orc1d_march.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int, dp, dp,
                                   ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp, dp]
+                                  ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp, dp,
+                                  ctypes.c_int, dp, dp]
         L.orc3d_main_axis.restype = ctypes.c_int
         L.orc3d_main_axis.argtypes = [dp]
         L.orc3d_walk.restype = ctypes.c_int
@@ -83,17 +84,17 @@ def lib():
         L.orc3d_march.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp, dp,
                                   ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                  dp, dp, dp, dp, dp, dp]
+                                  dp, dp, dp, dp, dp, dp, ctypes.c_int, dp, dp]
         llp = ctypes.POINTER(ctypes.c_longlong)
         L.orcoct_march.restype = None
         L.orcoct_march.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ip, ctypes.c_double,
                                    dp, dp, dp, dp, dp, dp, ctypes.c_int, dp, ctypes.c_int,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                   dp, dp, dp, dp, dp, llp]
+                                   dp, dp, dp, dp, dp, llp, ctypes.c_int, dp, dp]
         L.orcoct_map_z.restype = None
         L.orcoct_map_z.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_double, dp, dp, dp, dp,
                                    dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_int, dp]
+                                   ctypes.c_double, ctypes.c_int, dp, ctypes.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -326,30 +327,46 @@ class MarchResult:
     cons: float
 
 
-def march_1d(R, vr, bD, kappa, eta, impact, area, spec, I_bg, n_threads=0, want_I=False):
+def _shape_call(shape):
+    """C arguments (n, v, w) of a line shape plus the arrays that must stay
+    alive during the call.  None is the single Gaussian; otherwise (v_k [cm/s],
+    w_k) of the hyperfine components (Sect. 1: LTE between the components),
+    the strengths relative (the C side divides by their sum)."""
+    if shape is None:
+        return [0, None, None], None
+    v, w = _f64(shape[0]).ravel(), _f64(shape[1]).ravel()
+    assert v.shape == w.shape and v.size > 0 and np.all(w > 0)
+    return [int(v.size), _dp(v), _dp(w)], (v, w)
+
+
+def march_1d(R, vr, bD, kappa, eta, impact, area, spec, I_bg, n_threads=0, want_I=False,
+             shape=None):
     R, vr, bD, kappa, eta = map(_f64, (R, vr, bD, kappa, eta))
     impact, area = _f64(impact), _f64(area)
     n, nr, nch = R.shape[0], impact.shape[0], spec.n_channels
     J, Lm, W, E = (np.zeros(n) for _ in range(4))
     I_out = np.zeros(nr * nch) if want_I else None
     cons = np.zeros(1)
+    hf, _keep = _shape_call(shape)
     lib().orc1d_march(n, _dp(R), _dp(vr), _dp(bD), _dp(kappa), _dp(eta), nr, _dp(impact),
                       _dp(area), nch, float(spec.v_min), float(spec.dv), float(I_bg),
-                      int(n_threads), _dp(J), _dp(Lm), _dp(W), _dp(E), _dp(I_out), _dp(cons))
+                      int(n_threads), _dp(J), _dp(Lm), _dp(W), _dp(E), _dp(I_out), _dp(cons), *hf)
     return MarchResult(J, Lm, W, E, None if I_out is None else I_out.reshape(nr, nch), float(cons[0]))
 
 
-def march_3d(N, delta, vx, vy, vz, bD, kappa, eta, dirs, spec, I_bg, n_threads=0, want_I=False):
+def march_3d(N, delta, vx, vy, vz, bD, kappa, eta, dirs, spec, I_bg, n_threads=0, want_I=False,
+             shape=None):
     vx, vy, vz, bD, kappa, eta = map(_f64, (vx, vy, vz, bD, kappa, eta))
     dirs = _f64(dirs)
     nc, nd, nch = N ** 3, dirs.shape[0], spec.n_channels
     J, Lm, W, E = (np.zeros(nc) for _ in range(4))
     I_out = np.zeros(nd * N * N * nch) if want_I else None
     cons = np.zeros(1)
+    hf, _keep = _shape_call(shape)
     lib().orc3d_march(int(N), float(delta), _dp(vx), _dp(vy), _dp(vz), _dp(bD), _dp(kappa),
                       _dp(eta), nd, _dp(dirs), nch, float(spec.v_min), float(spec.dv),
                       float(I_bg), int(n_threads), _dp(J), _dp(Lm), _dp(W), _dp(E),
-                      _dp(I_out), _dp(cons))
+                      _dp(I_out), _dp(cons), *hf)
     return MarchResult(J, Lm, W, E, None if I_out is None else I_out.reshape(nd, N * N, nch),
                        float(cons[0]))
 
@@ -419,8 +436,10 @@ def _iterate(prob, march, n_iter, use_ali, x0, tol, record, solve_mask=None):
 
 
 def run_1d(mol, model, spec, T_bg, n_iter, use_ali=True, x0=None, tol=None,
-           n_threads=0, record=True):
-    """Lambda / ALI iteration on a 1D shell model from LTE (or x0)."""
+           n_threads=0, record=True, hyperfine=None):
+    """Lambda / ALI iteration on a 1D shell model from LTE (or x0).
+    hyperfine: {transition: (v_k [cm/s], w_k)} line shapes (others Gaussian)."""
+    hfs = hyperfine or {}
     prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
     R = _f64(model.r_out)
     impact = equidistant_impacts(R[-1], model.n_rays) if model.impact is None else _f64(model.impact)
@@ -428,14 +447,17 @@ def run_1d(mol, model, spec, T_bg, n_iter, use_ali=True, x0=None, tol=None,
     vr = _f64(model.v_r)
 
     def march(t, kap, eta):
-        return march_1d(R, vr, prob.bD, kap, eta, impact, area, spec, prob.I_bg[t], n_threads)
+        return march_1d(R, vr, prob.bD, kap, eta, impact, area, spec, prob.I_bg[t], n_threads,
+                        shape=hfs.get(t))
 
     return _iterate(prob, march, n_iter, use_ali, x0, tol, record)
 
 
 def run_3d(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, tol=None,
-           n_threads=0, record=True):
-    """Lambda / ALI iteration on a regular N^3 model (FP32 fields promoted to FP64)."""
+           n_threads=0, record=True, hyperfine=None):
+    """Lambda / ALI iteration on a regular N^3 model (FP32 fields promoted to
+    FP64); hyperfine as in run_1d."""
+    hfs = hyperfine or {}
     N = int(model.n0[0])
     assert model.n0 == (N, N, N) and model.n_oct_levels == 0
     prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
@@ -444,7 +466,7 @@ def run_3d(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, tol
 
     def march(t, kap, eta):
         return march_3d(N, float(model.root_cell_cm), vx, vy, vz, prob.bD, kap, eta, dirs,
-                        spec, prob.I_bg[t], n_threads)
+                        spec, prob.I_bg[t], n_threads, shape=hfs.get(t))
 
     return _iterate(prob, march, n_iter, use_ali, x0, tol, record)
 
@@ -485,7 +507,8 @@ def octree_of(model) -> OctTree:
 OCT_STATS = ("root", "split", "side", "terminated", "wrapped", "steps")
 
 
-def march_oct(tree: OctTree, root_cm, vx, vy, vz, bD, kappa, eta, dirs, spec, I_bg, n_threads=0):
+def march_oct(tree: OctTree, root_cm, vx, vy, vz, bD, kappa, eta, dirs, spec, I_bg, n_threads=0,
+              shape=None):
     """One transition through an octree for the given directions; also returns
     the ray statistics (dict over OCT_STATS).  kappa None: geometry only."""
     nc = tree.child.shape[0]
@@ -497,19 +520,21 @@ def march_oct(tree: OctTree, root_cm, vx, vy, vz, bD, kappa, eta, dirs, spec, I_
     cons = np.zeros(1)
     st = np.zeros(len(OCT_STATS), np.int64)
     child = np.ascontiguousarray(tree.child, dtype=np.int32)
+    hf, _keep = _shape_call(shape)
     lib().orcoct_march(tree.N, tree.Lmax, nc, child.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                        float(root_cm), *[_dp(a) for a in args], dirs.shape[0], _dp(dirs), nch,
                        0.0 if geo else float(spec.v_min), 1.0 if geo else float(spec.dv),
                        0.0 if geo else float(I_bg), int(n_threads), _dp(J), _dp(Lm), _dp(W),
-                       _dp(E), _dp(cons), st.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+                       _dp(E), _dp(cons), st.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), *hf)
     return MarchResult(J, Lm, W, E, None, float(cons[0])), dict(zip(OCT_STATS, map(int, st)))
 
 
 def run_oct(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, tol=None,
-            n_threads=0, record=True):
+            n_threads=0, record=True, hyperfine=None):
     """Lambda / ALI iteration on an octree model.  Every cell of every level
     carries populations; only leaves are marched and solved, refined cells
-    keep their starting values."""
+    keep their starting values.  hyperfine as in run_1d."""
+    hfs = hyperfine or {}
     tree = octree_of(model)
     leaf = tree.leaf
     prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
@@ -518,32 +543,35 @@ def run_oct(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, to
 
     def march(t, kap, eta):
         return march_oct(tree, float(model.root_cell_cm), vx, vy, vz, prob.bD, kap, eta, dirs,
-                         spec, prob.I_bg[t], n_threads)[0]
+                         spec, prob.I_bg[t], n_threads, shape=hfs.get(t))[0]
 
     res = _iterate(prob, march, n_iter, use_ali, x0, tol, record, solve_mask=leaf)
     return res
 
 
-def spectra_oct(mol, model, spec, T_bg, x, trans, n_threads=0):
+def spectra_oct(mol, model, spec, T_bg, x, trans, n_threads=0, shape=None):
     """+z map of an octree: one line of sight per root surface element on the
-    level-0 ray lattice, Delta I [N*N (index y*N + x), n_ch]."""
+    level-0 ray lattice, Delta I [N*N (index y*N + x), n_ch]; shape: the
+    transition's hyperfine components (v_k, w_k) or None."""
     tree = octree_of(model)
     N = tree.N
     prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
     kap, eta = prepare(mol, _f64(x), prob.n_mol)
     out = np.zeros(N * N * spec.n_channels)
     child = np.ascontiguousarray(tree.child, dtype=np.int32)
+    hf, _keep = _shape_call(shape)
     lib().orcoct_map_z(N, tree.Lmax, child.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                        float(model.root_cell_cm), _dp(_f64(model.vx)), _dp(_f64(model.vy)),
                        _dp(_f64(model.vz)), _dp(prob.bD), _dp(_f64(kap[trans])), _dp(_f64(eta[trans])),
                        spec.n_channels, float(spec.v_min), float(spec.dv), float(prob.I_bg[trans]),
-                       int(n_threads), _dp(out))
+                       int(n_threads), _dp(out), *hf)
     return out.reshape(N * N, spec.n_channels) - prob.I_bg[trans]
 
 
-def spectra_1d(mol, model, spec, T_bg, x, trans, impact=None, n_threads=0):
+def spectra_1d(mol, model, spec, T_bg, x, trans, impact=None, n_threads=0, shape=None):
     """Emergent Delta I = I - I_bg [n_los, n_ch] of transition ``trans`` for
-    rays with the given impact parameters (default: the model's ray set)."""
+    rays with the given impact parameters (default: the model's ray set);
+    shape as in spectra_oct."""
     prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
     R = _f64(model.r_out)
     if impact is None:
@@ -552,17 +580,17 @@ def spectra_1d(mol, model, spec, T_bg, x, trans, impact=None, n_threads=0):
     kap, eta = prepare(mol, _f64(x), prob.n_mol)
     area = np.ones_like(impact)
     res = march_1d(R, _f64(model.v_r), prob.bD, kap[trans], eta[trans], impact, area, spec,
-                   prob.I_bg[trans], n_threads, want_I=True)
+                   prob.I_bg[trans], n_threads, want_I=True, shape=shape)
     return res.I_out - prob.I_bg[trans]
 
 
-def spectra_3d(mol, model, spec, T_bg, x, trans, n_threads=0):
+def spectra_3d(mol, model, spec, T_bg, x, trans, n_threads=0, shape=None):
     """+z map: one line of sight per surface cell (x, y) through the cell
-    centres, Delta I [N*N (index y*N + x), n_ch]."""
+    centres, Delta I [N*N (index y*N + x), n_ch]; shape as in spectra_oct."""
     N = int(model.n0[0])
     prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
     kap, eta = prepare(mol, _f64(x), prob.n_mol)
     res = march_3d(N, float(model.root_cell_cm), _f64(model.vx), _f64(model.vy), _f64(model.vz),
                    prob.bD, kap[trans], eta[trans], np.array([[0.0, 0.0, 1.0]]), spec,
-                   prob.I_bg[trans], n_threads, want_I=True)
+                   prob.I_bg[trans], n_threads, want_I=True, shape=shape)
     return res.I_out[0] - prob.I_bg[trans]

@@ -41,6 +41,10 @@
  *   (the gas velocity projected on the propagation direction; the line of gas
  *   moving towards the observer appears at negative channel velocity);
  *   f_c = p_c dv;  tau_c = kappa p_c s.
+ *   Hyperfine structure (Sect. 1; LTE between the components): the profile is
+ *   the weighted sum of K such Gaussians, component k centred at the channel
+ *   velocity v_k - w, p_c = sum_k w_k exp(-((v_c + w - v_k)/b)^2) / (b sqrt(pi))
+ *   with the relative strengths w_k divided by their sum.
  *   3D cell (x,y,z) of an N^3 grid is stored at index (z N + y) N + x.
  */
 #include <math.h>
@@ -69,19 +73,50 @@ static void escape_terms(double tau, double* e, double* beta, double* omb)
     }
 }
 
+/* Line shape of one transition: n == 0 is the single Gaussian; otherwise n
+ * hyperfine components at velocity offsets v[k] (cm/s) with relative
+ * strengths w[k] (normalised here by their sum). */
+typedef struct {
+    int n;
+    const double* v;
+    const double* w;
+    double wsum;
+} shape_t;
+
+static shape_t shape_of(int n, const double* v, const double* w)
+{
+    shape_t L = {n > 0 ? n : 0, v, w, 0.0};
+    for (int k = 0; k < L.n; ++k) L.wsum += w[k];
+    return L;
+}
+
+/* Profile density at u = v_c + w for Doppler width b (see file header). */
+static double profile(const shape_t* L, double u, double b)
+{
+    const double norm = 1.0 / (b * sqrt(M_PI));
+    if (L->n == 0) {
+        double x = u / b;
+        return exp(-x * x) * norm;
+    }
+    double p = 0.0;
+    for (int k = 0; k < L->n; ++k) {
+        double x = (u - L->v[k]) / b;
+        p += L->w[k] * exp(-x * x);
+    }
+    return p / L->wsum * norm;
+}
+
 /* One ray step through one cell for all channels.  Returns the raw per-step
  * sums sum_c f_c I_c beta_c, sum_c f_c (1-beta_c) and sum_c f_c through the
  * pointers (not multiplied by a s). */
-static void cell_step(int nch, double vmin, double dv, double* I,
+static void cell_step(const shape_t* L, int nch, double vmin, double dv, double* I,
                       double kappa, double eta, double b, double w, double s,
                       double* sj, double* sl, double* se)
 {
     double js = 0.0, ls = 0.0, es = 0.0;
-    const double norm = 1.0 / (b * sqrt(M_PI));
     for (int c = 0; c < nch; ++c) {
         double v = vmin + (c + 0.5) * dv;
-        double x = (v + w) / b;
-        double p = exp(-x * x) * norm;
+        double p = profile(L, v + w, b);
         double f = p * dv;
         double tau = kappa * p * s;
         double e, beta, omb;
@@ -207,14 +242,16 @@ int orc1d_ray_steps(int n, const double* R, double b, int* shell, double* s, dou
  *   impact[j], area[j]: ray impact parameter and weight (annulus area).
  * Outputs (any may be NULL): raw per-shell sums Jraw, Lraw (see file header),
  * Wraw = sum a s, Eraw = sum a s sum_c f_c; I_out[j*nch + c] emergent intensity;
- * cons = sum_j a_j dv sum_c (I_bg - I_out). */
+ * cons = sum_j a_j dv sum_c (I_bg - I_out).  n_hf, hf_v, hf_w: line shape
+ * (n_hf = 0: single Gaussian). */
 void orc1d_march(int n, const double* R, const double* vr, const double* bD,
                  const double* kappa, const double* eta,
                  int n_rays, const double* impact, const double* area,
                  int nch, double vmin, double dv, double I_bg, int n_threads,
                  double* Jraw, double* Lraw, double* Wraw, double* Eraw,
-                 double* I_out, double* cons)
+                 double* I_out, double* cons, int n_hf, const double* hf_v, const double* hf_w)
 {
+    const shape_t shape = shape_of(n_hf, hf_v, hf_w);
     int nt = nthreads_of(n_threads);
     accum_t* acc = accum_alloc(nt, n);
 #ifdef _OPENMP
@@ -241,7 +278,7 @@ void orc1d_march(int n, const double* R, const double* vr, const double* bD,
                 int k = shell[i];
                 double w = vr[k] * mu[i];
                 double sj, sl, se;
-                cell_step(nch, vmin, dv, I, kappa[k], eta[k], bD[k], w, s[i], &sj, &sl, &se);
+                cell_step(&shape, nch, vmin, dv, I, kappa[k], eta[k], bD[k], w, s[i], &sj, &sl, &se);
                 A->J[k] += a * s[i] * sj;
                 A->L[k] += a * s[i] * sl;
                 A->W[k] += a * s[i];
@@ -362,14 +399,16 @@ void orc3d_path_sums(int N, int n_dir, const double* dirs, double* out)
  * all directions; ray weight a = delta^2 |d_m|.  Per-cell inputs are FP64:
  * velocity components, Doppler width, kappa, eta.  Outputs as orc1d_march;
  * I_out[(dir*N*N + j*N + i)*nch + c] is the intensity leaving the downstream
- * face for ray (i, j) of each direction (may be NULL). */
+ * face for ray (i, j) of each direction (may be NULL).  Line shape as in
+ * orc1d_march. */
 void orc3d_march(int N, double delta, const double* vx, const double* vy, const double* vz,
                  const double* bD, const double* kappa, const double* eta,
                  int n_dir, const double* dirs,
                  int nch, double vmin, double dv, double I_bg, int n_threads,
                  double* Jraw, double* Lraw, double* Wraw, double* Eraw,
-                 double* I_out, double* cons)
+                 double* I_out, double* cons, int n_hf, const double* hf_v, const double* hf_w)
 {
+    const shape_t shape = shape_of(n_hf, hf_v, hf_w);
     long nc = (long)N * N * N;
     int nt = nthreads_of(n_threads);
     accum_t* acc = accum_alloc(nt, nc);
@@ -412,7 +451,7 @@ void orc3d_march(int N, double delta, const double* vx, const double* vy, const 
                 double s = len[k] * delta;
                 double w = vx[cc] * d[0] + vy[cc] * d[1] + vz[cc] * d[2];
                 double sj, sl, se;
-                cell_step(nch, vmin, dv, I, kappa[cc], eta[cc], bD[cc], w, s, &sj, &sl, &se);
+                cell_step(&shape, nch, vmin, dv, I, kappa[cc], eta[cc], bD[cc], w, s, &sj, &sl, &se);
                 A->J[cc] += a * s * sj;
                 A->L[cc] += a * s * sl;
                 A->W[cc] += a * s;
@@ -612,7 +651,7 @@ enum { OCT_ROOT, OCT_SPLIT, OCT_SIDE, OCT_TERM, OCT_WRAP, OCT_STEPS, OCT_NSTAT }
  * the path bookkeeping (W) is done.  'plain' traces the single line without
  * splitting, side rays or termination (lines of sight for maps); I_end then
  * receives its final intensity. */
-static void oct_trace_root(const oct_geom_t* G, int i, int j, double root_cm,
+static void oct_trace_root(const oct_geom_t* G, const shape_t* shape, int i, int j, double root_cm,
                            const double* dvec, const double* vx, const double* vy, const double* vz,
                            const double* bD, const double* kappa, const double* eta,
                            int nch, double vmin, double dv, double I_bg, int plain,
@@ -738,7 +777,7 @@ static void oct_trace_root(const oct_geom_t* G, int i, int j, double root_cm,
                 double in = 0.0, out = 0.0;
                 for (int c = 0; c < nch; ++c) in += I[c];
                 double sj, sl, se;
-                cell_step(nch, vmin, dv, I, kappa[g], eta[g], bD[g], w, s_cm, &sj, &sl, &se);
+                cell_step(shape, nch, vmin, dv, I, kappa[g], eta[g], bD[g], w, s_cm, &sj, &sl, &se);
                 for (int c = 0; c < nch; ++c) out += I[c];
                 if (A) {
                     A->J[g] += a_w * s_cm * sj;
@@ -774,15 +813,17 @@ static void oct_trace_root(const oct_geom_t* G, int i, int j, double root_cm,
 /* March one transition through an octree for all directions (see above).
  * Per-cell FP64 inputs over all cells (only leaves are used).  Raw sums as
  * orc3d_march; 'stats' receives OCT_NSTAT counters (may be NULL).  With
- * nch == 0 only W is produced (kappa, eta, velocities may be NULL). */
+ * nch == 0 only W is produced (kappa, eta, velocities may be NULL).  Line
+ * shape as in orc1d_march. */
 void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_cm,
                   const double* vx, const double* vy, const double* vz,
                   const double* bD, const double* kappa, const double* eta,
                   int n_dir, const double* dirs,
                   int nch, double vmin, double dv, double I_bg, int n_threads,
                   double* Jraw, double* Lraw, double* Wraw, double* Eraw, double* cons,
-                  long long* stats)
+                  long long* stats, int n_hf, const double* hf_v, const double* hf_w)
 {
+    const shape_t shape = shape_of(n_hf, hf_v, hf_w);
     int nt = nthreads_of(n_threads);
     accum_t* acc = accum_alloc(nt, n_cells);
     long long* st = (long long*)calloc((size_t)nt * OCT_NSTAT, sizeof(long long));
@@ -805,7 +846,7 @@ void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_c
             const int rem = (int)(r % ((long)N * N));
             oct_geom_t G;
             oct_geom_init(&G, N, Lmax, child, dirs + 3 * q);
-            oct_trace_root(&G, rem % N, rem / N, root_cm, dirs + 3 * q, vx, vy, vz, bD, kappa, eta,
+            oct_trace_root(&G, &shape, rem % N, rem / N, root_cm, dirs + 3 * q, vx, vy, vz, bD, kappa, eta,
                            nch, vmin, dv, I_bg, 0, &acc[tid], st + (size_t)tid * OCT_NSTAT, &S, I, NULL);
         }
         free(S.r);
@@ -825,12 +866,15 @@ void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_c
 /* +z map of an octree: one straight line of sight per root surface element
  * (x, y) on the level-0 ray lattice of the +z direction (transverse offset
  * h_Lmax / 2 from the element's corner), marched without accumulation.
- * I_out[(y N + x) * nch + c] is the intensity leaving the top face. */
+ * I_out[(y N + x) * nch + c] is the intensity leaving the top face.  Line
+ * shape as in orc1d_march. */
 void orcoct_map_z(int N, int Lmax, const int* child, double root_cm,
                   const double* vx, const double* vy, const double* vz,
                   const double* bD, const double* kappa, const double* eta,
-                  int nch, double vmin, double dv, double I_bg, int n_threads, double* I_out)
+                  int nch, double vmin, double dv, double I_bg, int n_threads, double* I_out,
+                  int n_hf, const double* hf_v, const double* hf_w)
 {
+    const shape_t shape = shape_of(n_hf, hf_v, hf_w);
     int nt = nthreads_of(n_threads);
     const double dz[3] = {0.0, 0.0, 1.0};
 #ifdef _OPENMP
@@ -846,7 +890,7 @@ void orcoct_map_z(int N, int Lmax, const int* child, double root_cm,
         for (long r = 0; r < (long)N * N; ++r) {
             oct_geom_t G;
             oct_geom_init(&G, N, Lmax, child, dz);
-            oct_trace_root(&G, (int)(r % N), (int)(r / N), root_cm, dz, vx, vy, vz, bD, kappa, eta,
+            oct_trace_root(&G, &shape, (int)(r % N), (int)(r / N), root_cm, dz, vx, vy, vz, bD, kappa, eta,
                            nch, vmin, dv, I_bg, 1, NULL, st, &S, I, I_out + (size_t)r * nch);
         }
         free(S.r);

@@ -547,3 +547,105 @@ def test_p10_infall_gives_blue_asymmetry():
     sp = oracle.spectra_1d(mol, m, spec, 2.73, run.x, 0, impact=np.array([1e-4 * m.r_out[-1]]))
     half = spec.n_channels // 2
     assert sp[0, :half].max() > sp[0, half:].max()
+
+
+# ---------------------------------------------------------------------------
+# Hyperfine multiplets with LTE between the components (Sect. 1)
+# ---------------------------------------------------------------------------
+
+HF_V = np.array([-0.62, 0.0, 0.37]) * KMS      # asymmetric, so a sign error shows
+HF_W = np.array([1.0, 5.0, 3.0])
+
+
+def _hf_profile(v, b):
+    """sum_k (w_k / sum w) exp(-((v - v_k)/b)^2) / (b sqrt(pi)) written out."""
+    p = np.zeros_like(v)
+    for vk, wk in zip(HF_V, HF_W / HF_W.sum()):
+        p += wk * np.exp(-((v - vk) / b) ** 2)
+    return p / (b * math.sqrt(math.pi))
+
+
+def test_hf_homogeneous_sphere_closed_form():
+    """Uniform static sphere, three components: the emergent spectrum is the
+    slab solution with tau_c = kappa L sum_k w_k p_k(c)."""
+    spec = _spec(96, 1.5)
+    nsh, Rtot = 6, 3.0e17
+    R = Rtot * (np.arange(nsh) + 1.0) / nsh
+    b = np.full(nsh, 0.12 * KMS)
+    kap, eta = _uniform_kappa_eta(nsh, 5.0e-13, 3.0e-27)
+    impact = np.array([0.05, 0.5, 0.93]) * Rtot
+    I_bg = 1.1e-15
+    res = oracle.march_1d(R, np.zeros(nsh), b, kap, eta, impact, np.ones(3), spec, I_bg,
+                          want_I=True, shape=(HF_V, HF_W))
+    v = spec.v_min + (np.arange(spec.n_channels) + 0.5) * spec.dv
+    p = _hf_profile(v, b[0])
+    S = eta[0] / kap[0]
+    for j, bj in enumerate(impact):
+        tau = kap[0] * p * 2 * math.sqrt(Rtot ** 2 - bj ** 2)
+        expect = S * (1 - np.exp(-tau)) + I_bg * np.exp(-tau)
+        assert np.allclose(res.I_out[j], expect, rtol=1e-12, atol=0)
+    # the three components are resolved: the spectrum has three local maxima
+    sp = res.I_out[0] - I_bg
+    peaks = np.flatnonzero((sp[1:-1] > sp[:-2]) & (sp[1:-1] > sp[2:]))
+    assert len(peaks) == 3
+
+
+def test_hf_moving_cube_closed_form():
+    """Uniform cube moving at u along +z, line of sight +z: the components
+    appear at channel velocity v_k - u (the sign convention of the shift)."""
+    N, delta = 4, 1.0e16
+    spec = _spec(96, 1.5)
+    nc = N ** 3
+    b, u = 0.1 * KMS, 0.21 * KMS
+    kap, eta = 3.0e-13, 2.0e-27
+    I_bg = 2.0e-15
+    res = oracle.march_3d(N, delta, np.zeros(nc), np.zeros(nc), np.full(nc, u), np.full(nc, b),
+                          np.full(nc, kap), np.full(nc, eta), np.array([[0.0, 0.0, 1.0]]), spec,
+                          I_bg, want_I=True, shape=(HF_V, HF_W))
+    v = spec.v_min + (np.arange(spec.n_channels) + 0.5) * spec.dv
+    tau = kap * _hf_profile(v + u, b) * N * delta
+    expect = eta / kap * (1 - np.exp(-tau)) + I_bg * np.exp(-tau)
+    for r in range(N * N):
+        assert np.allclose(res.I_out[0, r], expect, rtol=1e-12, atol=0)
+
+
+def test_hf_single_and_split_components():
+    """One component of any strength at offset 0 is the plain Gaussian; one
+    component at offset v0 is the plain line of gas moving at -v0 along the
+    line of sight; a component split into two at the same offset is unchanged."""
+    N, delta = 3, 2.0e16
+    spec = _spec(64, 1.5)
+    nc = N ** 3
+    rng = np.random.default_rng(7)
+    b = rng.uniform(0.1, 0.2, nc) * KMS
+    kap = rng.uniform(1e-13, 6e-13, nc)
+    eta = kap * rng.uniform(1e-15, 3e-15, nc)
+    uz = rng.uniform(-0.2, 0.2, nc) * KMS
+    z = np.zeros(nc)
+    d = np.array([[0.0, 0.0, 1.0]])
+    args = (N, delta, z, z, uz, b, kap, eta, d, spec, 1.5e-15)
+    plain = oracle.march_3d(*args, want_I=True)
+    one = oracle.march_3d(*args, want_I=True, shape=([0.0], [2.5]))
+    for f in ("Jraw", "Lraw", "W", "E", "I_out"):
+        assert np.allclose(getattr(plain, f), getattr(one, f), rtol=1e-14, atol=0)
+    v0 = 0.07 * KMS
+    shifted = oracle.march_3d(*args, want_I=True, shape=([v0], [1.0]))
+    moved = oracle.march_3d(N, delta, z, z, uz - v0, b, kap, eta, d, spec, 1.5e-15, want_I=True)
+    assert np.allclose(shifted.I_out, moved.I_out, rtol=1e-12, atol=0)
+    assert np.allclose(shifted.Jraw, moved.Jraw, rtol=1e-12, atol=0)
+    split = oracle.march_3d(*args, want_I=True, shape=([v0, v0], [0.25, 0.75]))
+    assert np.allclose(split.I_out, shifted.I_out, rtol=1e-13, atol=0)
+    assert np.allclose(split.Lraw, shifted.Lraw, rtol=1e-13, atol=0)
+
+
+def test_hf_channel_fractions_sum_to_one():
+    """The multiplet's channel fractions still sum to one (sum_k w_k = 1 after
+    normalisation) when the band covers every component."""
+    mol = _thin_two_level()
+    m = synth.cloud_1d_log(n_shells=12)
+    spec = synth.Spectral.symmetric(256, 2.0)
+    prob = oracle._Problem(mol, m.n_H2, m.T_kin, m.b_turb, m.abundance, spec, 2.73)
+    imp = oracle.equidistant_impacts(m.r_out[-1], 20)
+    r = oracle.march_1d(m.r_out, m.v_r, prob.bD, np.zeros(12), np.zeros(12), imp,
+                        oracle.ray_areas_1d(m.r_out[-1], imp), spec, 1.0, shape=(HF_V, HF_W))
+    assert np.allclose(r.E / r.W, 1.0, atol=1e-12)
