@@ -198,6 +198,24 @@ miloc_status miloc_set_spectral(miloc_ctx* ctx, int n_channels, double v_min_cms
  * Eq. (1)).  Default 2.73 K.  T_bg >= 0 (0 => no background). */
 miloc_status miloc_set_background(miloc_ctx* ctx, double T_bg_K);
 
+/* Hyperfine structure of transition `trans` with LTE between its components
+ * (Sect. 1; the NH3(1,1) and HCN(1-0) examples of Sect. 3): the line profile
+ * becomes sum_k w_k phi(v - dv_k), phi the cell's Gaussian, component k
+ * centred at channel velocity dv_cms[k] - (u . d).  strength[k] > 0 are
+ * relative strengths (normalised to sum 1 here); n_comp in
+ * 0..MILOC_MAX_HF_COMPONENTS, 0 restores the single Gaussian.  The arrays
+ * are copied.  The statistical equilibrium treats the multiplet as one
+ * transition.  Needs the molecule; reset by miloc_load_molecule.  Every
+ * transition's channel window then spans the lowest to the highest offset
+ * of all multiplets plus the profile cut, and the band check of
+ * miloc_set_spectral includes the offsets.  The 1D request loop
+ * (miloc_server_*) serves single-Gaussian lines only.  Errors: MILOC_ESTATE
+ * without a molecule, MILOC_EINVAL for a bad index, count, offset or
+ * strength (state unchanged). */
+#define MILOC_MAX_HF_COMPONENTS 32
+miloc_status miloc_set_hyperfine(miloc_ctx* ctx, int trans, int n_comp, const double* dv_cms,
+                                 const double* strength);
+
 /* 3D ray directions: the 12*nside^2 HEALPix pixel centres (Sect. 2.2; 48 for
  * nside = 2, the default).  nside 1..8. */
 miloc_status miloc_set_directions_healpix(miloc_ctx* ctx, int nside);

@@ -96,6 +96,7 @@ SIGNATURES = {
                                              _i64p, _i64p, _ip, ctypes.POINTER(ctypes.c_uint32), _i64p]),
     "miloc_set_spectral": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
     "miloc_set_background": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "miloc_set_hyperfine": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     "miloc_set_directions_healpix": (ctypes.c_int, [_vp, ctypes.c_int]),
     "miloc_set_directions": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "miloc_set_march_precision": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -363,6 +364,17 @@ class Context:
 
     def set_background(self, T_bg: float):
         self._check(self._lib.miloc_set_background(self._h, float(T_bg)))
+
+    def set_hyperfine(self, trans: int, dv_cms, strength):
+        """Hyperfine components of one transition (LTE between them): velocity
+        offsets [cm/s] and relative strengths; empty arrays restore the single
+        Gaussian."""
+        v = _f64(dv_cms).ravel()
+        w = _f64(strength).ravel()
+        if v.shape != w.shape:
+            raise ValueError("dv_cms and strength differ in length")
+        self._check(self._lib.miloc_set_hyperfine(self._h, int(trans), int(v.size),
+                                                  _ptr(v, ctypes.c_double), _ptr(w, ctypes.c_double)))
 
     def set_directions_healpix(self, nside: int):
         self._check(self._lib.miloc_set_directions_healpix(self._h, int(nside)))

@@ -107,12 +107,12 @@ __device__ __forceinline__ double group_sum(double v)
 // c* = -(chalf + w), clipped to the band.  frac = clo - c*.
 template <typename T>
 __device__ __forceinline__ void window(double w, double chalf, T Kw, T ibs, int nch,
-                                       int& clo, int& chi, T& frac)
+                                       int& clo, int& chi, T& frac, double dlo = 0.0, double dhi = 0.0)
 {
     const double cstar = -(chalf + w);
     const double hw = (double)(Kw * fast_rcp(ibs));
-    int lo = (int)ceil(cstar - hw);
-    int hi = (int)floor(cstar + hw);
+    int lo = (int)ceil(cstar + dlo - hw);
+    int hi = (int)floor(cstar + dhi + hw);
     lo = lo < 0 ? 0 : lo;
     hi = hi > nch - 1 ? nch - 1 : hi;
     clo = lo;
@@ -195,11 +195,15 @@ __device__ __forceinline__ void move_transverse(int& c, int& idx, int s, int st,
 // Window table of one direction: for every cell the first channel of its
 // window, the number of window channels and the profile argument of the first
 // channel, all from the FP64 line-of-sight velocity (Sect. 3.1: Doppler shift
-// per step; App. A.2: only channels where the profile is significant).
+// per step; App. A.2: only channels where the profile is significant).  With
+// hyperfine components the window runs from the lowest to the highest
+// component centre (offsets dlo <= 0 <= dhi channels from the line centre)
+// plus the cut on either side; the profile argument stays that of the
+// reference centre.
 template <typename T>
 __global__ void window_table_kernel(int nc, int n_dir, const DirDev* __restrict__ dirs,
                                     const float4* __restrict__ vel, const double* __restrict__ bD,
-                                    double dv, double chalf, double K, int nch,
+                                    double dv, double chalf, double K, int nch, double dlo, double dhi,
                                     typename V4<T>::type* __restrict__ win)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -211,8 +215,8 @@ __global__ void window_table_kernel(int nc, int n_dir, const DirDev* __restrict_
     const double cstar = -(chalf + w);
     const double bc = bD[k] / dv;                 // Doppler width in channels
     const double hw = K * bc;
-    int lo = (int)ceil(cstar - hw);
-    int hi = (int)floor(cstar + hw);
+    int lo = (int)ceil(cstar + dlo - hw);
+    int hi = (int)floor(cstar + dhi + hw);
     lo = lo < 0 ? 0 : lo;
     hi = hi > nch - 1 ? nch - 1 : hi;
     const int n = hi >= lo ? hi - lo + 1 : 0;
@@ -264,22 +268,45 @@ __device__ __forceinline__ double omb_any(double tau)
     return omb;
 }
 
+// Line shape at scaled profile argument xs (the reference centre at 0):
+// exp2(-xs^2), or with HF the hyperfine multiplet (Sect. 1, LTE between the
+// components): sum_k w_k exp2(-(xs - d_k ibs)^2) over the transition's
+// components {d_k = offset in channels, w_k = strength, sum 1}.
+template <bool HF, typename T>
+__device__ __forceinline__ T line_shape(T xs, T ibs, const typename V2<T>::type* __restrict__ hf, int hfk)
+{
+    if constexpr (!HF) {
+        return fast_exp2(-xs * xs);
+    } else {
+        T e = 0;
+        for (int k = 0; k < hfk; ++k) {
+            const typename V2<T>::type c = hf[k];
+            const T y = xs - c.x * ibs;
+            e += c.y * fast_exp2(-y * y);
+        }
+        return e;
+    }
+}
+
 // The channel window of one step for one ray (Sect. 2: I e^-tau + S(1 -
 // e^-tau) per channel, absorbed counts and the diagonal operator summed):
 // channels clo .. clo + nwin - 1, profile argument x_j = x0 + j ibs (scaled
 // so that the profile is exp2(-x^2)), tau_j = kl e_j, emission el e_j beta_j.
 // Partial sums of this lane in sj, sl.  The series/exact choice for 1 - beta
-// is made once per step for the whole wavefront.
-template <int LANES, typename T>
+// is made once per step for the whole wavefront (with HF the multiplet's
+// profile peaks at most at 1, so |kl| still bounds every |tau_j|).
+template <int LANES, typename T, bool HF = false>
 __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
-                                                T kl, T el, T& sj, T& sl)
+                                                T kl, T el, T& sj, T& sl,
+                                                const typename V2<T>::type* __restrict__ hf = nullptr,
+                                                int hfk = 0)
 {
     const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
     T* __restrict__ row = I + clo;
     if (thin) {
         for (int j = lane; j < nwin; j += LANES) {
             const T xs = (T)j * ibs + x0;
-            const T ec = fast_exp2(-xs * xs);
+            const T ec = line_shape<HF, T>(xs, ibs, hf, hfk);
             const T omb = omb_thin(kl * ec);
             const T Iin = row[j];
             const T u = ec - ec * omb;                 // e_c beta_c
@@ -290,7 +317,7 @@ __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int
     } else {
         for (int j = lane; j < nwin; j += LANES) {
             const T xs = (T)j * ibs + x0;
-            const T ec = fast_exp2(-xs * xs);
+            const T ec = line_shape<HF, T>(xs, ibs, hf, hfk);
             const T omb = omb_any(kl * ec);
             const T Iin = row[j];
             const T u = ec - ec * omb;
@@ -303,7 +330,7 @@ __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int
 
 }  // namespace
 
-template <typename T, int LANES, bool ACCUM>
+template <typename T, int LANES, bool ACCUM, bool HF>
 __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
 {
     using T2 = typename V2<T>::type;
@@ -352,6 +379,7 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
                              : nullptr;
     const T aw = (T)D.aw;
     const int ns = D.nsteps;
+    const T2* __restrict__ hfrow = HF ? p.hf + (size_t)t * p.hfk : nullptr;
     // Invalid channel slots read and write a private dummy word in the
     // ray's padding so that no lane touches another ray's channels.
     T* __restrict__ dummy = I + p.nch + lane;
@@ -404,7 +432,7 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         const T kl = kv.x * rec.len;      // tau at the line centre
         const T el = kv.y * rec.len;
         T sj = 0, sl = 0;
-        window_channels<LANES, T>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
+        window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, hfrow, p.hfk);
         (void)dummy;
         if (ACCUM) {
             sj = group_sum<LANES>(sj);
@@ -613,7 +641,7 @@ struct SpanStack {
 // grid's: channel window of the (direction, leaf) pair, I e^-tau + S(1 -
 // e^-tau); with accumulation, the step's absorbed-count and Lambda sums go to
 // the per-step buffer E (required then), summed per cell by gather_oct_kernel.
-template <typename T, int LANES, bool ACCUM>
+template <typename T, int LANES, bool ACCUM, bool HF>
 __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
 {
     using T2 = typename V2<T>::type;
@@ -650,6 +678,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         const uint2* __restrict__ rec = p.steps + tr.off;
         const T aw = (T)p.aw[tr.q];
         const T Ibg = p.Ibg[t];
+        const T2* __restrict__ hfrow = HF ? p.hf + (size_t)t * p.hfk : nullptr;
         const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
         T2q* __restrict__ Et = p.E ? p.E + (size_t)tr.off * p.estride + (t - p.trans_offset) : nullptr;
         int qn = 0, qs0 = 0;
@@ -736,7 +765,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
-            window_channels<LANES, T>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl);
+            window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, hfrow, p.hfk);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
@@ -782,7 +811,7 @@ __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); 
 // runs.  With p.lds_acc the per-step sums go to per-shell LDS accumulators
 // (LDS atomics do not stall the next step's loads), flushed to the FP64
 // global sums once per workgroup; otherwise each step issues two FP64 atomics.
-template <typename T, int LANES, bool ACCUM, bool TRANS_GROUPS = false>
+template <typename T, int LANES, bool ACCUM, bool TRANS_GROUPS = false, bool HF = false>
 __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0, int t_in, unsigned char* smem_raw)
 {
     using T2 = typename V2<T>::type;
@@ -812,6 +841,7 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
         const int nsteps = 2 * nin + 2;
         const T2* __restrict__ rec = p.steps + p.ray_off[j];
         const T Ibg = p.Ibg[t];
+        const T2* __restrict__ hfrow = HF ? p.hf + (size_t)t * p.hfk : nullptr;
         for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
         auto shell_of = [&](int s) {
             return s < nin ? n - 1 - s : (s <= nin + 1 ? kmin : kmin + (s - nin - 1));
@@ -839,10 +869,14 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
             }
             int clo, chi;
             T frac;
-            window<T>((double)r.y, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
+            if (HF)
+                window<T>((double)r.y, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac, p.hf_lo, p.hf_hi);
+            else
+                window<T>((double)r.y, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
             const T tl = r.x;
             T sj = 0, sl = 0;
-            window_channels<LANES, T>(I, lane, clo, chi - clo + 1, frac * sv.y, sv.y, kev.x * tl, kev.y * tl, sj, sl);
+            window_channels<LANES, T, HF>(I, lane, clo, chi - clo + 1, frac * sv.y, sv.y, kev.x * tl, kev.y * tl,
+                                          sj, sl, hfrow, p.hfk);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
@@ -952,12 +986,12 @@ __global__ __launch_bounds__(256) void shell_weights_kernel(int n, const double*
     if (lane == 0) out[k] = bsq ? (w > 0 ? dv / (bsq[k] * w) : 0.0) : w;
 }
 
-template <typename T, int LANES, bool ACCUM>
+template <typename T, int LANES, bool ACCUM, bool HF>
 __global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
 {
     extern __shared__ unsigned char smem_raw[];
     const int rpb = blockDim.x / LANES;
-    march1d_block<T, LANES, ACCUM>(p, blockIdx.x * rpb, p.trans_offset + blockIdx.y, smem_raw);
+    march1d_block<T, LANES, ACCUM, false, HF>(p, blockIdx.x * rpb, p.trans_offset + blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------------------- SE solve
@@ -1347,17 +1381,17 @@ hipError_t launch_prepare(hipStream_t s, int nc, const MolDev* mol, int ntr, con
 }
 
 hipError_t launch_window_table(hipStream_t s, int nc, int n_dir, const DirDev* dirs, const float4* vel,
-                               const double* bD, double dv, double chalf, double K, int nch, void* win,
-                               bool fp64)
+                               const double* bD, double dv, double chalf, double K, int nch, double dlo,
+                               double dhi, void* win, bool fp64)
 {
     const int bs = 256;
     const dim3 grid((nc + bs - 1) / bs, n_dir);
     if (fp64)
         hipLaunchKernelGGL(window_table_kernel<double>, grid, dim3(bs), 0, s, nc, n_dir, dirs, vel, bD, dv,
-                           chalf, K, nch, reinterpret_cast<double4*>(win));
+                           chalf, K, nch, dlo, dhi, reinterpret_cast<double4*>(win));
     else
         hipLaunchKernelGGL(window_table_kernel<float>, grid, dim3(bs), 0, s, nc, n_dir, dirs, vel, bD, dv,
-                           chalf, K, nch, reinterpret_cast<float4*>(win));
+                           chalf, K, nch, dlo, dhi, reinterpret_cast<float4*>(win));
     return hipGetLastError();
 }
 
@@ -1377,7 +1411,7 @@ int rays_per_block(int lanes, int nch)
     return rpb;
 }
 
-template <typename T, int LANES, bool ACCUM>
+template <typename T, int LANES, bool ACCUM, bool HF>
 hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
 {
     // Channel vectors are padded by 16 words so that the rays of one
@@ -1394,15 +1428,15 @@ hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
     const size_t shm = (size_t)a.queue_lds_offset + (size_t)rpb * LANES * 2 * sizeof(T);
     if (shm > 163840) return hipErrorInvalidValue;
     if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)march3d_kernel<T, LANES, ACCUM>,
+        hipError_t e = hipFuncSetAttribute((const void*)march3d_kernel<T, LANES, ACCUM, HF>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((march3d_kernel<T, LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
+    hipLaunchKernelGGL((march3d_kernel<T, LANES, ACCUM, HF>), grid, dim3(rpb * LANES), shm, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int LANES, bool ACCUM>
+template <typename T, int LANES, bool ACCUM, bool HF>
 hipError_t do_march1d(hipStream_t s, March1DArgs<T> a)
 {
     const int rpb = rays_per_block<T>(LANES, a.nch);
@@ -1410,29 +1444,42 @@ hipError_t do_march1d(hipStream_t s, March1DArgs<T> a)
     a.acc_lds_bytes = (int)((((size_t)a.n * 2 * sizeof(T)) + 15) & ~(size_t)15);
     a.lds_acc = ACCUM && ((size_t)a.acc_lds_bytes + (size_t)rpb * a.nch * sizeof(T) <= 65536) ? 1 : 0;
     const size_t shm = (a.lds_acc ? (size_t)a.acc_lds_bytes : 0) + (size_t)rpb * a.nch * sizeof(T);
-    hipLaunchKernelGGL((march1d_kernel<T, LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
+    hipLaunchKernelGGL((march1d_kernel<T, LANES, ACCUM, HF>), grid, dim3(rpb * LANES), shm, s, a);
     return hipGetLastError();
+}
+
+template <typename T, bool HF>
+hipError_t dispatch3d_hf(hipStream_t s, const March3DArgs<T>& a, int lanes, bool accum, int max_steps)
+{
+    if (lanes == 8)
+        return accum ? do_march3d<T, 8, true, HF>(s, a, max_steps) : do_march3d<T, 8, false, HF>(s, a, max_steps);
+    if (lanes == 16)
+        return accum ? do_march3d<T, 16, true, HF>(s, a, max_steps) : do_march3d<T, 16, false, HF>(s, a, max_steps);
+    if (lanes == 32)
+        return accum ? do_march3d<T, 32, true, HF>(s, a, max_steps) : do_march3d<T, 32, false, HF>(s, a, max_steps);
+    return accum ? do_march3d<T, 64, true, HF>(s, a, max_steps) : do_march3d<T, 64, false, HF>(s, a, max_steps);
 }
 
 template <typename T>
 hipError_t dispatch3d(hipStream_t s, const March3DArgs<T>& a, int lanes, bool accum, int max_steps)
 {
-    if (lanes == 8)
-        return accum ? do_march3d<T, 8, true>(s, a, max_steps) : do_march3d<T, 8, false>(s, a, max_steps);
-    if (lanes == 16)
-        return accum ? do_march3d<T, 16, true>(s, a, max_steps) : do_march3d<T, 16, false>(s, a, max_steps);
-    if (lanes == 32)
-        return accum ? do_march3d<T, 32, true>(s, a, max_steps) : do_march3d<T, 32, false>(s, a, max_steps);
-    return accum ? do_march3d<T, 64, true>(s, a, max_steps) : do_march3d<T, 64, false>(s, a, max_steps);
+    return a.hf ? dispatch3d_hf<T, true>(s, a, lanes, accum, max_steps)
+                : dispatch3d_hf<T, false>(s, a, lanes, accum, max_steps);
+}
+
+template <typename T, bool HF>
+hipError_t dispatch1d_hf(hipStream_t s, const March1DArgs<T>& a, int lanes, bool accum)
+{
+    if (lanes == 8) return accum ? do_march1d<T, 8, true, HF>(s, a) : do_march1d<T, 8, false, HF>(s, a);
+    if (lanes == 16) return accum ? do_march1d<T, 16, true, HF>(s, a) : do_march1d<T, 16, false, HF>(s, a);
+    if (lanes == 32) return accum ? do_march1d<T, 32, true, HF>(s, a) : do_march1d<T, 32, false, HF>(s, a);
+    return accum ? do_march1d<T, 64, true, HF>(s, a) : do_march1d<T, 64, false, HF>(s, a);
 }
 
 template <typename T>
 hipError_t dispatch1d(hipStream_t s, const March1DArgs<T>& a, int lanes, bool accum)
 {
-    if (lanes == 8) return accum ? do_march1d<T, 8, true>(s, a) : do_march1d<T, 8, false>(s, a);
-    if (lanes == 16) return accum ? do_march1d<T, 16, true>(s, a) : do_march1d<T, 16, false>(s, a);
-    if (lanes == 32) return accum ? do_march1d<T, 32, true>(s, a) : do_march1d<T, 32, false>(s, a);
-    return accum ? do_march1d<T, 64, true>(s, a) : do_march1d<T, 64, false>(s, a);
+    return a.hf ? dispatch1d_hf<T, true>(s, a, lanes, accum) : dispatch1d_hf<T, false>(s, a, lanes, accum);
 }
 }  // namespace
 
@@ -1502,7 +1549,7 @@ hipError_t do_gather3d(hipStream_t s, const Gather3DArgs<T>& a)
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a) { return do_gather3d(s, a); }
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<double>& a) { return do_gather3d(s, a); }
 
-template <typename T, int LANES>
+template <typename T, int LANES, bool HF>
 hipError_t do_march_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, bool accum)
 {
     constexpr int kGroupsPerBlock = 256 / LANES;
@@ -1513,16 +1560,18 @@ hipError_t do_march_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, boo
     hipError_t e = hipMemsetAsync(a.counter, 0, sizeof(unsigned long long), s);
     if (e != hipSuccess) return e;
     if (accum)
-        hipLaunchKernelGGL((march_oct_kernel<T, LANES, true>), dim3(blocks), dim3(256), shm, s, a);
+        hipLaunchKernelGGL((march_oct_kernel<T, LANES, true, HF>), dim3(blocks), dim3(256), shm, s, a);
     else
-        hipLaunchKernelGGL((march_oct_kernel<T, LANES, false>), dim3(blocks), dim3(256), shm, s, a);
+        hipLaunchKernelGGL((march_oct_kernel<T, LANES, false, HF>), dim3(blocks), dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t dispatch_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, bool accum, int lanes)
 {
-    return lanes == 8 ? do_march_oct<T, 8>(s, a, groups, accum) : do_march_oct<T, 16>(s, a, groups, accum);
+    if (a.hf)
+        return lanes == 8 ? do_march_oct<T, 8, true>(s, a, groups, accum) : do_march_oct<T, 16, true>(s, a, groups, accum);
+    return lanes == 8 ? do_march_oct<T, 8, false>(s, a, groups, accum) : do_march_oct<T, 16, false>(s, a, groups, accum);
 }
 
 template <typename T>

@@ -87,6 +87,8 @@ struct March3DArgs {
     int ich;                             // LDS stride of one ray's channel vector
     int queue_lds_offset;                // LDS offset of the per-ray accumulation queues
     int ntr_total;                       // transitions in ke / acc (cell-major stride)
+    const typename V2<T>::type* hf;      // hyperfine components [ntr_total][hfk] {offset / dv, strength}, or null
+    int hfk;                             // components per transition (zero-strength padding)
 };
 
 // Per-cell gather of the per-step partial sums written by march3d, for the
@@ -122,6 +124,9 @@ struct March1DArgs {
     int ntr_total;                       // transitions in ke / acc (cell-major stride)
     int lds_acc;                         // per-shell LDS accumulators (set by the launcher)
     int acc_lds_bytes;                   // their size
+    const typename V2<T>::type* hf;      // hyperfine components as in March3DArgs, or null
+    int hfk;
+    double hf_lo, hf_hi;                 // lowest / highest component offset (channels; <= 0, >= 0)
 };
 
 struct SEArgs {
@@ -223,6 +228,8 @@ struct OctMarchArgs {
     unsigned long long* counter;         // work counter, zero at launch
     T* stack;                            // [groups][depth][ich] saved vectors
     int depth;
+    const typename V2<T>::type* hf;      // hyperfine components as in March3DArgs, or null
+    int hfk;
 };
 
 // Stride (elements) of an octree march channel vector, in LDS and in the
@@ -243,7 +250,8 @@ hipError_t launch_prepare(hipStream_t s, int nc, const MolDev* mol, int ntr, con
 hipError_t launch_lte(hipStream_t s, int nc, const MolDev* mol, const double* Tkin, double* x);
 // Channel windows of every (direction, cell) of a regular grid.
 hipError_t launch_window_table(hipStream_t s, int nc, int n_dir, const DirDev* dirs, const float4* vel,
-                               const double* bD, double dv, double chalf, double K, int nch, void* win,
+                               const double* bD, double dv, double chalf, double K, int nch, double dlo,
+                               double dhi, void* win,
                                bool fp64);
 // max_steps: the longest step list of the launched directions (LDS staging).
 hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum,

@@ -127,6 +127,12 @@ struct miloc_ctx {
     double Kw = 0;
     int n_dir_dev = 0;
     std::vector<DirDev> dir_host;
+    // hyperfine multiplets per transition: offsets (cm/s) and strengths
+    // normalised to sum 1; empty = single Gaussian
+    std::vector<std::vector<double>> hf_v, hf_w;
+    int hfk = 0;                 // components per transition in d_hf (0: no multiplets)
+    double hf_lo = 0, hf_hi = 0; // lowest / highest offset over all transitions, channels
+    DevBuf d_hf;                 // [T][hfk] {offset / dv, strength}, zero-strength padding
 
     miloc_counters ctr{};
 };
@@ -449,6 +455,8 @@ miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, c
     a.counter = c->d_ocounter.as<unsigned long long>();
     a.stack = c->d_ostack.as<TT>();
     a.depth = accum ? c->oct_depth : 0;
+    a.hf = c->hfk ? c->d_hf.as<typename V2<TT>::type>() : nullptr;
+    a.hfk = c->hfk;
     HIPCHK(c, launch_march_oct(c->stream, a, groups, accum, c->lanes));
     return MILOC_OK;
 }
@@ -478,20 +486,34 @@ miloc_status ensure_static(miloc_ctx* c)
         }
         maxu = std::max(maxu, u + 5.0 * b[k]);
     }
+    // hyperfine components widen the line by their offset range
+    double vlo = 0.0, vhi = 0.0;
+    int hfk = 0;
+    for (int t = 0; t < c->T; ++t) {
+        hfk = std::max(hfk, (int)c->hf_v[t].size());
+        for (double v : c->hf_v[t]) {
+            vlo = std::min(vlo, v);
+            vhi = std::max(vhi, v);
+        }
+    }
     const double vmax = c->vmin + c->nch * c->dv;
-    if (-maxu < c->vmin || maxu > vmax) {
+    if (-maxu + vlo < c->vmin || maxu + vhi > vmax) {
         char buf[256];
         std::snprintf(buf, sizeof buf,
-                      "velocity band [%g, %g] cm/s does not contain |v| + 5 b = %g cm/s",
-                      c->vmin, vmax, maxu);
+                      "velocity band [%g, %g] cm/s does not contain the line: |v| + 5 b = %g cm/s "
+                      "beyond the component offsets [%g, %g] cm/s",
+                      c->vmin, vmax, maxu, vlo, vhi);
         return fail(c, MILOC_EINVAL, buf);
     }
+    c->hfk = hfk;
+    c->hf_lo = vlo / c->dv;
+    c->hf_hi = vhi / c->dv;
     const double Kd = fp64 ? kWindowK64 : kWindowK32;
     c->Kw = Kd * kSqrtLog2e;
     c->chalf = 0.5 + c->vmin / c->dv;
     // lanes per ray: the widest channel window over the cells (at most wmax
     // channels) is covered in one to three passes of the ray's lane group
-    const double wmax = 2.0 * Kd * maxb / c->dv + 2.0;
+    const double wmax = 2.0 * Kd * maxb / c->dv + 2.0 + (vhi - vlo) / c->dv;
     if (c->kind == 3)
         c->lanes = wmax <= 32.0 ? 8 : (wmax <= 64.0 ? 16 : 32);
     else if (c->kind == 4)
@@ -624,7 +646,7 @@ miloc_status ensure_static(miloc_ctx* c)
         HIPCHK(c, c->d_win.ensure((size_t)c->n_dir_dev * nc * 4 * tsz));
         HIPCHK(c, launch_window_table(c->stream, (int)nc, c->n_dir_dev, c->d_dirs.as<DirDev>(),
                                       c->d_vel.as<float4>(), c->d_bD.as<double>(), c->dv, c->chalf,
-                                      Kd, c->nch, c->d_win.p, fp64));
+                                      Kd, c->nch, c->hf_lo, c->hf_hi, c->d_win.p, fp64));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->d_cellv.release();
     } else {
@@ -632,6 +654,30 @@ miloc_status ensure_static(miloc_ctx* c)
         if (fp64) pack_cell_static<double>(c, b, cvb); else pack_cell_static<float>(c, b, cvb);
         HIPCHK(c, c->d_cellv.ensure(cvb.size()));
         HIPCHK(c, hipMemcpy(c->d_cellv.p, cvb.data(), cvb.size(), hipMemcpyHostToDevice));
+    }
+    if (hfk > 0) {
+        // transitions without a multiplet: one component at offset 0
+        std::vector<double> tab((size_t)c->T * hfk * 2, 0.0);
+        for (int t = 0; t < c->T; ++t) {
+            double* row = tab.data() + (size_t)t * hfk * 2;
+            if (c->hf_v[t].empty()) {
+                row[1] = 1.0;
+                continue;
+            }
+            for (size_t k = 0; k < c->hf_v[t].size(); ++k) {
+                row[2 * k] = c->hf_v[t][k] / c->dv;
+                row[2 * k + 1] = c->hf_w[t][k];
+            }
+        }
+        HIPCHK(c, c->d_hf.ensure(tab.size() * tsz));
+        if (fp64) {
+            HIPCHK(c, hipMemcpy(c->d_hf.p, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> tf(tab.begin(), tab.end());
+            HIPCHK(c, hipMemcpy(c->d_hf.p, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
+    } else {
+        c->d_hf.release();
     }
     HIPCHK(c, c->d_ke.ensure((size_t)c->T * nc * 2 * tsz));
     HIPCHK(c, c->d_acc.ensure((size_t)c->T * nc * sizeof(double2)));
@@ -698,6 +744,8 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.ntr_total = c->T;
         a.E = accum ? c->d_E.as<typename V2<TT>::type>() : nullptr;
         a.e_tstride = (size_t)c->total_steps * c->N * c->N;
+        a.hf = c->hfk ? c->d_hf.as<typename V2<TT>::type>() : nullptr;
+        a.hfk = c->hfk;
         int max_steps = 0;
         if (zdir) {
             max_steps = c->N;
@@ -725,6 +773,10 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.Kw = (TT)c->Kw;
         a.Iout = Iout;
         a.ntr_total = c->T;
+        a.hf = c->hfk ? c->d_hf.as<typename V2<TT>::type>() : nullptr;
+        a.hfk = c->hfk;
+        a.hf_lo = c->hf_lo;
+        a.hf_hi = c->hf_hi;
         // lines of sight run alone: 64 lanes shorten each step's channel loop
         e = launch_march1d(c->stream, a, accum ? c->lanes : 64, accum);
     }
@@ -855,6 +907,8 @@ miloc_status miloc_load_molecule(miloc_ctx* c, const miloc_molecule* m)
     c->nu.assign(m->nu_Hz, m->nu_Hz + T);
     c->gamma.assign(m->gamma_down, m->gamma_down + (size_t)L * L);
     c->mass_amu = m->mass_amu;
+    c->hf_v.assign(T, {});
+    c->hf_w.assign(T, {});
     c->has_mol = true;
     invalidate_model(c);
     return MILOC_OK;
@@ -989,6 +1043,30 @@ miloc_status miloc_set_spectral(miloc_ctx* c, int n_channels, double v_min_cms, 
     c->vmin = v_min_cms;
     c->dv = dv_cms;
     c->has_spec = true;
+    c->dirty = true;
+    c->has_rad = false;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_hyperfine(miloc_ctx* c, int trans, int n_comp, const double* dv_cms, const double* strength)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (!c->has_mol) return fail(c, MILOC_ESTATE, "molecule must be loaded first");
+    if (trans < 0 || trans >= c->T) return fail(c, MILOC_EINVAL, "transition index out of range");
+    if (n_comp < 0 || n_comp > MILOC_MAX_HF_COMPONENTS)
+        return fail(c, MILOC_EINVAL, "n_comp out of range 0..MILOC_MAX_HF_COMPONENTS");
+    if (n_comp > 0 && (!dv_cms || !strength)) return fail(c, MILOC_EINVAL, "NULL component array");
+    double sum = 0.0;
+    for (int k = 0; k < n_comp; ++k) {
+        if (!std::isfinite(dv_cms[k])) return fail(c, MILOC_EINVAL, "non-finite component offset");
+        if (!(strength[k] > 0) || !std::isfinite(strength[k]))
+            return fail(c, MILOC_EINVAL, "component strengths must be finite and > 0");
+        sum += strength[k];
+    }
+    c->hf_v[trans].assign(dv_cms, dv_cms + n_comp);
+    c->hf_w[trans].resize(n_comp);
+    for (int k = 0; k < n_comp; ++k) c->hf_w[trans][k] = strength[k] / sum;
     c->dirty = true;
     c->has_rad = false;
     return MILOC_OK;
@@ -1309,7 +1387,8 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
         HIPCHK(c, zwin.ensure((size_t)c->nc * 4 * tsz));
         HIPCHK(c, launch_window_table(c->stream, (int)c->nc, 1, zdir.as<DirDev>(), c->d_vel.as<float4>(),
                                       c->d_bD.as<double>(), c->dv, c->chalf,
-                                      fp64 ? kWindowK64 : kWindowK32, c->nch, zwin.p, fp64));
+                                      fp64 ? kWindowK64 : kWindowK32, c->nch, c->hf_lo, c->hf_hi, zwin.p,
+                                      fp64));
         HIPCHK(c, out.ensure((size_t)n_los * c->nch * tsz));
         const int gpb = 256 / c->lanes;
         const int groups = (int)std::min<int64_t>(c->oct_groups, ((int64_t)n_los + gpb - 1) / gpb * gpb);
@@ -1345,7 +1424,8 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
         HIPCHK(c, zwin.ensure((size_t)c->nc * 4 * tsz));
         HIPCHK(c, launch_window_table(c->stream, (int)c->nc, 1, extra.as<DirDev>(), c->d_vel.as<float4>(),
                                       c->d_bD.as<double>(), c->dv, c->chalf,
-                                      fp64 ? kWindowK64 : kWindowK32, c->nch, zwin.p, fp64));
+                                      fp64 ? kWindowK64 : kWindowK32, c->nch, c->hf_lo, c->hf_hi, zwin.p,
+                                      fp64));
         s = fp64 ? launch_march<double>(c, 1, trans, false, out.as<double>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0, zwin.p)
                  : launch_march<float>(c, 1, trans, false, out.as<float>(), true, extra.as<DirDev>(), extra2.p, 1, nullptr, 0, zwin.p);
         if (s) return s;

@@ -387,6 +387,9 @@ bool admit_device(miloc_server* S, Request* r, const char* img)
     a.ntr_total = r->T;
     a.lds_acc = 1;
     a.acc_lds_bytes = (int)((((size_t)n * 2 * sizeof(float)) + 15) & ~(size_t)15);
+    a.hf = nullptr;                      // requests carry single-Gaussian lines
+    a.hfk = 0;
+    a.hf_lo = a.hf_hi = 0.0;
     d.mol = static_cast<const MolDev*>(dptr(lay.mol));
     d.nmolLb = static_cast<const double*>(dptr(lay.nmolLb));
     d.ke_w = static_cast<float2*>(dptr(lay.ke));
