@@ -13,12 +13,13 @@ Prints one JSON line.  ``value`` = nominal ray-cell-channel updates per second
 of the whole timed region (every channel counted, including those outside
 each step's profile window).  ``roofline`` describes the dominant kernel (the
 3D march) from its HIP-event durations; ``cpu_baseline`` is the FP64 oracle
-timed on this host's cores on a bounded sample of the same workload.  Two more
-objects by default: ``octree`` (64^3 root refined four levels, 2 timed ALI
-iterations, same per-step measures) and ``serving`` (a 512-request 1D stream:
-model solves/s with all requests queued at once, p50/p99 latency under Poisson
-arrivals at 0.5x and 0.8x of that rate, and the same requests solved one at a
-time through a single-model context).
+timed on this host's cores on a bounded sample of the same workload.  Three
+more objects by default: ``hyperfine`` (the same cube with a three-component
+multiplet on every transition, 2 timed iterations), ``octree`` (64^3 root
+refined four levels, 2 timed ALI iterations, same per-step measures) and
+``serving`` (a 512-request 1D stream: model solves/s with all requests queued
+at once, p50/p99 latency under Poisson arrivals at 0.5x and 0.8x of that rate,
+and the same requests solved one at a time through a single-model context).
 """
 import argparse
 import hashlib
@@ -162,10 +163,72 @@ def octree_bench(steps=2, warmup=1):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": traffic, "valu_busy": valu_busy,
-                     "kernel": f"march_oct_kernel<float,{cnt['march_lanes']},true>",
+                     "kernel": f"march_oct_kernel<float,{cnt['march_lanes']},true,false>",
                      "flops_per_channel_update": FLOPS_PER_CHANNEL, "window_channels_mean": nwin,
                      "hbm_algorithmic_gbs": hbm_gbs, "hbm_algorithmic_frac": hbm_gbs / HBM_PEAK_GBS,
                      "bytes_per_step": OCT_BYTES_PER_STEP},
+    }
+
+
+# Synthetic hyperfine multiplet (LTE between the components): offsets and
+# relative strengths, the same on every transition of the hyperfine leg.
+HF_OFFSETS_KMS = (-0.62, 0.0, 0.37)
+HF_STRENGTHS = (1.0, 5.0, 3.0)
+# Per in-window channel with K components: the single line's 22 operations
+# less its profile (argument FMA, square, exponential: 4) plus, per component,
+# the shifted argument (FMA, 2), its square (1), the exponential (1) and the
+# weighted sum (FMA, 2).
+def hf_flops_per_channel(k):
+    return FLOPS_PER_CHANNEL - 4.0 + 6.0 * k
+
+
+def hyperfine_bench(w, steps=2, warmup=1):
+    """Hyperfine leg: the headline cube and species with a three-component
+    multiplet on every transition (each channel's profile is the sum of three
+    shifted Gaussians, windows widened by the offset range)."""
+    import numpy as np
+
+    import paper_2009_12609_amd as miloc
+    m = w.model
+    ctx = miloc.Context(0)
+    ctx.load_molecule(w.mol)
+    ctx.load_model_3d(m)
+    ctx.set_spectral(w.spec.n_channels, w.spec.v_min, w.spec.dv)
+    ctx.set_background(w.T_bg)
+    off = np.array(HF_OFFSETS_KMS) * 1e5
+    for t in range(int(w.mol.n_trans)):
+        ctx.set_hyperfine(t, off, np.array(HF_STRENGTHS))
+    ctx.init_lte()
+    ctx.run(max(1, warmup))
+    ctx.init_lte()
+    ctx.reset_counters()
+    t0 = time.perf_counter()
+    ctx.run(steps)
+    elapsed = time.perf_counter() - t0
+    cnt = ctx.counters()
+    ctx.close()
+    launches = max(1, cnt["march_launches"])
+    march_ms = cnt["march_ms"] / launches
+    steps_per_launch = cnt["ray_steps"] / launches
+    k = len(HF_OFFSETS_KMS)
+    nwin = mean_window_channels(w) + (max(HF_OFFSETS_KMS) - min(HF_OFFSETS_KMS)) * 1e5 / w.spec.dv
+    fpc = hf_flops_per_channel(k)
+    achieved = steps_per_launch * nwin * fpc / (march_ms * 1e-3) / 1e12
+    return {
+        "metric": "ray-cell-channel updates/s (3D, hyperfine multiplets)",
+        "value": cnt["channel_updates"] / elapsed,
+        "unit": "ray-cell-channel updates/s",
+        "steps": steps,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "workload": f"{w.name} with a {k}-component multiplet on every transition",
+        "components_kms": list(HF_OFFSETS_KMS),
+        "strengths": list(HF_STRENGTHS),
+        "march_ms_per_launch": march_ms,
+        "solve_ms_per_step": cnt["solve_ms"] / max(1, cnt["iterations"]),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true,true>",
+                     "flops_per_channel_update": fpc, "window_channels_mean": nwin},
     }
 
 
@@ -279,6 +342,9 @@ def main():
                     help="run the 1D request stream with N_REQ requests ('serving' object; 0 = skip)")
     ap.add_argument("--octree", type=int, default=2, metavar="STEPS",
                     help="time STEPS iterations of the octree workload ('octree' object; 0 = skip)")
+    ap.add_argument("--hyperfine", type=int, default=2, metavar="STEPS",
+                    help="time STEPS iterations of the headline cube with hyperfine multiplets "
+                         "('hyperfine' object; 0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -367,7 +433,7 @@ def main():
             "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": traffic,
             "valu_busy": valu_busy,
-            "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true>",
+            "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true,false>",
             "flops_per_channel_update": FLOPS_PER_CHANNEL,
             "window_channels_mean": nwin,
             "hbm_algorithmic_gbs": hbm_gbs,
@@ -377,6 +443,8 @@ def main():
         },
     }
     ctx.close()
+    if args.hyperfine > 0:
+        out["hyperfine"] = hyperfine_bench(w, args.hyperfine)
     if args.octree > 0:
         out["octree"] = octree_bench(args.octree)
     if args.serve > 0:

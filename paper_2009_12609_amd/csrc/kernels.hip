@@ -268,21 +268,52 @@ __device__ __forceinline__ double omb_any(double tau)
     return omb;
 }
 
+// Hyperfine components of one transition {d_k = offset in channels, w_k =
+// strength, sum 1}: the first kReg in registers, loaded together once per ray
+// (a load inside the channel loop would wait on memory per component and
+// channel); any further ones are read from memory where they are used.
+template <typename T>
+struct HfRegs {
+    static constexpr int kReg = sizeof(T) == 4 ? 16 : 8;
+    T d[kReg], w[kReg];
+    const typename V2<T>::type* row;
+    int n;
+    __device__ __forceinline__ void load(const typename V2<T>::type* __restrict__ r, int count)
+    {
+        row = r;
+        n = count;
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) {
+            const typename V2<T>::type c = r[k < count ? k : 0];
+            d[k] = c.x;
+            w[k] = k < count ? c.y : (T)0;
+        }
+    }
+};
+
 // Line shape at scaled profile argument xs (the reference centre at 0):
-// exp2(-xs^2), or with HF the hyperfine multiplet (Sect. 1, LTE between the
-// components): sum_k w_k exp2(-(xs - d_k ibs)^2) over the transition's
-// components {d_k = offset in channels, w_k = strength, sum 1}.
-template <bool HF, typename T>
-__device__ __forceinline__ T line_shape(T xs, T ibs, const typename V2<T>::type* __restrict__ hf, int hfk)
+// KC = 0: exp2(-xs^2); otherwise the hyperfine multiplet (Sect. 1, LTE
+// between the components) sum_k w_k exp2(-(xs - d_k ibs)^2) over KC register
+// components (zero-strength padding beyond the transition's count), and, when
+// KC is the whole register set, over the components past it in memory.
+template <int KC, typename T>
+__device__ __forceinline__ T line_shape(T xs, T ibs, const HfRegs<T>* __restrict__ hf)
 {
-    if constexpr (!HF) {
+    if constexpr (KC == 0) {
         return fast_exp2(-xs * xs);
     } else {
         T e = 0;
-        for (int k = 0; k < hfk; ++k) {
-            const typename V2<T>::type c = hf[k];
-            const T y = xs - c.x * ibs;
-            e += c.y * fast_exp2(-y * y);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const T y = xs - hf->d[k] * ibs;
+            e += hf->w[k] * fast_exp2(-y * y);
+        }
+        if constexpr (KC == HfRegs<T>::kReg) {
+            for (int k = KC; k < hf->n; ++k) {
+                const typename V2<T>::type c = hf->row[k];
+                const T y = xs - c.x * ibs;
+                e += c.y * fast_exp2(-y * y);
+            }
         }
         return e;
     }
@@ -295,18 +326,16 @@ __device__ __forceinline__ T line_shape(T xs, T ibs, const typename V2<T>::type*
 // Partial sums of this lane in sj, sl.  The series/exact choice for 1 - beta
 // is made once per step for the whole wavefront (with HF the multiplet's
 // profile peaks at most at 1, so |kl| still bounds every |tau_j|).
-template <int LANES, typename T, bool HF = false>
-__device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
-                                                T kl, T el, T& sj, T& sl,
-                                                const typename V2<T>::type* __restrict__ hf = nullptr,
-                                                int hfk = 0)
+template <int LANES, typename T, int KC>
+__device__ __forceinline__ void window_loop(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
+                                            T kl, T el, T& sj, T& sl, const HfRegs<T>* hf)
 {
     const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
     T* __restrict__ row = I + clo;
     if (thin) {
         for (int j = lane; j < nwin; j += LANES) {
             const T xs = (T)j * ibs + x0;
-            const T ec = line_shape<HF, T>(xs, ibs, hf, hfk);
+            const T ec = line_shape<KC, T>(xs, ibs, hf);
             const T omb = omb_thin(kl * ec);
             const T Iin = row[j];
             const T u = ec - ec * omb;                 // e_c beta_c
@@ -317,7 +346,7 @@ __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int
     } else {
         for (int j = lane; j < nwin; j += LANES) {
             const T xs = (T)j * ibs + x0;
-            const T ec = line_shape<HF, T>(xs, ibs, hf, hfk);
+            const T ec = line_shape<KC, T>(xs, ibs, hf);
             const T omb = omb_any(kl * ec);
             const T Iin = row[j];
             const T u = ec - ec * omb;
@@ -325,6 +354,27 @@ __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int
             sl += ec * omb;
             row[j] = Iin + u * (el - kl * Iin);
         }
+    }
+}
+
+// With HF the component count picks, once per step (it is uniform), a loop
+// whose profile sum is unrolled over exactly 1..4 components, or over 8 or
+// all register components with zero-strength padding.
+template <int LANES, typename T, bool HF = false>
+__device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
+                                                T kl, T el, T& sj, T& sl, const HfRegs<T>* hf = nullptr)
+{
+    if constexpr (!HF) {
+        window_loop<LANES, T, 0>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+    } else {
+        constexpr int R = HfRegs<T>::kReg;
+        const int n = hf->n;
+        if (n == 1) window_loop<LANES, T, 1>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+        else if (n == 2) window_loop<LANES, T, 2>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+        else if (n == 3) window_loop<LANES, T, 3>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+        else if (n == 4) window_loop<LANES, T, 4>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+        else if (n <= 8 || R == 8) window_loop<LANES, T, 8>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+        else window_loop<LANES, T, R>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
     }
 }
 
@@ -379,7 +429,8 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
                              : nullptr;
     const T aw = (T)D.aw;
     const int ns = D.nsteps;
-    const T2* __restrict__ hfrow = HF ? p.hf + (size_t)t * p.hfk : nullptr;
+    HfRegs<T> hfr;
+    if constexpr (HF) hfr.load(p.hf + (size_t)t * p.hfk, p.hfk);
     // Invalid channel slots read and write a private dummy word in the
     // ray's padding so that no lane touches another ray's channels.
     T* __restrict__ dummy = I + p.nch + lane;
@@ -432,7 +483,7 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         const T kl = kv.x * rec.len;      // tau at the line centre
         const T el = kv.y * rec.len;
         T sj = 0, sl = 0;
-        window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, hfrow, p.hfk);
+        window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr);
         (void)dummy;
         if (ACCUM) {
             sj = group_sum<LANES>(sj);
@@ -678,7 +729,8 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         const uint2* __restrict__ rec = p.steps + tr.off;
         const T aw = (T)p.aw[tr.q];
         const T Ibg = p.Ibg[t];
-        const T2* __restrict__ hfrow = HF ? p.hf + (size_t)t * p.hfk : nullptr;
+        HfRegs<T> hfr;
+        if constexpr (HF) hfr.load(p.hf + (size_t)t * p.hfk, p.hfk);
         const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
         T2q* __restrict__ Et = p.E ? p.E + (size_t)tr.off * p.estride + (t - p.trans_offset) : nullptr;
         int qn = 0, qs0 = 0;
@@ -765,7 +817,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
-            window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, hfrow, p.hfk);
+            window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
@@ -841,7 +893,8 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
         const int nsteps = 2 * nin + 2;
         const T2* __restrict__ rec = p.steps + p.ray_off[j];
         const T Ibg = p.Ibg[t];
-        const T2* __restrict__ hfrow = HF ? p.hf + (size_t)t * p.hfk : nullptr;
+        HfRegs<T> hfr;
+        if constexpr (HF) hfr.load(p.hf + (size_t)t * p.hfk, p.hfk);
         for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
         auto shell_of = [&](int s) {
             return s < nin ? n - 1 - s : (s <= nin + 1 ? kmin : kmin + (s - nin - 1));
@@ -876,7 +929,7 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
             const T tl = r.x;
             T sj = 0, sl = 0;
             window_channels<LANES, T, HF>(I, lane, clo, chi - clo + 1, frac * sv.y, sv.y, kev.x * tl, kev.y * tl,
-                                          sj, sl, hfrow, p.hfk);
+                                          sj, sl, &hfr);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);

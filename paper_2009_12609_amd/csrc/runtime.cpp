@@ -515,7 +515,7 @@ miloc_status ensure_static(miloc_ctx* c)
     // channels) is covered in one to three passes of the ray's lane group
     const double wmax = 2.0 * Kd * maxb / c->dv + 2.0 + (vhi - vlo) / c->dv;
     if (c->kind == 3)
-        c->lanes = wmax <= 32.0 ? 8 : (wmax <= 64.0 ? 16 : 32);
+        c->lanes = wmax <= 64.0 ? 8 : (wmax <= 128.0 ? 16 : 32);   // 8: measured faster up to ~64
     else if (c->kind == 4)
         c->lanes = 8;                     // octree: groups of 8 (measured faster than 16), any window width
     else

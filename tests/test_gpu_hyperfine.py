@@ -108,6 +108,30 @@ def test_octree_hyperfine_fp32():
     ctx.close()
 
 
+@pytest.mark.parametrize("n_comp,fp64", [(2, False), (4, False), (5, False), (12, False), (20, False),
+                                          (6, True), (12, True)])
+def test_1d_hyperfine_component_counts(n_comp, fp64):
+    """Every unrolled form of the multiplet sum: exactly 2 or 4 components,
+    8 or 16 register components with zero-strength padding, and (20 in FP32,
+    12 in FP64) the components past the register set read from memory."""
+    rng = np.random.default_rng(100 + n_comp)
+    v = rng.uniform(-0.6, 0.6, n_comp) * KMS
+    s = rng.uniform(0.5, 2.0, n_comp)
+    w = synth.workload_1d_small()
+    w.model = synth.cloud_1d_log(abundance=3e-8)
+    w.spec = synth.Spectral.symmetric(192, 3.0)
+    hfs = {0: (v, s)}
+    print(f"[case] 1d hyperfine {n_comp} components fp64={fp64}", flush=True)
+    ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, 4, hyperfine=hfs)
+    ctx = hf_ctx(w, hfs, fp64=fp64)
+    ctx.run(4)
+    assert_pops(ctx.populations(), ref.x, 1e-10 if fp64 else 1e-5, f"1d hf n={n_comp}")
+    sp = ctx.spectra(0, n_los=w.model.n_rays)
+    ref_sp = oracle.spectra_1d(w.mol, w.model, w.spec, w.T_bg, ref.x, 0, shape=hfs[0])
+    assert_spectra(sp, ref_sp, 1e-9 if fp64 else 1e-4, f"1d hf n={n_comp}")
+    ctx.close()
+
+
 def test_hyperfine_single_component_and_reset():
     """One component at offset 0 runs the multiplet kernels with the plain
     line; clearing the multiplet returns the single-Gaussian kernels."""

@@ -98,3 +98,17 @@ def test_octree_uniform_field_full_size():
           f"{cnt['ray_steps']:.3e} steps", flush=True)
     assert rel < 1e-5
     ctx.close()
+
+
+def test_octree_sixteen_lane_groups(monkeypatch):
+    """The 16-lane instance of the octree march (MILOC_LANES=16) agrees with
+    the oracle like the default 8-lane one."""
+    monkeypatch.setenv("MILOC_LANES", "16")
+    w = oct_workload()
+    lf = leaf_rows(w)
+    ref = oracle.run_oct(w.mol, w.model, w.spec, w.T_bg, 2)
+    ctx = make_ctx(w)
+    ctx.run(2)
+    assert ctx.counters()["march_lanes"] == 16
+    assert_pops(ctx.populations()[lf], ref.x[lf], 1e-5, "octree 16 lanes")
+    ctx.close()

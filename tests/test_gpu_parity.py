@@ -211,6 +211,26 @@ def test_3d_small_grid(N, abundance, n_iter):
     assert_spectra(sp, ref_sp, 1e-4, f"3d-{N}")
 
 
+@pytest.mark.parametrize("kind,lanes", [("1d", 8), ("1d", 32), ("1d", 64), ("3d", 16), ("3d", 32),
+                                        ("3d", 64)])
+def test_lane_group_widths(kind, lanes, monkeypatch):
+    """The march instances for every lane-group width (chosen from the
+    window width, or forced through MILOC_LANES) agree with the oracle."""
+    monkeypatch.setenv("MILOC_LANES", str(lanes))
+    if kind == "1d":
+        w = workload_1d_plummer(61, 1e-8)
+        ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, 4)
+    else:
+        w = workload_3d(9, seed=29, abundance=1e-7, n_levels=5, box_pc=0.075)
+        ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, 2)
+    print(f"[case] {kind} lanes={lanes}", flush=True)
+    ctx = make_ctx(w)
+    ctx.run(4 if kind == "1d" else 2)
+    assert ctx.counters()["march_lanes"] == lanes
+    assert_pops(ctx.populations(), ref.x, 1e-5, f"{kind} lanes={lanes}")
+    ctx.close()
+
+
 def test_3d_fp64_march():
     w = workload_3d(8, seed=7, abundance=1e-7, n_levels=5, box_pc=0.05, nch=128)
     ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, 3)
