@@ -91,6 +91,8 @@ def lib():
                                    dp, dp, dp, dp, dp, dp, ctypes.c_int, dp, ctypes.c_int,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    dp, dp, dp, dp, dp, llp, ctypes.c_int, dp, dp]
+        L.orcoct_march_brute.restype = None
+        L.orcoct_march_brute.argtypes = L.orcoct_march.argtypes
         L.orcoct_map_z.restype = None
         L.orcoct_map_z.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_double, dp, dp, dp, dp,
                                    dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -120,9 +122,10 @@ def _f64(a) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def planck(nu, T):
-    """B_nu(T) = (2 h nu^3 / c^2) / (exp(h nu / k T) - 1)."""
+    """B_nu(T) = (2 h nu^3 / c^2) / (exp(h nu / k T) - 1); 0 at T = 0."""
     nu = np.asarray(nu, dtype=np.float64)
-    return (2.0 * H * nu ** 3 / C ** 2) / np.expm1(H * nu / (KB * T))
+    with np.errstate(divide="ignore"):
+        return (2.0 * H * nu ** 3 / C ** 2) / np.expm1(H * nu / (KB * T))
 
 
 def doppler_b(T_kin, b_turb, mass_amu):
@@ -508,9 +511,11 @@ OCT_STATS = ("root", "split", "side", "terminated", "wrapped", "steps")
 
 
 def march_oct(tree: OctTree, root_cm, vx, vy, vz, bD, kappa, eta, dirs, spec, I_bg, n_threads=0,
-              shape=None):
+              shape=None, brute=False):
     """One transition through an octree for the given directions; also returns
-    the ray statistics (dict over OCT_STATS).  kappa None: geometry only."""
+    the ray statistics (dict over OCT_STATS).  kappa None: geometry only.
+    brute: the brute-force lattice of 4^Lmax straight lines per root surface
+    element instead of the created and terminated rays (Sect. 2.2)."""
     nc = tree.child.shape[0]
     dirs = _f64(dirs)
     geo = kappa is None
@@ -521,7 +526,8 @@ def march_oct(tree: OctTree, root_cm, vx, vy, vz, bD, kappa, eta, dirs, spec, I_
     st = np.zeros(len(OCT_STATS), np.int64)
     child = np.ascontiguousarray(tree.child, dtype=np.int32)
     hf, _keep = _shape_call(shape)
-    lib().orcoct_march(tree.N, tree.Lmax, nc, child.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+    fn = lib().orcoct_march_brute if brute else lib().orcoct_march
+    fn(tree.N, tree.Lmax, nc, child.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                        float(root_cm), *[_dp(a) for a in args], dirs.shape[0], _dp(dirs), nch,
                        0.0 if geo else float(spec.v_min), 1.0 if geo else float(spec.dv),
                        0.0 if geo else float(I_bg), int(n_threads), _dp(J), _dp(Lm), _dp(W),
@@ -530,10 +536,11 @@ def march_oct(tree: OctTree, root_cm, vx, vy, vz, bD, kappa, eta, dirs, spec, I_
 
 
 def run_oct(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, tol=None,
-            n_threads=0, record=True, hyperfine=None):
+            n_threads=0, record=True, hyperfine=None, brute=False):
     """Lambda / ALI iteration on an octree model.  Every cell of every level
     carries populations; only leaves are marched and solved, refined cells
-    keep their starting values.  hyperfine as in run_1d."""
+    keep their starting values.  hyperfine as in run_1d; brute as in
+    march_oct."""
     hfs = hyperfine or {}
     tree = octree_of(model)
     leaf = tree.leaf
@@ -543,7 +550,7 @@ def run_oct(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, to
 
     def march(t, kap, eta):
         return march_oct(tree, float(model.root_cell_cm), vx, vy, vz, prob.bD, kap, eta, dirs,
-                         spec, prob.I_bg[t], n_threads, shape=hfs.get(t))[0]
+                         spec, prob.I_bg[t], n_threads, shape=hfs.get(t), brute=brute)[0]
 
     res = _iterate(prob, march, n_iter, use_ali, x0, tol, record, solve_mask=leaf)
     return res

@@ -647,24 +647,29 @@ static int oct_save(oct_stack_t* S, const double* I, int nch)
  * coarser leaf, model-side re-entries, steps. */
 enum { OCT_ROOT, OCT_SPLIT, OCT_SIDE, OCT_TERM, OCT_WRAP, OCT_STEPS, OCT_NSTAT };
 
-/* Trace every ray that root line (i, j) gives rise to.  With nch == 0 only
- * the path bookkeeping (W) is done.  'plain' traces the single line without
- * splitting, side rays or termination (lines of sight for maps); I_end then
- * receives its final intensity. */
-static void oct_trace_root(const oct_geom_t* G, const shape_t* shape, int i, int j, double root_cm,
+/* Trace every ray that the line (la, lb) of the finest lattice (a root line
+ * has la, lb multiples of 2^Lmax) gives rise to.  With nch == 0 only the path
+ * bookkeeping (W) is done.  'plain' traces the single line without splitting,
+ * side rays or termination (lines of sight for maps); I_end then receives its
+ * final intensity.  'brute' (the brute-force alternative of Sect. 2.2: a
+ * regular lattice of 4^Lmax lines per root surface element) traces the single
+ * line as 'plain' and weights every step with the finest lattice's h^2 |d_m|
+ * instead of the crossed leaf's. */
+static void oct_trace_root(const oct_geom_t* G, const shape_t* shape, long long la, long long lb, double root_cm,
                            const double* dvec, const double* vx, const double* vy, const double* vz,
                            const double* bD, const double* kappa, const double* eta,
-                           int nch, double vmin, double dv, double I_bg, int plain,
+                           int nch, double vmin, double dv, double I_bg, int plain, int brute,
                            accum_t* A, long long* stats, oct_stack_t* S, double* I, double* I_end)
 {
     const int Lmax = G->Lmax;
     const double h = G->h;
     const double dm = G->du[2];
+    if (brute) plain = 1;
     S->n = 0;
     S->nv = 0;
     oct_ray_t r0;
-    r0.l[0] = (long long)i << Lmax;
-    r0.l[1] = (long long)j << Lmax;
+    r0.l[0] = la;
+    r0.l[1] = lb;
     r0.f[0] = r0.l[0];
     r0.f[1] = r0.l[1];
     r0.f[2] = 0;
@@ -770,7 +775,8 @@ static void oct_trace_root(const oct_geom_t* G, const shape_t* shape, int i, int
                 if (oct_before(te[u], u, te[ex], ex)) ex = u;
             double s = te[ex] - R.t;
             if (s < 0.0) s = 0.0;
-            const double a_w = (Dc * root_cm) * (Dc * root_cm) * dm;
+            const double side = brute ? h : Dc;
+            const double a_w = (side * root_cm) * (side * root_cm) * dm;
             const double s_cm = s * root_cm;
             if (nch > 0) {
                 const double w = vx[g] * dvec[0] + vy[g] * dvec[1] + vz[g] * dvec[2];
@@ -810,24 +816,26 @@ static void oct_trace_root(const oct_geom_t* G, const shape_t* shape, int i, int
     }
 }
 
-/* March one transition through an octree for all directions (see above).
+/* One transition through an octree for all directions (see above).
  * Per-cell FP64 inputs over all cells (only leaves are used).  Raw sums as
  * orc3d_march; 'stats' receives OCT_NSTAT counters (may be NULL).  With
  * nch == 0 only W is produced (kappa, eta, velocities may be NULL).  Line
  * shape as in orc1d_march. */
-void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_cm,
-                  const double* vx, const double* vy, const double* vz,
-                  const double* bD, const double* kappa, const double* eta,
-                  int n_dir, const double* dirs,
-                  int nch, double vmin, double dv, double I_bg, int n_threads,
-                  double* Jraw, double* Lraw, double* Wraw, double* Eraw, double* cons,
-                  long long* stats, int n_hf, const double* hf_v, const double* hf_w)
+static void oct_march(int N, int Lmax, long n_cells, const int* child, double root_cm,
+                      const double* vx, const double* vy, const double* vz,
+                      const double* bD, const double* kappa, const double* eta,
+                      int n_dir, const double* dirs,
+                      int nch, double vmin, double dv, double I_bg, int n_threads,
+                      double* Jraw, double* Lraw, double* Wraw, double* Eraw, double* cons,
+                      long long* stats, int n_hf, const double* hf_v, const double* hf_w, int brute)
 {
     const shape_t shape = shape_of(n_hf, hf_v, hf_w);
     int nt = nthreads_of(n_threads);
     accum_t* acc = accum_alloc(nt, n_cells);
     long long* st = (long long*)calloc((size_t)nt * OCT_NSTAT, sizeof(long long));
-    long n_task = (long)n_dir * N * N;
+    /* tasks: root elements, or with 'brute' every line of the finest lattice */
+    const long side = brute ? ((long)N << Lmax) : (long)N;
+    long n_task = (long)n_dir * side * side;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(nt)
 #endif
@@ -842,12 +850,14 @@ void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_c
 #pragma omp for schedule(dynamic, 16)
 #endif
         for (long r = 0; r < n_task; ++r) {
-            const int q = (int)(r / ((long)N * N));
-            const int rem = (int)(r % ((long)N * N));
+            const int q = (int)(r / (side * side));
+            const long rem = r % (side * side);
+            const int sh = brute ? 0 : Lmax;
             oct_geom_t G;
             oct_geom_init(&G, N, Lmax, child, dirs + 3 * q);
-            oct_trace_root(&G, &shape, rem % N, rem / N, root_cm, dirs + 3 * q, vx, vy, vz, bD, kappa, eta,
-                           nch, vmin, dv, I_bg, 0, &acc[tid], st + (size_t)tid * OCT_NSTAT, &S, I, NULL);
+            oct_trace_root(&G, &shape, (long long)(rem % side) << sh, (long long)(rem / side) << sh, root_cm,
+                           dirs + 3 * q, vx, vy, vz, bD, kappa, eta, nch, vmin, dv, I_bg, 0, brute, &acc[tid],
+                           st + (size_t)tid * OCT_NSTAT, &S, I, NULL);
         }
         free(S.r);
         free(S.vec);
@@ -861,6 +871,36 @@ void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_c
             stats[k] = v;
         }
     free(st);
+}
+
+/* March one transition through an octree for all directions with the rays
+ * the octree scheme creates and terminates (see above). */
+void orcoct_march(int N, int Lmax, long n_cells, const int* child, double root_cm,
+                  const double* vx, const double* vy, const double* vz,
+                  const double* bD, const double* kappa, const double* eta,
+                  int n_dir, const double* dirs,
+                  int nch, double vmin, double dv, double I_bg, int n_threads,
+                  double* Jraw, double* Lraw, double* Wraw, double* Eraw, double* cons,
+                  long long* stats, int n_hf, const double* hf_v, const double* hf_w)
+{
+    oct_march(N, Lmax, n_cells, child, root_cm, vx, vy, vz, bD, kappa, eta, n_dir, dirs, nch, vmin, dv, I_bg,
+              n_threads, Jraw, Lraw, Wraw, Eraw, cons, stats, n_hf, hf_v, hf_w, 0);
+}
+
+/* The brute-force alternative (Sect. 2.2): every line of the finest lattice
+ * (4^Lmax per root surface element) traced straight through the leaves with
+ * weight h_Lmax^2 |d_m|, re-entering with the background at model sides;
+ * arguments and outputs as orcoct_march. */
+void orcoct_march_brute(int N, int Lmax, long n_cells, const int* child, double root_cm,
+                        const double* vx, const double* vy, const double* vz,
+                        const double* bD, const double* kappa, const double* eta,
+                        int n_dir, const double* dirs,
+                        int nch, double vmin, double dv, double I_bg, int n_threads,
+                        double* Jraw, double* Lraw, double* Wraw, double* Eraw, double* cons,
+                        long long* stats, int n_hf, const double* hf_v, const double* hf_w)
+{
+    oct_march(N, Lmax, n_cells, child, root_cm, vx, vy, vz, bD, kappa, eta, n_dir, dirs, nch, vmin, dv, I_bg,
+              n_threads, Jraw, Lraw, Wraw, Eraw, cons, stats, n_hf, hf_v, hf_w, 1);
 }
 
 /* +z map of an octree: one straight line of sight per root surface element
@@ -890,8 +930,8 @@ void orcoct_map_z(int N, int Lmax, const int* child, double root_cm,
         for (long r = 0; r < (long)N * N; ++r) {
             oct_geom_t G;
             oct_geom_init(&G, N, Lmax, child, dz);
-            oct_trace_root(&G, &shape, (int)(r % N), (int)(r / N), root_cm, dz, vx, vy, vz, bD, kappa, eta,
-                           nch, vmin, dv, I_bg, 1, NULL, st, &S, I, I_out + (size_t)r * nch);
+            oct_trace_root(&G, &shape, (long long)(r % N) << Lmax, (long long)(r / N) << Lmax, root_cm, dz, vx, vy,
+                           vz, bD, kappa, eta, nch, vmin, dv, I_bg, 1, 0, NULL, st, &S, I, I_out + (size_t)r * nch);
         }
         free(S.r);
         free(S.vec);

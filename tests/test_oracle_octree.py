@@ -194,3 +194,122 @@ def test_p5_detailed_balance_octree():
     J = run.history[0]["J"]
     assert np.max(run.history[0]["Lam"][:, lf]) > 1e-2       # not transparent
     assert np.all(np.isfinite(J))
+
+
+# ---------------------------------------------------------------------------
+# Brute-force lattice (Sect. 2.2: 4^Lmax straight lines per root element)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,nref,frac,seed", [(4, 2, 0.3, 2), (3, 3, 0.35, 3), (2, 4, 0.6, 5)])
+def test_brute_path_per_leaf(N, nref, frac, seed):
+    """Every finest-lattice line, weight h_Lmax^2 |d_m|: each leaf again
+    carries W = its volume exactly, with no created or terminated rays."""
+    m = synth.octree_random(N, nref, frac, seed, 1.0 * N, 1e3, 10.0, 0.0, 1e-9)
+    tree = oracle.octree_of(m)
+    V = (0.5 ** tree.level) ** 3
+    for d in _dirs_all()[::3]:
+        res, st = oracle.march_oct(tree, 1.0, *([None] * 6), d[None, :], None, 0.0, brute=True)
+        err = np.abs(res.W - np.where(tree.leaf, V, 0.0)) / V
+        assert np.max(err) < 1e-12, (d, np.max(err))
+        assert st["root"] == (N << tree.Lmax) ** 2
+        assert st["split"] == st["side"] == st["terminated"] == 0
+
+
+def test_brute_equals_fine_grid_for_root_constant_fields():
+    """Fields constant within each root cell: a straight line crossing a leaf
+    in one step sees the same medium as the finest regular grid crossing it in
+    several, so the lattice march equals the (N 2^Lmax)^3 grid march in the
+    path-averaged intensity J + S Lambda and in W, leaf by leaf."""
+    N, delta = 3, 2.0e16
+    spec = synth.Spectral.symmetric(48, 3.0)
+    m = synth.octree_random(N, 2, 0.4, 11, N * delta, 1e3, 10.0, 0.0, 1e-9)
+    tree = oracle.octree_of(m)
+    L = tree.Lmax
+    rng = np.random.default_rng(12)
+    nroot = N ** 3
+    v = rng.normal(scale=0.3 * KMS, size=(3, nroot))
+    b = rng.uniform(0.15, 0.3, nroot) * KMS
+    kap = rng.uniform(0.5, 2.0, nroot) * 3e-13
+    eta = rng.uniform(0.5, 2.0, nroot) * 1e-27
+    # root ancestor of every cell and the leaf of every finest cell
+    nc = tree.child.shape[0]
+    root_of = np.arange(nc)
+    for lev in range(1, L + 1):
+        for g in range(int(tree.offsets[lev - 1]), int(tree.offsets[lev])):
+            c = tree.child[g]
+            if c >= 0:
+                root_of[c:c + 8] = root_of[g]
+    cx, cy, cz = synth.octree_centres(N, _coords_of(tree))
+    F = lambda a: a[root_of]
+    dirs = oracle.healpix_nside2()[::2]
+    o, st = oracle.march_oct(tree, delta, F(v[0]), F(v[1]), F(v[2]), F(b), F(kap), F(eta), dirs, spec,
+                             1.5e-15, brute=True)
+    Nf = N << L
+    fx, fy, fz = np.meshgrid(np.arange(Nf), np.arange(Nf), np.arange(Nf), indexing="ij")
+    fx, fy, fz = fx.ravel(), fy.ravel(), fz.ravel()
+    freg = (fz * Nf + fy) * Nf + fx
+    froot = ((fz >> L) * N + (fy >> L)) * N + (fx >> L)
+    G = lambda a: np.zeros(Nf ** 3) + np.bincount(freg, weights=a[froot], minlength=Nf ** 3)
+    r = oracle.march_3d(Nf, delta / (1 << L), G(v[0]), G(v[1]), G(v[2]), G(b), G(kap), G(eta), dirs, spec,
+                        1.5e-15)
+    # leaf of each finest cell
+    leaf_of = np.full(Nf ** 3, -1, np.int64)
+    for g in np.flatnonzero(tree.leaf):
+        s = 1 << (L - tree.level[g])
+        x0 = int(round(cx[g] * Nf - 0.5 * s))
+        y0 = int(round(cy[g] * Nf - 0.5 * s))
+        z0 = int(round(cz[g] * Nf - 0.5 * s))
+        xs, ys, zs = np.meshgrid(np.arange(x0, x0 + s), np.arange(y0, y0 + s), np.arange(z0, z0 + s), indexing="ij")
+        leaf_of[((zs * Nf + ys) * Nf + xs).ravel()] = g
+    assert (leaf_of >= 0).all()
+    S = eta / kap
+    JLI_f = r.Jraw + G(S) * r.Lraw
+    sum_leaf = lambda a: np.bincount(leaf_of, weights=a, minlength=nc)
+    lf = tree.leaf
+    JLI_o = o.Jraw + F(S) * o.Lraw
+    assert np.allclose(JLI_o[lf], sum_leaf(JLI_f)[lf], rtol=1e-11, atol=0)
+    assert np.allclose(o.W[lf], sum_leaf(r.W)[lf], rtol=1e-12, atol=0)
+
+
+def _coords_of(tree):
+    """Integer coordinates per level of every cell (from the child links)."""
+    N, L = tree.N, tree.Lmax
+    coords = []
+    iz, iy, ix = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    cur = (ix.ravel().astype(np.int64), iy.ravel().astype(np.int64), iz.ravel().astype(np.int64))
+    coords.append(cur)
+    for lev in range(1, L + 1):
+        n = int(tree.offsets[lev + 1] - tree.offsets[lev])
+        x = np.zeros(n, np.int64); y = np.zeros(n, np.int64); z = np.zeros(n, np.int64)
+        base = int(tree.offsets[lev - 1])
+        for k in range(int(tree.offsets[lev] - base)):
+            c = tree.child[base + k]
+            if c < 0:
+                continue
+            j = c - int(tree.offsets[lev])
+            for o in range(8):
+                x[j + o] = 2 * coords[lev - 1][0][k] + (o & 1)
+                y[j + o] = 2 * coords[lev - 1][1][k] + ((o >> 1) & 1)
+                z[j + o] = 2 * coords[lev - 1][2][k] + ((o >> 2) & 1)
+        coords.append((x, y, z))
+    return coords
+
+
+def test_brute_uniform_field_invariance():
+    """S = I_bg everywhere: J + S Lambda = I_bg sum_c f_c on every leaf also
+    for the straight-line lattice."""
+    mol = synth.two_level_molecule()
+    spec = synth.Spectral.symmetric(64, 4.0)
+    m = synth.octree_cloud(N_root=3, n_refine=2, frac=0.35, grf_N=12, box_pc=0.1,
+                           abundance=1e-6, T_kin=10.0, b_turb_kms=0.2, seed=78)
+    tree = oracle.octree_of(m)
+    x = np.tile(_source_pops(mol, 2.73), (tree.child.shape[0], 1))
+    prob = oracle._Problem(mol, m.n_H2, m.T_kin, m.b_turb, m.abundance, spec, 2.73)
+    kap, eta = oracle.prepare(mol, x, prob.n_mol)
+    I_bg = float(prob.I_bg[0])
+    r, _ = oracle.march_oct(tree, m.root_cell_cm, m.vx.astype(float), m.vy.astype(float),
+                            m.vz.astype(float), prob.bD, kap[0], eta[0], oracle.healpix_nside2()[::4],
+                            spec, I_bg, brute=True)
+    lf = tree.leaf
+    JLI = r.Jraw + (eta[0] / kap[0]) * r.Lraw
+    assert np.allclose(JLI[lf], I_bg * r.E[lf], rtol=1e-10, atol=0)
