@@ -308,6 +308,55 @@ def test_3d_full_size_uniform_field():
 # ABI behaviour on the device
 # ---------------------------------------------------------------------------
 
+def _edge_case(case):
+    """Degenerate and extreme inputs of the method, each small enough for the
+    oracle: (workload, fp64)."""
+    two = synth.two_level_molecule()
+    if case == "1d-one-shell-one-ray":
+        m = synth.uniform_sphere_1d(1, 3e17, 1e4, 12.0, 0.2 * KMS, 1e-8, 1)
+        return synth.Workload(case, two, synth.Spectral.symmetric(64, 2.0), 2.73, m, 4), True
+    if case == "1d-two-shells-three-rays-fp32":
+        m = synth.uniform_sphere_1d(2, 3e17, 1e4, 12.0, 0.2 * KMS, 1e-8, 3, v_r=-0.1 * KMS)
+        return synth.Workload(case, two, synth.Spectral.symmetric(64, 2.0), 2.73, m, 4), False
+    if case == "1d-zero-abundance":
+        m = synth.cloud_1d_log(n_shells=30, abundance=1e-9)
+        m.abundance[:] = 0.0
+        return synth.Workload(case, two, synth.Spectral.symmetric(64, 2.0), 2.73, m, 3), True
+    if case == "1d-no-background":
+        m = synth.cloud_1d_log(n_shells=30, abundance=3e-8)
+        return synth.Workload(case, synth.rotor_molecule(4), synth.Spectral.symmetric(64, 2.0), 0.0, m, 4), True
+    if case == "1d-4096-channels":
+        m = synth.cloud_1d_log(n_shells=24, abundance=3e-8, n_rays=24)
+        return synth.Workload(case, two, synth.Spectral.symmetric(4096, 2.0), 2.73, m, 2), False
+    if case == "3d-smallest-grid":
+        cube = synth.turbulent_cube(N=2, box_pc=0.02, seed=5, abundance=1e-7)
+        return synth.Workload(case, synth.rotor_molecule(4), synth.Spectral.symmetric(128, 4.0), 2.73, cube, 3), False
+    if case == "3d-smallest-grid-fp64":
+        cube = synth.uniform_cube(2, 2e16, 1e4, 10.0, 0.2 * KMS, 1e-7, velocity=(0.1 * KMS, 0.0, -0.2 * KMS))
+        return synth.Workload(case, synth.rotor_molecule(4), synth.Spectral.symmetric(128, 2.0), 2.73, cube, 3), True
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["1d-one-shell-one-ray", "1d-two-shells-three-rays-fp32", "1d-zero-abundance",
+                                  "1d-no-background", "1d-4096-channels", "3d-smallest-grid",
+                                  "3d-smallest-grid-fp64"])
+def test_degenerate_and_extreme_inputs(case):
+    """One shell crossed by one ray, a few rays, no emitting molecules (only
+    the background drives the levels), no background, the largest channel
+    count, the smallest regular grid: populations against the oracle."""
+    w, fp64 = _edge_case(case)
+    n_iter = w.n_iter
+    print(f"[case] {case} fp64={fp64}", flush=True)
+    if isinstance(w.model, synth.Model1D):
+        ref = oracle.run_1d(w.mol, w.model, w.spec, w.T_bg, n_iter)
+    else:
+        ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, n_iter)
+    ctx = make_ctx(w, fp64=fp64)
+    ctx.run(n_iter)
+    assert_pops(ctx.populations(), ref.x, 1e-10 if fp64 else 1e-5, case)
+    ctx.close()
+
+
 def test_abi_state_and_argument_errors():
     ctx = miloc.Context()
     with pytest.raises(miloc.MilocError) as e:
