@@ -232,6 +232,40 @@ def hyperfine_bench(w, steps=2, warmup=1):
     }
 
 
+def lattice_bench(steps=2, warmup=1, n_refine=2):
+    """Octree rays compared on a shallow tree: the same 64^3-root cloud refined
+    n_refine levels, marched with the scheme's created and ended rays and with
+    the brute-force lattice of 4^n_refine straight lines per root element."""
+    import paper_2009_12609_amd as miloc
+    import synth
+
+    w = synth.workload_octree(n_refine=n_refine)
+    out = {"workload": w.name, "n_cells_per_level": list(map(int, w.model.n_cells_per_level)), "steps": steps}
+    for name, lattice in (("scheme", False), ("lattice", True)):
+        ctx = miloc.Context(0)
+        ctx.load_molecule(w.mol)
+        ctx.load_model_3d(w.model)
+        ctx.set_spectral(w.spec.n_channels, w.spec.v_min, w.spec.dv)
+        ctx.set_background(w.T_bg)
+        ctx.set_octree_rays(lattice)
+        ctx.init_lte()
+        ctx.run(max(1, warmup))
+        ctx.init_lte()
+        ctx.reset_counters()
+        t0 = time.perf_counter()
+        ctx.run(steps)
+        elapsed = time.perf_counter() - t0
+        cnt = ctx.counters()
+        ctx.close()
+        launches = max(1, cnt["march_launches"])
+        out[name] = {"ms_per_step": elapsed * 1e3 / steps,
+                     "march_ms_per_launch": cnt["march_ms"] / launches,
+                     "gather_ms_per_step": cnt["accumulate_ms"] / max(1, cnt["iterations"]),
+                     "ray_cell_steps_per_iteration": cnt["ray_steps"] / max(1, cnt["iterations"]),
+                     "updates_per_s": cnt["channel_updates"] / elapsed}
+    return out
+
+
 def _pct(a, q):
     import numpy as np
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
@@ -345,6 +379,9 @@ def main():
     ap.add_argument("--hyperfine", type=int, default=2, metavar="STEPS",
                     help="time STEPS iterations of the headline cube with hyperfine multiplets "
                          "('hyperfine' object; 0 = skip)")
+    ap.add_argument("--lattice", type=int, default=0, metavar="STEPS",
+                    help="time STEPS iterations of a two-level octree with the scheme's rays and with the "
+                         "brute-force lattice ('lattice' object; 0 = skip, the default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -447,6 +484,8 @@ def main():
         out["hyperfine"] = hyperfine_bench(w, args.hyperfine)
     if args.octree > 0:
         out["octree"] = octree_bench(args.octree)
+    if args.lattice > 0:
+        out["lattice"] = lattice_bench(args.lattice)
     if args.serve > 0:
         out["serving"] = serve_bench(args.serve)
     if not args.no_cpu_baseline and N == 128:

@@ -182,8 +182,11 @@ miloc_status miloc_load_model_3d(miloc_ctx* ctx, const miloc_model3d* model);
  * the last saved vector, 3 copy of it and drop it; word 1: the step length in
  * root-cell units as an IEEE float) and trees_out 4 * n_trees values (first
  * step, step count, direction, root element j*N + i), largest trees first.
- * plain != 0 traces single lines (no new rays, no ending).  MILOC_EINVAL for
- * an invalid model or directions. */
+ * plain = 1 traces the root lines alone (no new rays, no ending; lines of
+ * sight), plain = 2 the brute-force lattice (every line of the finest level,
+ * 4^Lmax per root element, traced straight; see miloc_set_octree_rays),
+ * plain = 0 the octree scheme.  MILOC_EINVAL for an invalid model,
+ * directions or plain. */
 miloc_status miloc_octree_schedule(const miloc_model3d* model, int n_dir, const double* dirs, int plain,
                                    int64_t* n_steps, int64_t* n_trees, int* max_depth, uint32_t* steps_out,
                                    int64_t* trees_out);
@@ -213,6 +216,19 @@ miloc_status miloc_set_background(miloc_ctx* ctx, double T_bg_K);
  * without a molecule, MILOC_EINVAL for a bad index, count, offset or
  * strength (state unchanged). */
 #define MILOC_MAX_HF_COMPONENTS 32
+
+/* Rays of the octree march (Sect. 2.2).  MILOC_OCT_RAYS_SCHEME (default):
+ * rays created on entering refined cells and through side faces, ended in
+ * coarser cells, each of the level of the cells it crosses.
+ * MILOC_OCT_RAYS_LATTICE: the brute-force alternative the paper weighs
+ * against it, a regular lattice of 4^Lmax straight lines per root surface
+ * element (Lmax = the deepest level), each of weight h_Lmax^2 |d_m|, no rays
+ * created or ended (cost grows as 4^Lmax: for shallow trees).  Applies to
+ * octree models (ignored otherwise); the ray schedule is rebuilt at the next
+ * miloc_run.  MILOC_EINVAL for another value. */
+#define MILOC_OCT_RAYS_SCHEME 0
+#define MILOC_OCT_RAYS_LATTICE 1
+miloc_status miloc_set_octree_rays(miloc_ctx* ctx, int rays);
 miloc_status miloc_set_hyperfine(miloc_ctx* ctx, int trans, int n_comp, const double* dv_cms,
                                  const double* strength);
 

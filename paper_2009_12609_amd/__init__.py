@@ -97,6 +97,7 @@ SIGNATURES = {
     "miloc_set_spectral": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
     "miloc_set_background": (ctypes.c_int, [_vp, ctypes.c_double]),
     "miloc_set_hyperfine": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
+    "miloc_set_octree_rays": (ctypes.c_int, [_vp, ctypes.c_int]),
     "miloc_set_directions_healpix": (ctypes.c_int, [_vp, ctypes.c_int]),
     "miloc_set_directions": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "miloc_set_march_precision": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -203,21 +204,24 @@ def _model3d_struct(m, keep):
                          *[_ptr(a, ctypes.c_float) for a in arrs])
 
 
-def octree_schedule(model, dirs, plain=False):
+def octree_schedule(model, dirs, plain=False, lattice=False):
     """Host-built ray schedule of an octree model (miloc_octree_schedule):
-    (steps uint32 [n_steps, 2], trees int64 [n_trees, 4], max_depth)."""
+    (steps uint32 [n_steps, 2], trees int64 [n_trees, 4], max_depth).
+    plain: root lines only, traced straight; lattice: the brute-force lattice
+    of 4^Lmax straight lines per root element."""
     L = load_library()
     keep = []
     s = _model3d_struct(model, keep)
     d = _f64(dirs).reshape(-1, 3)
     ns, nt, md = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int(0)
-    rc = L.miloc_octree_schedule(ctypes.byref(s), int(d.shape[0]), _ptr(d, ctypes.c_double), int(bool(plain)),
+    mode = 2 if lattice else (1 if plain else 0)
+    rc = L.miloc_octree_schedule(ctypes.byref(s), int(d.shape[0]), _ptr(d, ctypes.c_double), mode,
                                  ctypes.byref(ns), ctypes.byref(nt), ctypes.byref(md), None, None)
     if rc != OK:
         raise MilocError(rc, "miloc_octree_schedule failed")
     steps = np.zeros((ns.value, 2), np.uint32)
     trees = np.zeros((nt.value, 4), np.int64)
-    rc = L.miloc_octree_schedule(ctypes.byref(s), int(d.shape[0]), _ptr(d, ctypes.c_double), int(bool(plain)),
+    rc = L.miloc_octree_schedule(ctypes.byref(s), int(d.shape[0]), _ptr(d, ctypes.c_double), mode,
                                  ctypes.byref(ns), ctypes.byref(nt), ctypes.byref(md),
                                  _ptr(steps, ctypes.c_uint32), _ptr(trees, ctypes.c_int64))
     if rc != OK:
@@ -375,6 +379,11 @@ class Context:
             raise ValueError("dv_cms and strength differ in length")
         self._check(self._lib.miloc_set_hyperfine(self._h, int(trans), int(v.size),
                                                   _ptr(v, ctypes.c_double), _ptr(w, ctypes.c_double)))
+
+    def set_octree_rays(self, lattice: bool):
+        """Octree rays: the scheme's created and ended rays (False, default) or
+        the brute-force lattice of 4^Lmax straight lines per root element."""
+        self._check(self._lib.miloc_set_octree_rays(self._h, 1 if lattice else 0))
 
     def set_directions_healpix(self, nside: int):
         self._check(self._lib.miloc_set_directions_healpix(self._h, int(nside)))

@@ -171,7 +171,7 @@ public:
 
     // All rays of root element (i, j): appends step records to rec.  False if
     // the saved vectors do not follow stack order (not expected).
-    bool tree(int i, int j, bool plain, std::vector<uint32_t>& rec, std::vector<double>* len64, int& max_depth,
+    bool tree(int i, int j, OctRays rays, std::vector<uint32_t>& rec, std::vector<double>* len64, int& max_depth,
               int64_t& n_rays);
 
 private:
@@ -196,25 +196,32 @@ inline int64_t index_after(double pos, double h, int u, int by)
     return (int64_t)std::floor(x);
 }
 
-bool DirTracer::tree(int i, int j, bool plain, std::vector<uint32_t>& rec, std::vector<double>* len64, int& max_depth,
-                     int64_t& n_rays)
+bool DirTracer::tree(int i, int j, OctRays rays, std::vector<uint32_t>& rec, std::vector<double>* len64,
+                     int& max_depth, int64_t& n_rays)
 {
     const int L = M_.Lmax;
     const double dm = du_[2];
+    const bool plain = rays != OctRays::Scheme;
     std::vector<Pending> todo;
     std::vector<int> users;          // rays still to start from each saved vector
-    Pending root;
-    root.line[0] = (int64_t)i << L;
-    root.line[1] = (int64_t)j << L;
-    root.cell[0] = root.line[0];
-    root.cell[1] = root.line[1];
-    root.cell[2] = 0;
-    root.t = 0.0;
-    root.entered = 2;
-    root.tag = 0;
-    root.lev = 0;
-    root.src = -1;
-    todo.push_back(root);
+    // the root line, or with the lattice all 4^L lines of the element (taken
+    // from the back: the first line first)
+    const int64_t nl = rays == OctRays::Lattice ? (int64_t)1 << L : 1;
+    for (int64_t b = nl - 1; b >= 0; --b)
+        for (int64_t a = nl - 1; a >= 0; --a) {
+            Pending root;
+            root.line[0] = ((int64_t)i << L) + a;
+            root.line[1] = ((int64_t)j << L) + b;
+            root.cell[0] = root.line[0];
+            root.cell[1] = root.line[1];
+            root.cell[2] = 0;
+            root.t = 0.0;
+            root.entered = 2;
+            root.tag = 0;
+            root.lev = 0;
+            root.src = -1;
+            todo.push_back(root);
+        }
     while (!todo.empty()) {
         Pending R = todo.back();
         todo.pop_back();
@@ -355,7 +362,7 @@ bool DirTracer::tree(int i, int j, bool plain, std::vector<uint32_t>& rec, std::
 
 }  // namespace
 
-std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, bool plain, int n_threads,
+std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, OctRays rays, int n_threads,
                             OctSchedule& out, bool want_len64, int64_t n_cells)
 {
     const int nd = (int)dirs.size() / 3;
@@ -381,7 +388,7 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
                 for (int64_t r = 0; r < nroot; ++r) {
                     const int64_t off = (int64_t)P.rec.size() / 2;
                     int depth = 0;
-                    if (!tr.tree((int)(r % N), (int)(r / N), plain, P.rec, want_len64 ? &P.len64 : nullptr, depth,
+                    if (!tr.tree((int)(r % N), (int)(r / N), rays, P.rec, want_len64 ? &P.len64 : nullptr, depth,
                                  P.n_rays))
                         P.ok = false;
                     OctTreeRec& T = P.trees[r];

@@ -38,14 +38,20 @@ struct OctSchedule {
     int64_t n_rays = 0;
 };
 
-// Ray schedule of every root element and direction (Sect. 2.2); 'plain'
-// traces single lines (no new rays, no termination: lines of sight).  Trees
-// are ordered by decreasing length.  Uses up to n_threads host threads.
+// Which rays a schedule holds: the octree scheme's created and terminated
+// rays (Sect. 2.2), the root lines alone traced straight (lines of sight for
+// maps), or the brute-force lattice of Sect. 2.2: every line of the finest
+// lattice, 4^Lmax per root element, traced straight.
+enum class OctRays { Scheme = 0, Plain = 1, Lattice = 2 };
+
+// Ray schedule of every root element and direction.  Trees (one per root
+// element: all of its rays in processing order) are ordered by decreasing
+// length.  Uses up to n_threads host threads.
 // want_len64 also keeps the FP64 step lengths (for the FP64 march).
 // n_cells > 0 also lists, per cell, the steps that cross it (at most 2^32
 // steps in all).
 // Returns an empty string on success, else the reason.
-std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, bool plain, int n_threads,
+std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, OctRays rays, int n_threads,
                             OctSchedule& out, bool want_len64 = false, int64_t n_cells = 0);
 
 }  // namespace miloc

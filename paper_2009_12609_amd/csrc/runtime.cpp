@@ -131,6 +131,7 @@ struct miloc_ctx {
     // normalised to sum 1; empty = single Gaussian
     std::vector<std::vector<double>> hf_v, hf_w;
     int hfk = 0;                 // components per transition in d_hf (0: no multiplets)
+    bool oct_lattice = false;    // octree rays: brute-force lattice instead of the created rays
     double hf_lo = 0, hf_hi = 0; // lowest / highest offset over all transitions, channels
     DevBuf d_hf;                 // [T][hfk] {offset / dv, strength}, zero-strength padding
 
@@ -353,7 +354,8 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
     const int nd = (int)c->dirs.size() / 3;
     OctSchedule S;
     const bool fp64 = c->precision == MILOC_MARCH_FP64;
-    const std::string e = octree_schedule(c->oct, c->dirs, false, host_threads(), S, fp64, c->nc);
+    const std::string e = octree_schedule(c->oct, c->dirs, c->oct_lattice ? OctRays::Lattice : OctRays::Scheme,
+                                          host_threads(), S, fp64, c->nc);
     if (!e.empty()) return fail(c, MILOC_EINVAL, e);
     HIPCHK(c, c->d_ocell_off.ensure(S.cell_off.size() * sizeof(int64_t)));
     HIPCHK(c, hipMemcpy(c->d_ocell_off.p, S.cell_off.data(), S.cell_off.size() * sizeof(int64_t),
@@ -623,9 +625,10 @@ miloc_status ensure_static(miloc_ctx* c)
         const double bs = b[k] * std::sqrt(kPi);
         q[k] = W[k] > 0 ? c->dv / (bs * W[k]) : 0.0;
         if (c->kind == 4) {
-            // the octree march leaves out the leaf's h_L^2 of the ray weight;
-            // refined cells are not solved
-            const double hl = std::ldexp(1.0, -(int)c->oct.level[k]);
+            // the octree march leaves out the ray weight's h^2 (the leaf's
+            // h_L with created rays, the finest h with the lattice); refined
+            // cells are not solved
+            const double hl = std::ldexp(1.0, -(c->oct_lattice ? c->oct.Lmax : (int)c->oct.level[k]));
             q[k] = c->oct.child[k] >= 0 ? -1.0 : q[k] * hl * hl;
         }
         nmolLb[k] = cv.nH2(k) * cv.X(k) * Lunit / bs;
@@ -1017,7 +1020,8 @@ miloc_status miloc_octree_schedule(const miloc_model3d* m, int n_dir, const doub
         d[3 * q] = x / nrm; d[3 * q + 1] = y / nrm; d[3 * q + 2] = z / nrm;
     }
     OctSchedule S;
-    if (!octree_schedule(oct, d, plain != 0, host_threads(), S).empty()) return MILOC_EINVAL;
+    if (plain < 0 || plain > 2) return MILOC_EINVAL;
+    if (!octree_schedule(oct, d, static_cast<OctRays>(plain), host_threads(), S).empty()) return MILOC_EINVAL;
     if (n_steps) *n_steps = S.n_steps;
     if (n_trees) *n_trees = (int64_t)S.trees.size();
     if (max_depth) *max_depth = S.max_depth;
@@ -1069,6 +1073,21 @@ miloc_status miloc_set_hyperfine(miloc_ctx* c, int trans, int n_comp, const doub
     for (int k = 0; k < n_comp; ++k) c->hf_w[trans][k] = strength[k] / sum;
     c->dirty = true;
     c->has_rad = false;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_octree_rays(miloc_ctx* c, int rays)
+{
+    miloc_status s = check_ctx(c);
+    if (s) return s;
+    if (rays != MILOC_OCT_RAYS_SCHEME && rays != MILOC_OCT_RAYS_LATTICE)
+        return fail(c, MILOC_EINVAL, "rays must be MILOC_OCT_RAYS_SCHEME or MILOC_OCT_RAYS_LATTICE");
+    const bool lat = rays == MILOC_OCT_RAYS_LATTICE;
+    if (lat != c->oct_lattice) {
+        c->oct_lattice = lat;
+        c->dirty = true;
+        c->has_rad = false;
+    }
     return MILOC_OK;
 }
 
@@ -1367,7 +1386,7 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
         // +z lines of sight on the root ray lattice, traced without new rays
         const std::vector<double> zd = {0.0, 0.0, 1.0};
         OctSchedule S;
-        const std::string e = octree_schedule(c->oct, zd, true, host_threads(), S, fp64);
+        const std::string e = octree_schedule(c->oct, zd, OctRays::Plain, host_threads(), S, fp64);
         if (!e.empty()) return fail(c, MILOC_EINVAL, e);
         DevBuf steps, trees, zdir, zaw, zwin, zlen;
         s = upload_oct_schedule(c, S, steps, trees);

@@ -112,3 +112,25 @@ def test_octree_sixteen_lane_groups(monkeypatch):
     assert ctx.counters()["march_lanes"] == 16
     assert_pops(ctx.populations()[lf], ref.x[lf], 1e-5, "octree 16 lanes")
     ctx.close()
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-10)])
+def test_octree_lattice_iterations(fp64, tol):
+    """The brute-force lattice (miloc_set_octree_rays): 4^2 straight lines per
+    root element of a two-level tree, every iteration against the oracle's
+    lattice march; the scheme's rays are restored by switching back."""
+    w = oct_workload(n_refine=2)
+    lf = leaf_rows(w)
+    print(f"[octree lattice] cells per level {w.model.n_cells_per_level} fp64={fp64}", flush=True)
+    ref = oracle.run_oct(w.mol, w.model, w.spec, w.T_bg, 3, brute=True)
+    ctx = make_ctx(w, fp64=fp64)
+    ctx.set_octree_rays(True)
+    for it in range(3):
+        ctx.run(1)
+        assert_pops(ctx.populations()[lf], ref.history[it]["x"][lf], tol, f"octree lattice it {it}")
+    ctx.set_octree_rays(False)
+    ctx.init_lte()
+    ctx.run(2)
+    ref_s = oracle.run_oct(w.mol, w.model, w.spec, w.T_bg, 2)
+    assert_pops(ctx.populations()[lf], ref_s.x[lf], tol, "octree scheme after the lattice")
+    ctx.close()

@@ -52,6 +52,34 @@ def test_schedule_paths_match_oracle(N, nref, frac, seed):
         assert np.all(cover == 1)
 
 
+@pytest.mark.parametrize("N,nref,frac,seed", [(3, 2, 0.35, 2), (2, 3, 0.5, 3)])
+def test_lattice_schedule_matches_oracle(N, nref, frac, seed):
+    """The brute-force lattice: per direction and leaf of level L the lines
+    cross it along h_L^3 / (h_Lmax^2 |d_m|) in all, with the oracle's step
+    count; every line starts from the background and nothing is saved."""
+    m = _model(N, nref, frac, seed)
+    tree = oracle.octree_of(m)
+    nc = tree.child.shape[0]
+    hmax = 0.5 ** tree.Lmax
+    for d in _dirs()[::2]:
+        steps, trees, depth = miloc.octree_schedule(m, d[None, :], lattice=True)
+        assert depth == 0
+        cell = (steps[:, 0] & CELL).astype(np.int64)
+        ln = steps[:, 1].view(np.float32).astype(np.float64)
+        assert np.all(tree.child[cell] < 0)
+        assert not np.any(steps[:, 0] & (1 << 28))                     # no saved vectors
+        assert np.all((steps[:, 0] >> 29) <= 1)                        # continue or background only
+        path = np.bincount(cell, weights=ln, minlength=nc)
+        dm = np.max(np.abs(d))
+        expect = np.where(tree.leaf, (0.5 ** tree.level) ** 3 / (hmax ** 2 * dm), 0.0)
+        assert np.allclose(path, expect, rtol=2e-6, atol=0)
+        res, st = oracle.march_oct(tree, 1.0, *([None] * 6), d[None, :], None, 0.0, brute=True)
+        assert st["steps"] == steps.shape[0]
+        starts = int(np.sum((steps[:, 0] >> 29) == 1))
+        assert starts == st["root"] + st["wrapped"]
+        assert trees.shape[0] == N * N
+
+
 def _replay(steps, trees, dirs, tree, root_cm, v, bD, kap, eta, spec, I_bg):
     """FP64 replay of a schedule: per tree, records in order; intensity start
     modes and the saved-vector stack as documented for the records."""
