@@ -653,30 +653,26 @@ __device__ __forceinline__ void copy_pieces(T* __restrict__ dst, const T* __rest
 }
 
 // Per-group stack of channel spans [lo, hi) in registers: entry e lives in
-// lane e % LANES, slot e / LANES.
+// lane e % LANES, slot e / LANES, as lo | hi << 16 (channel counts are at
+// most 4096), so that a push or a read selects among SLOTS words once.
 template <int LANES, int SLOTS>
 struct SpanStack {
-    int lo[SLOTS], hi[SLOTS];
+    int v[SLOTS];
     __device__ __forceinline__ void set(int e, int lane, int l, int h)
     {
         const bool mine = lane == e % LANES;
+        const int w = l | (h << 16);
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            const bool at = mine && s == e / LANES;
-            lo[s] = at ? l : lo[s];
-            hi[s] = at ? h : hi[s];
-        }
+        for (int s = 0; s < SLOTS; ++s) v[s] = mine && s == e / LANES ? w : v[s];
     }
     __device__ __forceinline__ void get(int e, int& l, int& h) const
     {
-        int a = 0, b = 0;
+        int a = 0;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            a = s == e / LANES ? lo[s] : a;
-            b = s == e / LANES ? hi[s] : b;
-        }
-        l = __shfl(a, e % LANES, LANES);
-        h = __shfl(b, e % LANES, LANES);
+        for (int s = 0; s < SLOTS; ++s) a = s == e / LANES ? v[s] : a;
+        a = __shfl(a, e % LANES, LANES);
+        l = a & 0xFFFF;
+        h = a >> 16;
     }
 };
 
@@ -740,21 +736,30 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         // whole chunk are fetched in parallel instead of one dependent load per
         // step (the cells of a ray's steps are scattered over the tree), then
         // broadcast step by step with shuffles.
-        // The next chunk is loaded while the current one is processed.
-        uint2 mine, nx;
-        double mine64 = 0.0, nx64 = 0.0;
+        // The next chunk's cell data are loaded while the current one is
+        // processed, and the records of the chunk after it one chunk earlier
+        // still, so that the cell loads never wait on their record.
+        uint2 mine, nx, nr{};
+        double mine64 = 0.0, nx64 = 0.0, nr64 = 0.0;
         T4 mywv, nxwv{};
         T2 mykv, nxkv{};
-        auto load_chunk = [&](int s0, uint2& r, double& r64, T4& wvv, T2& kvv) {
+        auto load_rec = [&](int s0, uint2& r, double& r64) {
             const int si = s0 + lane < tr.n ? s0 + lane : s0;
             r = rec[si];
             if (sizeof(T) == 8 && rec64) r64 = rec64[si];
+        };
+        auto load_cells = [&](const uint2& r, T4& wvv, T2& kvv) {
             const unsigned c = r.x & kOctCellMask;
             wvv = win[c];
             kvv = ke[(size_t)c * p.ntr_total];
         };
-        load_chunk(0, mine, mine64, mywv, mykv);
-        if (LANES < tr.n) load_chunk(LANES, nx, nx64, nxwv, nxkv);
+        load_rec(0, mine, mine64);
+        load_cells(mine, mywv, mykv);
+        if (LANES < tr.n) {
+            load_rec(LANES, nx, nx64);
+            load_cells(nx, nxwv, nxkv);
+        }
+        if (2 * LANES < tr.n) load_rec(2 * LANES, nr, nr64);
         for (int s = 0; s < tr.n; ++s) {
             const int k = s & (LANES - 1);
             if (k == 0 && s > 0) {
@@ -762,7 +767,12 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
                 mine64 = nx64;
                 mywv = nxwv;
                 mykv = nxkv;
-                if (s + LANES < tr.n) load_chunk(s + LANES, nx, nx64, nxwv, nxkv);
+                if (s + LANES < tr.n) {
+                    nx = nr;
+                    nx64 = nr64;
+                    load_cells(nx, nxwv, nxkv);
+                }
+                if (s + 2 * LANES < tr.n) load_rec(s + 2 * LANES, nr, nr64);
             }
             const unsigned w0 = __shfl(mine.x, k, LANES);
             T len = (T)__uint_as_float(__shfl(mine.y, k, LANES));
@@ -856,13 +866,15 @@ __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); 
 
 // One workgroup marches rays ray0 .. ray0 + rays_per_block - 1 of one
 // transition through a 1D shell model.  Each ray's steps {length, Doppler
-// shift in channels} were computed once on the host in FP64 (Sect. 2.1: the
-// paths are fixed, so they are precomputed); the shell of step s follows from
-// s and the ray's innermost shell.  Records arrive 16 at a time, one per
-// lane, and the next step's shell data are loaded before the current step
-// runs.  With p.lds_acc the per-step sums go to per-shell LDS accumulators
-// (LDS atomics do not stall the next step's loads), flushed to the FP64
-// global sums once per workgroup; otherwise each step issues two FP64 atomics.
+// shift in channels} were computed once per model in FP64 by ray_steps_kernel
+// (Sect. 2.1: the paths are fixed, so they are precomputed); the shell of step
+// s follows from s and the ray's innermost shell.  Records arrive LANES at a
+// time, one per lane (loading the next chunk a chunk ahead measured 11%
+// slower in the request loop), and the next step's shell data are loaded
+// before the current step runs.  With p.lds_acc the per-step sums go to
+// per-shell LDS accumulators (LDS atomics do not stall the next step's
+// loads), flushed to the FP64 global sums once per workgroup; otherwise each
+// step issues two FP64 atomics.
 template <typename T, int LANES, bool ACCUM, bool TRANS_GROUPS = false, bool HF = false>
 __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0, int t_in, unsigned char* smem_raw)
 {
