@@ -70,41 +70,47 @@ def test_1d_hyperfine_fp32_rotor():
     ctx.close()
 
 
-def test_3d_hyperfine_fp32():
+@pytest.mark.parametrize("fp64", [False, True])
+def test_3d_hyperfine(fp64):
     """Turbulent 9^3 cube, 48 directions, thick (X = 1e-7), multiplet on the
     first transition of a 5-level rotor; spectra of the multiplet."""
     w = workload_3d(9, seed=109, abundance=1e-7, n_levels=5, box_pc=0.075, half=5.0)
     hfs = {0: (HF_V, HF_W)}
-    print("[case] 3d hyperfine fp32", flush=True)
+    print(f"[case] 3d hyperfine fp64={fp64}", flush=True)
     ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, 3, hyperfine=hfs)
-    ctx = hf_ctx(w, hfs)
+    ctx = hf_ctx(w, hfs, fp64=fp64)
     ctx.run(3)
-    assert_pops(ctx.populations(), ref.x, 1e-5, "3d hf")
+    tol = 1e-10 if fp64 else 1e-5
+    assert_pops(ctx.populations(), ref.x, tol, f"3d hf fp64={fp64}")
     J, Lam = ctx.radiation()
     h = ref.history[-1]
-    assert np.allclose(J, h["J"], rtol=2e-5, atol=0)
-    assert np.allclose(Lam, h["Lam"], rtol=2e-5, atol=1e-9)
+    assert np.allclose(J, h["J"], rtol=1e-9 if fp64 else 2e-5, atol=0)
+    assert np.allclose(Lam, h["Lam"], rtol=1e-9 if fp64 else 2e-5, atol=1e-9)
     sp = ctx.spectra(0, n_los=81)
     ref_sp = oracle.spectra_3d(w.mol, w.model, w.spec, w.T_bg, ref.x, 0, shape=hfs[0])
-    assert_spectra(sp, ref_sp, 1e-4, "3d hf spectra")
+    assert_spectra(sp, ref_sp, 1e-9 if fp64 else 1e-4, f"3d hf spectra fp64={fp64}")
     ctx.close()
 
 
-def test_octree_hyperfine_fp32():
-    """Octree (root 4^3, three refinement levels) with the multiplet on the
-    first transition: every iteration's leaf populations, and the +z map."""
-    w = oct_workload(half=5.0)
+@pytest.mark.parametrize("fp64,lattice", [(False, False), (True, False), (False, True)])
+def test_octree_hyperfine(fp64, lattice):
+    """Octree (root 4^3, three refinement levels; two with the brute-force
+    lattice) with the multiplet on the first transition: every iteration's
+    leaf populations, and the +z map."""
+    w = oct_workload(half=5.0, n_refine=2 if lattice else 3)
     hfs = {0: (HF_V, HF_W)}
     lf = leaf_rows(w)
-    print("[case] octree hyperfine fp32", flush=True)
-    ref = oracle.run_oct(w.mol, w.model, w.spec, w.T_bg, 2, hyperfine=hfs)
-    ctx = hf_ctx(w, hfs)
+    print(f"[case] octree hyperfine fp64={fp64} lattice={lattice}", flush=True)
+    ref = oracle.run_oct(w.mol, w.model, w.spec, w.T_bg, 2, hyperfine=hfs, brute=lattice)
+    ctx = hf_ctx(w, hfs, fp64=fp64)
+    ctx.set_octree_rays(lattice)
+    tol = 1e-10 if fp64 else 1e-5
     for it in range(2):
         ctx.run(1)
-        assert_pops(ctx.populations()[lf], ref.history[it]["x"][lf], 1e-5, f"octree hf it {it}")
+        assert_pops(ctx.populations()[lf], ref.history[it]["x"][lf], tol, f"octree hf it {it}")
     sp = ctx.spectra(0, n_los=w.model.n0[0] ** 2)
     sref = oracle.spectra_oct(w.mol, w.model, w.spec, w.T_bg, ref.x, 0, shape=hfs[0])
-    assert_spectra(sp, sref, 1e-4, "octree hf +z map")
+    assert_spectra(sp, sref, 1e-9 if fp64 else 1e-4, "octree hf +z map")
     ctx.close()
 
 
