@@ -80,6 +80,15 @@ __device__ __forceinline__ float dpp_add(float v)
     return v + __builtin_bit_cast(float, got);
 }
 
+// Keeps v computed where it stands rather than sunk into a following branch
+// that is its only use (an empty asm statement: no instruction).  Used on the
+// group sums: sunk, their last DPP stage cannot be fused into its add.
+template <typename T>
+__device__ __forceinline__ void keep_here(T& v)
+{
+    asm volatile("" : "+v"(v));
+}
+
 template <int LANES>
 __device__ __forceinline__ float group_sum(float v)
 {
@@ -486,15 +495,16 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr);
         (void)dummy;
         if (ACCUM) {
-            sj = group_sum<LANES>(sj);
-            sl = group_sum<LANES>(sl);
-            if (lane == LANES - 1) {
-                const T wgt = aw * rec.len;
-                T2 v;
-                v.x = wgt * sj;
-                v.y = wgt * sl;
-                qw[qn * rpw + (rib % rpw)] = v;
-            }
+            // every lane forms the weighted sums (the wavefront issues them
+            // either way); only the group's last lane, which holds the
+            // total, stores them
+            const T wgt = aw * rec.len;
+            T2 v;
+            v.x = wgt * group_sum<LANES>(sj);
+            v.y = wgt * group_sum<LANES>(sl);
+            keep_here(v.x);
+            keep_here(v.y);
+            if (lane == LANES - 1) qw[qn * rpw + (rib % rpw)] = v;
             ++qn;
             if (qn == LANES || s == ns - 1) {
                 const int rq = r_first + q_ray;
@@ -829,15 +839,13 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             T sj = 0, sl = 0;
             window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr);
             if (ACCUM) {
-                sj = group_sum<LANES>(sj);
-                sl = group_sum<LANES>(sl);
-                if (lane == LANES - 1) {
-                    const T wgt = aw * len;
-                    T2q v;
-                    v.x = wgt * sj;
-                    v.y = wgt * sl;
-                    queue[qn] = v;
-                }
+                const T wgt = aw * len;
+                T2q v;
+                v.x = wgt * group_sum<LANES>(sj);
+                v.y = wgt * group_sum<LANES>(sl);
+                keep_here(v.x);
+                keep_here(v.y);
+                if (lane == LANES - 1) queue[qn] = v;
                 ++qn;
                 __builtin_amdgcn_wave_barrier();
                 if (qn == LANES || s == tr.n - 1) {
