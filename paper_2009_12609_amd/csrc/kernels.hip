@@ -953,6 +953,8 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
+                keep_here(sj);
+                keep_here(sl);
                 if (lane == LANES - 1) {
                     const double wgt = a * (double)tl;
                     if (lds_acc) {
