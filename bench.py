@@ -459,6 +459,7 @@ def main():
             "march": "FP32 intensities, FP64 accumulation, FP64 equilibrium solve",
             "march_ms_per_launch": march_ms,
             "prepare_ms_per_step": cnt["prepare_ms"] / max(1, cnt["iterations"]),
+            "gather_ms_per_step": cnt["accumulate_ms"] / max(1, cnt["iterations"]),
             "solve_ms_per_step": cnt["solve_ms"] / max(1, cnt["iterations"]),
             "march_updates_per_s": updates / (cnt["march_ms"] * 1e-3),
         },
