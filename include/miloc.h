@@ -225,7 +225,9 @@ miloc_status miloc_set_background(miloc_ctx* ctx, double T_bg_K);
  * element (Lmax = the deepest level), each of weight h_Lmax^2 |d_m|, no rays
  * created or ended (cost grows as 4^Lmax: for shallow trees).  Applies to
  * octree models (ignored otherwise); the ray schedule is rebuilt at the next
- * miloc_run.  MILOC_EINVAL for another value. */
+ * miloc_run, which returns MILOC_EINVAL when the lattice could exceed 4e9
+ * steps ((N 2^Lmax)^2 lines per direction of at most 3 N 2^Lmax steps).
+ * MILOC_EINVAL for another value of rays. */
 #define MILOC_OCT_RAYS_SCHEME 0
 #define MILOC_OCT_RAYS_LATTICE 1
 miloc_status miloc_set_octree_rays(miloc_ctx* ctx, int rays);

@@ -368,6 +368,16 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
     const int nd = (int)dirs.size() / 3;
     const int N = M.N;
     const int64_t nroot = (int64_t)N * N;
+    if (rays == OctRays::Lattice) {
+        // refuse before building what would not fit: a line of the finest
+        // lattice takes at most 3 N 2^Lmax steps (one per finest cell along
+        // each axis), 8 bytes each, and there are (N 2^Lmax)^2 per direction
+        const double side = std::ldexp((double)N, M.Lmax);
+        const double bound = (double)nd * side * side * 3.0 * side;
+        if (bound > 4.0e9)
+            return "octree: the brute-force lattice of this tree may take up to " + std::to_string(bound) +
+                   " steps (limit 4e9); use the octree scheme";
+    }
     struct Part {
         std::vector<uint32_t> rec;
         std::vector<double> len64;

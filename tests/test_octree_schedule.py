@@ -151,3 +151,18 @@ def test_schedule_rejects_bad_trees():
     bad.first_child = fc
     with pytest.raises(miloc.MilocError):
         miloc.octree_schedule(bad, np.array([[0, 0, 1.0]]))
+
+
+def test_lattice_refuses_oversize_schedules():
+    """A deep tree's brute-force lattice is refused before it is built (the
+    bound: (N 2^Lmax)^2 lines per direction of at most 3 N 2^Lmax steps),
+    while the octree scheme's schedule of the same tree is built."""
+    m = synth.octree_random(16, 4, 0.02, 13, 16.0, 1e3, 10.0, 0.0, 1e-9)
+    rng = np.random.default_rng(1)
+    d = rng.normal(size=(100, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    with pytest.raises(miloc.MilocError) as e:
+        miloc.octree_schedule(m, d, lattice=True)
+    assert e.value.code == miloc.EINVAL
+    steps, trees, _ = miloc.octree_schedule(m, d[:2])
+    assert steps.shape[0] > 0 and trees.shape[0] == 2 * 16 * 16
