@@ -216,6 +216,8 @@ miloc_status miloc_set_background(miloc_ctx* ctx, double T_bg_K);
  * without a molecule, MILOC_EINVAL for a bad index, count, offset or
  * strength (state unchanged). */
 #define MILOC_MAX_HF_COMPONENTS 32
+miloc_status miloc_set_hyperfine(miloc_ctx* ctx, int trans, int n_comp, const double* dv_cms,
+                                 const double* strength);
 
 /* Rays of the octree march (Sect. 2.2).  MILOC_OCT_RAYS_SCHEME (default):
  * rays created on entering refined cells and through side faces, ended in
@@ -231,8 +233,6 @@ miloc_status miloc_set_background(miloc_ctx* ctx, double T_bg_K);
 #define MILOC_OCT_RAYS_SCHEME 0
 #define MILOC_OCT_RAYS_LATTICE 1
 miloc_status miloc_set_octree_rays(miloc_ctx* ctx, int rays);
-miloc_status miloc_set_hyperfine(miloc_ctx* ctx, int trans, int n_comp, const double* dv_cms,
-                                 const double* strength);
 
 /* 3D ray directions: the 12*nside^2 HEALPix pixel centres (Sect. 2.2; 48 for
  * nside = 2, the default).  nside 1..8. */
