@@ -440,10 +440,6 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
     const int ns = D.nsteps;
     HfRegs<T> hfr;
     if constexpr (HF) hfr.load(p.hf + (size_t)t * p.hfk, p.hfk);
-    // Invalid channel slots read and write a private dummy word in the
-    // ray's padding so that no lane touches another ray's channels.
-    T* __restrict__ dummy = I + p.nch + lane;
-
     for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
 
     // Per-step partial sums {a len sum_c e_c I_c beta_c, a len sum_c e_c (1 - beta_c)}
@@ -493,7 +489,6 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         const T el = kv.y * rec.len;
         T sj = 0, sl = 0;
         window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr);
-        (void)dummy;
         if (ACCUM) {
             // every lane forms the weighted sums (the wavefront issues them
             // either way); only the group's last lane, which holds the
