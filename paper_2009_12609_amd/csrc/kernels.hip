@@ -715,70 +715,95 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
     // deeper stacks than the span registers hold copy whole vectors
     const bool use_spans = p.depth <= kSpanSlots * LANES;
     int lo = 0, hi = p.nch;                       // LDS contents unknown: a full reset first
+    // Work units start only at chunk boundaries, which all groups of the
+    // wavefront reach together: the records of a chunk are loaded (and the
+    // per-step sums flushed) once per LANES steps for the whole wavefront
+    // instead of whenever any of its groups crosses a boundary.  A group whose
+    // unit ends inside a chunk idles to the boundary (units are thousands of
+    // steps long).
+    bool have = false, done = false;
+    OctTreeRec tr{};
+    int t = 0, s = 0, qn = 0, qs0 = 0, sp = -1;
+    const T4* __restrict__ win = p.win;
+    const T2* __restrict__ ke = p.ke;
+    const uint2* __restrict__ rec = p.steps;
+    const double* __restrict__ rec64 = nullptr;
+    T2q* __restrict__ Et = nullptr;
+    T aw = 0, Ibg = 0;
+    HfRegs<T> hfr;
+    // Records arrive LANES at a time, one per lane, and each lane also loads
+    // the window and {khat, ehat} of its record's cell: the cell data of a
+    // whole chunk are fetched in parallel instead of one dependent load per
+    // step (the cells of a ray's steps are scattered over the tree), then
+    // broadcast step by step with shuffles.  The next chunk's cell data are
+    // loaded while the current one is processed, and the records of the chunk
+    // after it one chunk earlier still, so that the cell loads never wait on
+    // their record.
+    uint2 mine{}, nx{}, nr{};
+    double mine64 = 0.0, nx64 = 0.0, nr64 = 0.0;
+    T4 mywv{}, nxwv{};
+    T2 mykv{}, nxkv{};
+    auto load_rec = [&](int s0, uint2& r, double& r64) {
+        const int si = s0 + lane < tr.n ? s0 + lane : s0;
+        r = rec[si];
+        if (sizeof(T) == 8 && rec64) r64 = rec64[si];
+    };
+    auto load_cells = [&](const uint2& r, T4& wvv, T2& kvv) {
+        const unsigned c = r.x & kOctCellMask;
+        wvv = win[c];
+        kvv = ke[(size_t)c * p.ntr_total];
+    };
     for (;;) {
-        unsigned long long item = 0;
-        if (lane == 0) item = atomicAdd(p.counter, 1ull);
-        item = __shfl(item, 0, LANES);
-        if (item >= (unsigned long long)p.n_items) break;
-        lo = 0;                                   // a new transition's background everywhere
-        hi = p.nch;
-        const long long tree = (long long)(item / (unsigned long long)p.ntr);
-        const int t = p.trans_offset + (int)(item % (unsigned long long)p.ntr);
-        const OctTreeRec tr = p.trees[tree];
-        const T4* __restrict__ win = p.win + (size_t)tr.q * p.nc;
-        const T2* __restrict__ ke = p.ke + t;
-        const uint2* __restrict__ rec = p.steps + tr.off;
-        const T aw = (T)p.aw[tr.q];
-        const T Ibg = p.Ibg[t];
-        HfRegs<T> hfr;
-        if constexpr (HF) hfr.load(p.hf + (size_t)t * p.hfk, p.hfk);
-        const double* __restrict__ rec64 = p.len64 ? p.len64 + tr.off : nullptr;
-        T2q* __restrict__ Et = p.E ? p.E + (size_t)tr.off * p.estride + (t - p.trans_offset) : nullptr;
-        int qn = 0, qs0 = 0;
-        int sp = -1;
-        // Records arrive LANES at a time, one per lane, and each lane also loads
-        // the window and {khat, ehat} of its record's cell: the cell data of a
-        // whole chunk are fetched in parallel instead of one dependent load per
-        // step (the cells of a ray's steps are scattered over the tree), then
-        // broadcast step by step with shuffles.
-        // The next chunk's cell data are loaded while the current one is
-        // processed, and the records of the chunk after it one chunk earlier
-        // still, so that the cell loads never wait on their record.
-        uint2 mine, nx, nr{};
-        double mine64 = 0.0, nx64 = 0.0, nr64 = 0.0;
-        T4 mywv, nxwv{};
-        T2 mykv, nxkv{};
-        auto load_rec = [&](int s0, uint2& r, double& r64) {
-            const int si = s0 + lane < tr.n ? s0 + lane : s0;
-            r = rec[si];
-            if (sizeof(T) == 8 && rec64) r64 = rec64[si];
-        };
-        auto load_cells = [&](const uint2& r, T4& wvv, T2& kvv) {
-            const unsigned c = r.x & kOctCellMask;
-            wvv = win[c];
-            kvv = ke[(size_t)c * p.ntr_total];
-        };
-        load_rec(0, mine, mine64);
-        load_cells(mine, mywv, mykv);
-        if (LANES < tr.n) {
-            load_rec(LANES, nx, nx64);
-            load_cells(nx, nxwv, nxkv);
-        }
-        if (2 * LANES < tr.n) load_rec(2 * LANES, nr, nr64);
-        for (int s = 0; s < tr.n; ++s) {
-            const int k = s & (LANES - 1);
-            if (k == 0 && s > 0) {
-                mine = nx;
-                mine64 = nx64;
-                mywv = nxwv;
-                mykv = nxkv;
-                if (s + LANES < tr.n) {
-                    nx = nr;
-                    nx64 = nr64;
+        if (have) {
+            // a chunk boundary inside the unit (s is a positive multiple of LANES)
+            mine = nx;
+            mine64 = nx64;
+            mywv = nxwv;
+            mykv = nxkv;
+            if (s + LANES < tr.n) {
+                nx = nr;
+                nx64 = nr64;
+                load_cells(nx, nxwv, nxkv);
+            }
+            if (s + 2 * LANES < tr.n) load_rec(s + 2 * LANES, nr, nr64);
+        } else if (!done) {
+            unsigned long long item = 0;
+            if (lane == 0) item = atomicAdd(p.counter, 1ull);
+            item = __shfl(item, 0, LANES);
+            if (item >= (unsigned long long)p.n_items) {
+                done = true;
+            } else {
+                have = true;
+                lo = 0;                           // a new transition's background everywhere
+                hi = p.nch;
+                const long long tree = (long long)(item / (unsigned long long)p.ntr);
+                t = p.trans_offset + (int)(item % (unsigned long long)p.ntr);
+                tr = p.trees[tree];
+                win = p.win + (size_t)tr.q * p.nc;
+                ke = p.ke + t;
+                rec = p.steps + tr.off;
+                aw = (T)p.aw[tr.q];
+                Ibg = p.Ibg[t];
+                if constexpr (HF) hfr.load(p.hf + (size_t)t * p.hfk, p.hfk);
+                rec64 = p.len64 ? p.len64 + tr.off : nullptr;
+                Et = p.E ? p.E + (size_t)tr.off * p.estride + (t - p.trans_offset) : nullptr;
+                s = 0;
+                qn = 0;
+                qs0 = 0;
+                sp = -1;
+                load_rec(0, mine, mine64);
+                load_cells(mine, mywv, mykv);
+                if (LANES < tr.n) {
+                    load_rec(LANES, nx, nx64);
                     load_cells(nx, nxwv, nxkv);
                 }
-                if (s + 2 * LANES < tr.n) load_rec(s + 2 * LANES, nr, nr64);
+                if (2 * LANES < tr.n) load_rec(2 * LANES, nr, nr64);
             }
+        }
+        // every group without a unit has found the counter exhausted
+        if (__all(!have)) break;
+        for (int k = 0; k < LANES; ++k) {
+            if (!have || s >= tr.n) continue;
             const unsigned w0 = __shfl(mine.x, k, LANES);
             T len = (T)__uint_as_float(__shfl(mine.y, k, LANES));
             if (sizeof(T) == 8 && rec64) len = (T)__shfl(mine64, k, LANES);
@@ -850,10 +875,14 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            ++s;
         }
-        if (!ACCUM && p.Iout) {
-            T* out = p.Iout + (size_t)tr.r * p.nch;
-            for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
+        if (have && s >= tr.n) {
+            if (!ACCUM && p.Iout) {
+                T* out = p.Iout + (size_t)tr.r * p.nch;
+                for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
+            }
+            have = false;
         }
         __builtin_amdgcn_wave_barrier();
     }
