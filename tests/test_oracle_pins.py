@@ -486,6 +486,116 @@ def test_p4_lte_limit_high_density():
     assert np.max(np.abs(run.x[big] / lte[big] - 1)) < 1e-6
 
 
+# ---------------------------------------------------------------------------
+# Absolute scales: the Doppler width and the opacity / emissivity of
+# ``prepare`` (Sect. 2, Eqs. (1)-(3)), and the convergence measure (Sect. 2:
+# iterate until the populations stop changing)
+# ---------------------------------------------------------------------------
+
+# Textbook constants typed here, not taken from the oracle: CODATA-2018 exact
+# k_B, h, c and the 2018 atomic mass constant.
+K_B_CGS = 1.380649e-16
+H_CGS = 6.62607015e-27
+C_CGS = 2.99792458e10
+AMU_G = 1.66053906660e-24
+
+
+def _thin_sphere(T, b_turb, abundance, n_H2=1.0e3, radius_pc=0.01, n_shells=4, n_rays=4):
+    return synth.uniform_sphere_1d(n_shells=n_shells, radius_cm=radius_pc * synth.PC_CM,
+                                   n_H2=n_H2, T_kin=T, b_turb=b_turb, abundance=abundance,
+                                   n_rays=n_rays)
+
+
+@pytest.mark.parametrize("T,b_turb_kms", [(10.0, 0.0), (40.0, 0.15)])
+def test_doppler_width_from_thin_line_moments(T, b_turb_kms):
+    """An optically thin, static, uniform sphere with no background emits the
+    profile itself: the velocity variance of the emergent line is the 1D
+    Maxwell variance k T / m plus the turbulent part b_turb^2 / 2 (a Gaussian
+    exp(-v^2/b^2) has variance b^2/2).  Pins the thermal width: a k T / m for
+    2 k T / m, a wrong atomic mass unit or a turbulent term added linearly
+    each change the variance at O(1)."""
+    mol = _thin_two_level()
+    m = _thin_sphere(T, b_turb_kms * KMS, abundance=1e-17)
+    var_ref = K_B_CGS * T / (mol.mass_amu * AMU_G) + 0.5 * (b_turb_kms * KMS) ** 2
+    half = 10.0 * math.sqrt(2.0 * var_ref) / KMS          # +-10 Doppler widths
+    spec = synth.Spectral.symmetric(1024, half)           # ~50 channels per width
+    x = oracle.lte_populations(mol, m.T_kin)
+    sp = oracle.spectra_1d(mol, m, spec, 0.0, x, 0)
+    v = spec.v_min + (np.arange(spec.n_channels) + 0.5) * spec.dv
+    for row in sp:
+        assert row.min() >= 0.0 and row.max() > 0.0
+        mean = float(np.sum(v * row) / np.sum(row))
+        var = float(np.sum((v - mean) ** 2 * row) / np.sum(row))
+        assert abs(mean) < 1e-9 * math.sqrt(var_ref)
+        assert var == pytest.approx(var_ref, rel=1e-9)
+
+
+def test_absolute_emissivity_thin_column():
+    """Optically thin line without a background: the integrated line
+    temperature W = sum_c T_R dv (T_R = c^2 dI / (2 k nu^2)) and the column of
+    upper-level molecules along the line of sight obey the radio relation
+    N_u = 8 pi k nu^2 W / (h c^3 A_ul).  The column is counted here from the
+    model (n_mol = X n_H2, the ray's chord through the uniform sphere), so the
+    absolute scale of the emissivity (h c / 4 pi) A n_mol x_u is pinned, not
+    only its ratio to the opacity."""
+    mol = _thin_two_level()
+    X = 3.0e-17
+    m = _thin_sphere(15.0, 0.1 * KMS, abundance=X, n_shells=3, n_rays=5)
+    spec = synth.Spectral.symmetric(512, 1.5)
+    x = oracle.lte_populations(mol, m.T_kin)
+    sp = oracle.spectra_1d(mol, m, spec, 0.0, x, 0)
+    nu, A = float(mol.nu[0]), float(mol.A[0])
+    R = float(m.r_out[-1])
+    b = (np.arange(m.n_rays) + 0.5) * R / m.n_rays
+    chord = 2.0 * np.sqrt(R ** 2 - b ** 2)
+    N_u = m.n_H2[0] * X * x[0, 1] * chord
+    W = np.sum(C_CGS ** 2 * sp / (2.0 * K_B_CGS * nu ** 2), axis=1) * spec.dv
+    N_u_radio = 8.0 * math.pi * K_B_CGS * nu ** 2 * W / (H_CGS * C_CGS ** 3 * A)
+    assert np.allclose(N_u_radio, N_u, rtol=1e-8)
+
+
+def test_absolute_opacity_ground_state_absorption():
+    """All molecules in the lower level (no emission): the sphere only
+    absorbs the background, dI = I_bg (e^-tau - 1), and the velocity-integrated
+    optical depth of the line equals the textbook
+    sum_c tau_c dv = (c^3 / (8 pi nu^3)) A_ul (g_u/g_l) N_l with N_l = X n_H2
+    times the chord.  The Doppler width drops out of the integral, so this pins
+    the absolute opacity scale independently of the width."""
+    mol = _thin_two_level()
+    X = 2.0e-6
+    m = _thin_sphere(12.0, 0.12 * KMS, abundance=X, n_shells=3, n_rays=5)
+    spec = synth.Spectral.symmetric(400, 2.0)
+    x = np.zeros((m.n_shells, 2))
+    x[:, 0] = 1.0
+    T_bg = 8.0
+    sp = oracle.spectra_1d(mol, m, spec, T_bg, x, 0)
+    I_bg = 2.0 * H_CGS * mol.nu[0] ** 3 / C_CGS ** 2 / math.expm1(H_CGS * mol.nu[0] / (K_B_CGS * T_bg))
+    tau = -np.log1p(sp / I_bg)
+    nu, A = float(mol.nu[0]), float(mol.A[0])
+    g_ratio = float(mol.g[1] / mol.g[0])
+    R = float(m.r_out[-1])
+    b = (np.arange(m.n_rays) + 0.5) * R / m.n_rays
+    N_l = m.n_H2[0] * X * 2.0 * np.sqrt(R ** 2 - b ** 2)
+    ref = C_CGS ** 3 / (8.0 * math.pi * nu ** 3) * A * g_ratio * N_l
+    got = np.sum(tau, axis=1) * spec.dv
+    assert tau.max() > 0.3          # a real absorption line, not the thin limit
+    assert np.allclose(got, ref, rtol=1e-9)
+
+
+def test_max_rel_change_worked_example():
+    """The convergence measure on populations worked out by hand: relative to
+    the new value, entries below 1e-10 ignored, zero when nothing is left."""
+    x_old = np.array([[0.5, 0.5], [0.8, 0.2], [1.0 - 5e-11, 5e-11], [1.0 - 1e-10, 1e-10]])
+    x_new = np.array([[0.4, 0.6], [0.8, 0.2], [1.0 - 9e-11, 9e-11], [1.0 - 2e-10, 2e-10]])
+    # rows: 0.1/0.4 = 0.25 and 0.1/0.6; 0; 4e-11/(1-9e-11) (9e-11 is below the
+    # floor); 1e-10/(1-2e-10) and 1e-10/2e-10 = 0.5 (2e-10 is above it)
+    assert oracle.max_rel_change(x_new, x_old) == pytest.approx(0.5, rel=1e-6)
+    assert oracle.max_rel_change(x_new[:3], x_old[:3]) == pytest.approx(0.25, rel=1e-12)
+    assert oracle.max_rel_change(x_new[1:3], x_old[1:3]) == pytest.approx(4e-11, rel=1e-6)
+    tiny = np.array([[5e-11, 6e-11]])
+    assert oracle.max_rel_change(tiny, 2 * tiny) == 0.0
+
+
 @pytest.mark.parametrize("abund", [1e-9, 1e-6])
 def test_p5_detailed_balance_fixed_point(abund):
     """T_bg = T_kin everywhere: Boltzmann populations are the exact fixed point
