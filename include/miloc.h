@@ -38,9 +38,10 @@
  *     or 64; octree: 8 or 16).  Default: by the widest channel window
  *     (regular 3D), 16 (1D), 8 (octree).  Results do not depend on it beyond
  *     FP32 summation order.
- *   - MILOC_STEP_BUFFER_GB: device memory (GB, default 160) for the 3D
- *     per-step partial sums; with less, the transitions of an iteration are
- *     marched in several launches.
+ *   - MILOC_STEP_BUFFER_GB: device memory (GB) for the 3D per-step partial
+ *     sums of one march launch (default 16 for regular grids, 160 for
+ *     octrees); the transitions of an iteration that do not fit are marched
+ *     in further launches.
  */
 #ifndef MILOC_H
 #define MILOC_H
@@ -59,7 +60,8 @@ typedef enum {
     MILOC_EDEVICE = -3,  /* HIP runtime error, or no usable gfx950 device                            */
     MILOC_ESTATE = -4,   /* call out of order                                                        */
     MILOC_ENOTCONV = -5, /* miloc_run reached max_iter without meeting tol (results still valid)     */
-    MILOC_ENUMERIC = -6, /* non-finite or negative populations, or a maser optical depth below -40   */
+    MILOC_ENUMERIC = -6, /* non-finite or negative populations, or a maser: a step whose line-centre */
+                         /* optical depth is below -40 (population inversion; see miloc_run)         */
     MILOC_EBUSY = -7     /* resource exhausted (serving: no slot / budget)                           */
 } miloc_status;
 
@@ -266,7 +268,11 @@ miloc_status miloc_set_populations(miloc_ctx* ctx, const double* x);
  * device).  use_ali != 0 selects the ALI form (Sect. 2), 0 the plain lambda
  * iteration.  Stops early when delta < tol (tol <= 0: never).  Populations
  * are initialised to LTE if none are set.  iters_done / last_delta may be
- * NULL.  Returns MILOC_ENOTCONV when tol > 0 was not met (state is valid). */
+ * NULL.  Returns MILOC_ENOTCONV when tol > 0 was not met (state is valid).
+ * Inverted populations (negative opacity, a maser) are marched as written as
+ * long as no single step's line-centre optical depth falls below -40; such a
+ * step stops the run with MILOC_ENUMERIC and the populations of the failed
+ * iteration are not kept (miloc_get_spectra refuses it the same way). */
 miloc_status miloc_run(miloc_ctx* ctx, int max_iter, double tol, int use_ali,
                        int* iters_done, double* last_delta);
 

@@ -1,20 +1,28 @@
 // kernels.hip -- gfx950 kernels of the ALI line ray march.
 //
-//   prepare   populations -> per (transition, cell) opacity/emissivity (khat, ehat)
-//   lte       Boltzmann populations at T_kin
-//   march3d   3D regular grid: HEALPix directions, one ray per upstream surface
-//             cell, side re-entry with background; per step and channel the
-//             radiative update and the absorbed-count / diagonal-operator sums
-//   march1d   1D shells: impact-parameter rays, geometry on the fly (FP64)
-//   se        per-cell statistical equilibrium (FP64 partial-pivot elimination)
-//             and the maximum relative population change
+//   prepare      populations -> per (cell, transition) opacity/emissivity (khat, ehat)
+//   lte          Boltzmann populations at T_kin
+//   window table per (direction, cell) channel window of a regular grid or octree
+//   march3d      3D regular grid: HEALPix directions, one ray per upstream surface
+//                cell, side re-entry with background; per step and channel the
+//                radiative update; per-step partial sums of the absorbed counts
+//                and of the diagonal operator stored for the gather
+//   gather3d     per (cell, transition) FP64 sums of march3d's per-step sums
+//   march_oct    octree: replay of the host-built ray schedule (splits, side
+//                rays, ends) with saved intensity vectors on a per-group stack
+//   gather_oct   per-cell FP64 sums of the octree march's per-step sums
+//   march1d      1D shells: impact-parameter rays whose steps were computed once
+//                per model in FP64 (ray_steps); per-shell FP64 LDS accumulators
+//   se           per-cell statistical equilibrium (FP64 partial-pivot elimination)
+//                and the maximum relative population change
+//   serve_*      the request loop's persistent, model-indexed kernels
 //
-// Lane mapping of the marches: a ray owns a group of LANES (32 or 64) lanes of
-// one wavefront; the lanes cover the channel window of the current step,
+// Lane mapping of the marches: a ray owns a group of LANES (8 or 16; up to 64
+// for lines of sight) consecutive lanes of one wavefront, several rays per
+// wavefront; the lanes cover the channel window of the current step,
 // |v_c + w| <= K b, so only channels where the local profile is significantly
 // non-zero are touched (App. A.2).  The ray's full channel vector lives in LDS.
-// Per step the group reduces its two partial sums in registers and one lane
-// issues two FP64 atomic adds.
+// Per step the group reduces its two partial sums with DPP row operations.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -337,9 +345,15 @@ __device__ __forceinline__ T line_shape(T xs, T ibs, const HfRegs<T>* __restrict
 // profile peaks at most at 1, so |kl| still bounds every |tau_j|).
 template <int LANES, typename T, int KC>
 __device__ __forceinline__ void window_loop(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
-                                            T kl, T el, T& sj, T& sl, const HfRegs<T>* hf)
+                                            T kl, T el, T& sj, T& sl, const HfRegs<T>* hf,
+                                            unsigned* __restrict__ maser)
 {
     const bool thin = __all(kl < (T)0.01 && kl > (T)-0.01);
+    // A population inversion strong enough for a line-centre optical depth
+    // below kMaserTauMin over one step is reported, not marched on (its
+    // exponential gain leaves the FP32 range soon after); only steps off the
+    // thin path can qualify.
+    if (!thin && kl < (T)kMaserTauMin) *maser = 1u;
     T* __restrict__ row = I + clo;
     if (thin) {
         for (int j = lane; j < nwin; j += LANES) {
@@ -371,19 +385,20 @@ __device__ __forceinline__ void window_loop(T* __restrict__ I, int lane, int clo
 // all register components with zero-strength padding.
 template <int LANES, typename T, bool HF = false>
 __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
-                                                T kl, T el, T& sj, T& sl, const HfRegs<T>* hf = nullptr)
+                                                T kl, T el, T& sj, T& sl, const HfRegs<T>* hf,
+                                                unsigned* __restrict__ maser)
 {
     if constexpr (!HF) {
-        window_loop<LANES, T, 0>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+        window_loop<LANES, T, 0>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
     } else {
         constexpr int R = HfRegs<T>::kReg;
         const int n = hf->n;
-        if (n == 1) window_loop<LANES, T, 1>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
-        else if (n == 2) window_loop<LANES, T, 2>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
-        else if (n == 3) window_loop<LANES, T, 3>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
-        else if (n == 4) window_loop<LANES, T, 4>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
-        else if (n <= 8 || R == 8) window_loop<LANES, T, 8>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
-        else window_loop<LANES, T, R>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf);
+        if (n == 1) window_loop<LANES, T, 1>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
+        else if (n == 2) window_loop<LANES, T, 2>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
+        else if (n == 3) window_loop<LANES, T, 3>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
+        else if (n == 4) window_loop<LANES, T, 4>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
+        else if (n <= 8 || R == 8) window_loop<LANES, T, 8>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
+        else window_loop<LANES, T, R>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
     }
 }
 
@@ -488,7 +503,7 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         const T kl = kv.x * rec.len;      // tau at the line centre
         const T el = kv.y * rec.len;
         T sj = 0, sl = 0;
-        window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr);
+        window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr, p.maser);
         if (ACCUM) {
             // every lane forms the weighted sums (the wavefront issues them
             // either way); only the group's last lane, which holds the
@@ -857,7 +872,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
-            window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr);
+            window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr, p.maser);
             if (ACCUM) {
                 const T wgt = aw * len;
                 T2q v;
@@ -891,7 +906,6 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
 // ---------------------------------------------------------------- 1D march
 namespace {
 
-__device__ __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
 
 }  // namespace
@@ -904,9 +918,10 @@ __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); 
 // time, one per lane (loading the next chunk a chunk ahead measured 11%
 // slower in the request loop), and the next step's shell data are loaded
 // before the current step runs.  With p.lds_acc the per-step sums go to
-// per-shell LDS accumulators (LDS atomics do not stall the next step's
-// loads), flushed to the FP64 global sums once per workgroup; otherwise each
-// step issues two FP64 atomics.
+// per-shell FP64 LDS accumulators (LDS atomics do not stall the next step's
+// loads; in FP64 the sum of a shell's visits by the workgroup's rays does not
+// depend on their order beyond FP64 rounding), flushed to the FP64 global
+// sums once per workgroup; otherwise each step issues two FP64 atomics.
 template <typename T, int LANES, bool ACCUM, bool TRANS_GROUPS = false, bool HF = false>
 __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0, int t_in, unsigned char* smem_raw)
 {
@@ -919,14 +934,14 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
     const int t = TRANS_GROUPS ? (t_in + rib < p.ntr_total ? t_in + rib : t_in) : t_in;
     const int n = p.n;
     const bool lds_acc = ACCUM && p.lds_acc;
-    T* __restrict__ sacc = reinterpret_cast<T*>(smem_raw);                 // [n][2] when lds_acc
+    double* __restrict__ sacc = reinterpret_cast<double*>(smem_raw);       // [n][2] when lds_acc
     T* __restrict__ I = reinterpret_cast<T*>(smem_raw + (lds_acc ? p.acc_lds_bytes : 0)) + (size_t)rib * p.nch;
     const int ts = p.ntr_total;      // cell-major [shell][transition]
     const int kmin0 = p.kmin[ray0];  // the block's rays are sorted by impact parameter
     if (lds_acc) {
         for (int k = kmin0 + (int)threadIdx.x; k < n; k += blockDim.x) {
-            sacc[2 * k] = (T)0;
-            sacc[2 * k + 1] = (T)0;
+            sacc[2 * k] = 0.0;
+            sacc[2 * k + 1] = 0.0;
         }
         __syncthreads();
     }
@@ -973,7 +988,7 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
             const T tl = r.x;
             T sj = 0, sl = 0;
             window_channels<LANES, T, HF>(I, lane, clo, chi - clo + 1, frac * sv.y, sv.y, kev.x * tl, kev.y * tl,
-                                          sj, sl, &hfr);
+                                          sj, sl, &hfr, p.maser);
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
@@ -982,8 +997,8 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
                 if (lane == LANES - 1) {
                     const double wgt = a * (double)tl;
                     if (lds_acc) {
-                        lds_add(&sacc[2 * k], (T)wgt * sj);
-                        lds_add(&sacc[2 * k + 1], (T)wgt * sl);
+                        lds_add(&sacc[2 * k], wgt * (double)sj);
+                        lds_add(&sacc[2 * k + 1], wgt * (double)sl);
                     } else {
                         unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, wgt * (double)sj);
                         unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, wgt * (double)sl);
@@ -1000,10 +1015,10 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
     if (lds_acc) {
         __syncthreads();
         for (int k = kmin0 + (int)threadIdx.x; k < n; k += blockDim.x) {
-            const T vj = sacc[2 * k], vl = sacc[2 * k + 1];
-            if (vj != (T)0 || vl != (T)0) {
-                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, (double)vj);
-                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, (double)vl);
+            const double vj = sacc[2 * k], vl = sacc[2 * k + 1];
+            if (vj != 0.0 || vl != 0.0) {
+                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, vj);
+                unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, vl);
             }
         }
     }
@@ -1540,7 +1555,7 @@ hipError_t do_march1d(hipStream_t s, March1DArgs<T> a)
 {
     const int rpb = rays_per_block<T>(LANES, a.nch);
     const dim3 grid((a.nrays + rpb - 1) / rpb, a.ntr);
-    a.acc_lds_bytes = (int)((((size_t)a.n * 2 * sizeof(T)) + 15) & ~(size_t)15);
+    a.acc_lds_bytes = (int)((((size_t)a.n * 2 * sizeof(double)) + 15) & ~(size_t)15);
     a.lds_acc = ACCUM && ((size_t)a.acc_lds_bytes + (size_t)rpb * a.nch * sizeof(T) <= 65536) ? 1 : 0;
     const size_t shm = (a.lds_acc ? (size_t)a.acc_lds_bytes : 0) + (size_t)rpb * a.nch * sizeof(T);
     hipLaunchKernelGGL((march1d_kernel<T, LANES, ACCUM, HF>), grid, dim3(rpb * LANES), shm, s, a);

@@ -22,6 +22,12 @@ namespace miloc {
 constexpr int kMaxLevels = 32;
 constexpr int kMaxTrans = kMaxLevels * (kMaxLevels - 1) / 2;
 
+// Negative line-centre optical depth of one step (population inversion, a
+// maser) below which a march raises its maser flag instead of marching on
+// quietly: exp(40) = 2.4e17 of gain in a single step, and the FP32 exponential
+// overflows near -88.
+constexpr double kMaserTauMin = -40.0;
+
 // Molecule constants on the device (read through uniform loads).
 struct MolDev {
     int L, T;
@@ -89,6 +95,7 @@ struct March3DArgs {
     int ntr_total;                       // transitions in ke / acc (cell-major stride)
     const typename V2<T>::type* hf;      // hyperfine components [ntr_total][hfk] {offset / dv, strength}, or null
     int hfk;                             // components per transition (zero-strength padding)
+    unsigned* maser;                     // set to 1 by a step with line-centre tau < kMaserTauMin
 };
 
 // Per-cell gather of the per-step partial sums written by march3d, for the
@@ -127,6 +134,7 @@ struct March1DArgs {
     const typename V2<T>::type* hf;      // hyperfine components as in March3DArgs, or null
     int hfk;
     double hf_lo, hf_hi;                 // lowest / highest component offset (channels; <= 0, >= 0)
+    unsigned* maser;                     // as in March3DArgs
 };
 
 struct SEArgs {
@@ -230,6 +238,7 @@ struct OctMarchArgs {
     int depth;
     const typename V2<T>::type* hf;      // hyperfine components as in March3DArgs, or null
     int hfk;
+    unsigned* maser;                     // as in March3DArgs
 };
 
 // Stride (elements) of an octree march channel vector, in LDS and in the

@@ -238,6 +238,13 @@ miloc_status ensure_base(miloc_ctx* c)
     return MILOC_OK;
 }
 
+// The marches' maser flag: the fourth 32-bit word of d_flags (after the
+// convergence maximum and the failure counter of the equilibrium solve).
+unsigned* maser_flag(miloc_ctx* c)
+{
+    return reinterpret_cast<unsigned*>(c->d_flags.as<char>() + 12);
+}
+
 template <typename TT>
 void pack_cell_static(miloc_ctx* c, const std::vector<double>& b, std::vector<char>& out)
 {
@@ -459,6 +466,7 @@ miloc_status launch_oct(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, c
     a.depth = accum ? c->oct_depth : 0;
     a.hf = c->hfk ? c->d_hf.as<typename V2<TT>::type>() : nullptr;
     a.hfk = c->hfk;
+    a.maser = maser_flag(c);
     HIPCHK(c, launch_march_oct(c->stream, a, groups, accum, c->lanes));
     return MILOC_OK;
 }
@@ -749,6 +757,7 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.e_tstride = (size_t)c->total_steps * c->N * c->N;
         a.hf = c->hfk ? c->d_hf.as<typename V2<TT>::type>() : nullptr;
         a.hfk = c->hfk;
+        a.maser = maser_flag(c);
         int max_steps = 0;
         if (zdir) {
             max_steps = c->N;
@@ -780,6 +789,7 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         a.hfk = c->hfk;
         a.hf_lo = c->hf_lo;
         a.hf_hi = c->hf_hi;
+        a.maser = maser_flag(c);
         // lines of sight run alone: 64 lanes shorten each step's channel loop
         e = launch_march1d(c->stream, a, accum ? c->lanes : 64, accum);
     }
@@ -1199,6 +1209,8 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
     int it = 0;
     bool converged = false;
     for (; it < max_iter; ++it) {
+        // convergence maximum, failure counter and maser flag of this iteration
+        HIPCHK(c, hipMemsetAsync(c->d_flags.p, 0, 16, c->stream));
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
         HIPCHK(c, launch_prepare(c->stream, (int)nc, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
                                  c->d_nmolLb.as<double>(), nullptr, c->d_ke.p, fp64));
@@ -1265,7 +1277,6 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
             c->ctr.march_launches += 1;
         }
         HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
-        HIPCHK(c, hipMemsetAsync(c->d_flags.p, 0, 16, c->stream));
         SEArgs a{};
         a.nc = (int)nc;
         a.L = c->L;
@@ -1297,6 +1308,11 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
         c->ctr.iterations += 1;
         c->has_rad = true;
         const unsigned int bad = (unsigned int)(flags[1] & 0xffffffffu);
+        if (flags[1] >> 32) {
+            if (iters_done) *iters_done = it;
+            return fail(c, MILOC_ENUMERIC, "maser: a step's line-centre optical depth fell below -40 "
+                                           "(populations left as before the iteration)");
+        }
         if (bad) {
             if (iters_done) *iters_done = it;
             return fail(c, MILOC_ENUMERIC, "non-finite or negative populations from the equilibrium solve");
@@ -1378,6 +1394,7 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
     DevBuf out, extra, extra2;
     // march I - I_bg from zero (see prepare_kernel)
+    HIPCHK(c, hipMemsetAsync(maser_flag(c), 0, sizeof(unsigned), c->stream));
     HIPCHK(c, launch_prepare(c->stream, (int)c->nc, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
                              c->d_nmolLb.as<double>(), c->d_Ibg64.as<double>(), c->d_ke.p, fp64));
     if (c->kind == 4) {
@@ -1487,8 +1504,12 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
     const size_t n = (size_t)n_los * c->nch;
     std::vector<char> h(n * tsz);
     const DevBuf& res = c->kind == 1 ? c->d_los_out : out;
+    unsigned maser = 0;
     HIPCHK(c, hipMemcpyAsync(h.data(), res.p, n * tsz, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&maser, maser_flag(c), sizeof maser, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (maser)
+        return fail(c, MILOC_ENUMERIC, "maser: a step's line-centre optical depth fell below -40");
     const double sc = c->Iscale[trans];
     for (size_t i = 0; i < n; ++i) {
         const double v = fp64 ? reinterpret_cast<double*>(h.data())[i] : (double)reinterpret_cast<float*>(h.data())[i];

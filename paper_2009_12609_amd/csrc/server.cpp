@@ -52,16 +52,16 @@ constexpr size_t kStageBytes = (size_t)64 << 20;   // pinned admission staging p
 constexpr size_t kResBytes = (size_t)64 << 20;     // pinned result area per tick
 constexpr size_t kNoRes = ~(size_t)0;
 // LDS tiers of the tick's march kernel (one captured graph each): the largest
-// holds the per-shell accumulators of 2048 shells and 16 rays of 512
-// channels; the smaller ones let more workgroups share a CU (160 KB of LDS)
-// when the resident models are smaller.
-constexpr int kLdsTiers = 5;
-constexpr int kTierLds[kLdsTiers] = {20480, 27136, 32768, 40960, 49152};
+// holds the FP64 per-shell accumulators of 2048 shells and 16 rays of 512
+// channels; the smaller ones let more workgroups share a CU (160 KB of LDS:
+// 8, 6, 5, 4, 3 and 2 workgroups) when the resident models are smaller.
+constexpr int kLdsTiers = 6;
+constexpr int kTierLds[kLdsTiers] = {20480, 27136, 32768, 40960, 53248, 65536};
 
 // LDS bytes the tick's march kernel needs for one resident model.
 constexpr int march_lds_need(int n, int nch)
 {
-    return (int)((((size_t)n * 2 * sizeof(float)) + 15) & ~(size_t)15) + kRaysPerBlock * nch * (int)sizeof(float);
+    return (int)((((size_t)n * 2 * sizeof(double)) + 15) & ~(size_t)15) + kRaysPerBlock * nch * (int)sizeof(float);
 }
 static_assert(march_lds_need(kMaxServeShells, kMaxServeChannels) <= kTierLds[kLdsTiers - 1],
               "the largest LDS tier must hold the largest served model");
@@ -386,7 +386,7 @@ bool admit_device(miloc_server* S, Request* r, const char* img)
     a.trans_offset = 0;
     a.ntr_total = r->T;
     a.lds_acc = 1;
-    a.acc_lds_bytes = (int)((((size_t)n * 2 * sizeof(float)) + 15) & ~(size_t)15);
+    a.acc_lds_bytes = (int)((((size_t)n * 2 * sizeof(double)) + 15) & ~(size_t)15);
     a.hf = nullptr;                      // requests carry single-Gaussian lines
     a.hfk = 0;
     a.hf_lo = a.hf_hi = 0.0;
@@ -401,6 +401,9 @@ bool admit_device(miloc_server* S, Request* r, const char* img)
     d.q = static_cast<const double*>(dptr(lay.q));
     d.delta_bits = S->d_flags + 2 * r->slot;
     d.bad = reinterpret_cast<unsigned int*>(S->d_flags + 2 * r->slot + 1);
+    // a maser step fails the request like a failed solve (the tick's
+    // prepare kernel clears the word before the march)
+    a.maser = d.bad;
     d.nc = n;
     d.L = r->L;
     d.T = r->T;

@@ -139,3 +139,43 @@ def test_cancel_while_resident():
     st = srv.stats()
     assert st["cancelled"] == 1 and st["completed"] == 1 and st["arena_used"] == 0
     srv.close()
+
+
+def _request(shells, levels, nch, seed):
+    r = synth.serving_stream(1, seed=seed, shells=(shells, shells), levels=(levels,))[0]
+    r.spec = synth.Spectral.symmetric(nch, 2.0)
+    return r
+
+
+def test_large_models_alone_mix_and_oracle():
+    """Models that need the larger LDS tiers of the tick's march kernel (FP64
+    per-shell accumulators of up to 2048 shells beside sixteen channel vectors
+    of up to 512 channels): 1000 shells x 256 channels, 1600 x 256 and
+    1300 x 512 (the three largest of the six tiers), served together with two
+    small models; each result equals the model solved alone, and two equal
+    the oracle's run to the same tolerance."""
+    big = [_request(1000, 10, 256, 31), _request(1600, 5, 256, 32), _request(1300, 2, 512, 33)]
+    reqs = big + small_stream(2, seed=34)
+    srv = miloc.Server(hbm_budget_bytes=2 << 30, max_slots=8)
+    tickets = [srv.submit(r.mol, r.model, r.spec, r.T_bg, tol=1e-6, max_iter=200) for r in reqs]
+    for t in tickets:
+        assert srv.wait(t, 300.0)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["peak_active"] >= 3
+    for i, (r, t) in enumerate(zip(reqs, tickets)):
+        x, sp, info, rc = srv.take(t)
+        assert rc == miloc.OK and info["status"] == miloc.OK, info
+        xa, spa = alone(r, info["iterations"])
+        e = rel(x, xa)
+        print(f"[serve] large req {i}: L={r.mol.n_levels} nch={r.spec.n_channels} shells={r.model.n_shells} "
+              f"iters={info['iterations']} mix-vs-alone {e:.2e}", flush=True)
+        assert e < 1e-5, e
+        scale = np.max(np.abs(spa), axis=1, keepdims=True)
+        assert np.all(np.abs(sp - spa) <= 1e-5 * scale + 1e-40)
+        if i in (0, 2):
+            ref = oracle.run_1d(r.mol, r.model, r.spec, r.T_bg, 200, tol=1e-6, record=False)
+            eo = rel(x, ref.x)
+            print(f"[serve] large req {i}: vs oracle {eo:.2e} (oracle {ref.iters} iterations)", flush=True)
+            assert abs(ref.iters - info["iterations"]) <= 1
+            assert eo < 1e-5
+    srv.close()
