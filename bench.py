@@ -17,9 +17,10 @@ timed on this host's cores on a bounded sample of the same workload.  Three
 more objects by default: ``hyperfine`` (the same cube with a three-component
 multiplet on every transition, 2 timed iterations), ``octree`` (64^3 root
 refined four levels, 2 timed ALI iterations, same per-step measures) and
-``serving`` (a 512-request 1D stream: model solves/s with all requests queued
+``serving`` (a 5000-request 1D stream: model solves/s with all requests queued
 at once, p50/p99 latency under Poisson arrivals at 0.5x and 0.8x of that rate,
-and the same requests solved one at a time through a single-model context).
+and the first 1024 of the same requests solved one at a time through a
+single-model context).
 """
 import argparse
 import hashlib
@@ -33,6 +34,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+# The same vector units without packed FP32 (two FP32 lanes per instruction),
+# which this build's kernels do not use: 256 CUs x 4 SIMDs x 16 lanes x 2
+# (FMA) x 2.4 GHz.
+FP32_UNPACKED_TFLOPS = 78.6
+# The paper's GPU-vs-one-CPU-core speed-ups, with the hardware it states.
+PAPER_SPEEDUPS = {
+    "1d": "about 20x (abstract) to 23x (App. A.1, 2048 rays, 256 channels): NVIDIA GTX 1080 Ti "
+          "against one core of an Intel i7-8700K",
+    "3d_cartesian": "about 12.9x (App. A.2): AMD Radeon VII (external, Thunderbolt) against one "
+                    "i7-8700K core; 6.0x for the 6-core CPU run",
+    "3d_octree": "up to about 10x (abstract), hardware as above",
+}
 # Algorithmic bytes per ray-cell step of one transition: read the cell's
 # {kappa, eta} (8 B) and {u/dv, dv/b} (16 B), read-modify-write the FP64
 # {J, Lambda} accumulator pair (16 B, counted once).
@@ -79,9 +92,11 @@ def measured_counters(src_hash, path=TRAFFIC_FILE):
     return d.get("bytes_per_launch"), d.get("valu_busy")
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """Oracle (FP64, all channels) on the same cube, one transition (J=1-0),
-    directions added one at a time until ~budget_s of wall time."""
+def cpu_baseline(w, budget_s=8.0, gpu_value=None):
+    """Oracle (FP64, all channels) on the same cube, one transition (J=1-0):
+    on all host threads, directions added one at a time until ~budget_s of
+    wall time; on one thread, one direction (the paper's speed-ups are against
+    one CPU core)."""
     import numpy as np
 
     import oracle
@@ -92,26 +107,46 @@ def cpu_baseline(w, budget_s=15.0):
     kap, eta = oracle.prepare(w.mol, x0, prob.n_mol)
     vx, vy, vz = (np.asarray(a, dtype=np.float64) for a in (m.vx, m.vy, m.vz))
     dirs = oracle.healpix_nside2()
-    t_total = 0.0
-    updates = 0.0
-    used = 0
-    for q in range(dirs.shape[0]):
-        cells, _, _ = oracle.walk_3d(N, dirs[q], 0, 0)
-        t0 = time.perf_counter()
-        oracle.march_3d(N, m.root_cell_cm, vx, vy, vz, prob.bD, kap[0], eta[0], dirs[q:q + 1],
-                        w.spec, prob.I_bg[0])
-        t_total += time.perf_counter() - t0
-        updates += float(len(cells)) * N * N * w.spec.n_channels
-        used += 1
-        if t_total >= budget_s:
-            break
-    return {"value": updates / t_total, "unit": "ray-cell-channel updates/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle march of transition J=1-0 along {used} of 48 directions of the "
-                      f"full {N}^3 cube, all {w.spec.n_channels} channels ({t_total:.1f} s)"}
+
+    def run(threads, max_dirs, budget):
+        t_total, updates, used = 0.0, 0.0, 0
+        for q in range(min(max_dirs, dirs.shape[0])):
+            cells, _, _ = oracle.walk_3d(N, dirs[q], 0, 0)
+            t0 = time.perf_counter()
+            oracle.march_3d(N, m.root_cell_cm, vx, vy, vz, prob.bD, kap[0], eta[0], dirs[q:q + 1],
+                            w.spec, prob.I_bg[0], n_threads=threads)
+            t_total += time.perf_counter() - t0
+            updates += float(len(cells)) * N * N * w.spec.n_channels
+            used += 1
+            if t_total >= budget:
+                break
+        return updates / t_total, used, t_total
+
+    v_all, used_all, t_all = run(0, 48, budget_s)
+    v_one, used_one, t_one = run(1, 1, 0.0)
+    out = {"value": v_all, "unit": "ray-cell-channel updates/s",
+           "cores": oracle.max_threads(), "kind": "oracle",
+           "sample": f"FP64 oracle march of transition J=1-0 along {used_all} of 48 directions of the "
+                     f"full {N}^3 cube, all {w.spec.n_channels} channels ({t_all:.1f} s)",
+           "one_thread": {"value": v_one, "cores": 1,
+                          "sample": f"as above on one thread, {used_one} direction ({t_one:.1f} s)"},
+           "paper_gpu_vs_one_core": PAPER_SPEEDUPS}
+    if gpu_value:
+        out["gpu_vs_one_thread"] = gpu_value / v_one
+        out["gpu_vs_all_threads"] = gpu_value / v_all
+    return out
 
 
 OCT_BYTES_PER_STEP = 48.0     # the regular step's 40 B plus the 8 B step record
+
+
+def alu_view(tflops, valu_busy, nwin, flops_per_channel=FLOPS_PER_CHANNEL):
+    """The same launch as useful FP32 vector work against the packed and the
+    unpacked FP32 peaks, with the measured VALU-busy fraction."""
+    return {"achieved": tflops, "unit": "TFLOP/s", "peak_unpacked": FP32_UNPACKED_TFLOPS,
+            "frac_unpacked": tflops / FP32_UNPACKED_TFLOPS, "peak_packed": FP32_PEAK_TFLOPS,
+            "frac_packed": tflops / FP32_PEAK_TFLOPS, "valu_busy": valu_busy,
+            "flops_per_channel_update": flops_per_channel, "window_channels_mean": nwin}
 
 
 def octree_bench(steps=2, warmup=1):
@@ -146,7 +181,7 @@ def octree_bench(steps=2, warmup=1):
     hbm_gbs = steps_per_launch * OCT_BYTES_PER_STEP / (march_ms * 1e-3) / 1e9
     nwin = mean_window_channels(w)
     traffic, valu_busy = measured_counters(kernel_source_hash(), OCT_TRAFFIC_FILE)
-    achieved = steps_per_launch * nwin * FLOPS_PER_CHANNEL / (march_ms * 1e-3) / 1e12
+    alu_tflops = steps_per_launch * nwin * FLOPS_PER_CHANNEL / (march_ms * 1e-3) / 1e12
     return {
         "metric": "ray-cell-channel updates/s (3D octree)",
         "value": cnt["channel_updates"] / elapsed,
@@ -160,13 +195,11 @@ def octree_bench(steps=2, warmup=1):
         "solve_ms_per_step": cnt["solve_ms"] / max(1, cnt["iterations"]),
         "setup_s": t_setup,
         "generate_s": t_gen,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": traffic, "valu_busy": valu_busy,
+        "roofline": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"march_oct_kernel<float,{cnt['march_lanes']},true,false>",
-                     "flops_per_channel_update": FLOPS_PER_CHANNEL, "window_channels_mean": nwin,
-                     "hbm_algorithmic_gbs": hbm_gbs, "hbm_algorithmic_frac": hbm_gbs / HBM_PEAK_GBS,
-                     "bytes_per_step": OCT_BYTES_PER_STEP},
+                     "bytes_per_step": OCT_BYTES_PER_STEP, "steps_per_launch": steps_per_launch,
+                     "alu_view": alu_view(alu_tflops, valu_busy, nwin)},
     }
 
 
@@ -213,7 +246,8 @@ def hyperfine_bench(w, steps=2, warmup=1):
     k = len(HF_OFFSETS_KMS)
     nwin = mean_window_channels(w) + (max(HF_OFFSETS_KMS) - min(HF_OFFSETS_KMS)) * 1e5 / w.spec.dv
     fpc = hf_flops_per_channel(k)
-    achieved = steps_per_launch * nwin * fpc / (march_ms * 1e-3) / 1e12
+    alu_tflops = steps_per_launch * nwin * fpc / (march_ms * 1e-3) / 1e12
+    hbm_gbs = steps_per_launch * BYTES_PER_STEP / (march_ms * 1e-3) / 1e9
     return {
         "metric": "ray-cell-channel updates/s (3D, hyperfine multiplets)",
         "value": cnt["channel_updates"] / elapsed,
@@ -225,10 +259,11 @@ def hyperfine_bench(w, steps=2, warmup=1):
         "strengths": list(HF_STRENGTHS),
         "march_ms_per_launch": march_ms,
         "solve_ms_per_step": cnt["solve_ms"] / max(1, cnt["iterations"]),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+        "roofline": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None,
                      "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true,true>",
-                     "flops_per_channel_update": fpc, "window_channels_mean": nwin},
+                     "bytes_per_step": BYTES_PER_STEP, "steps_per_launch": steps_per_launch,
+                     "alu_view": alu_view(alu_tflops, None, nwin, fpc)},
     }
 
 
@@ -271,12 +306,12 @@ def _pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
-def serve_bench(n_req=512, seed=5001, tol=1e-6, max_iter=500):
+def serve_bench(n_req=5000, seed=5001, tol=1e-6, max_iter=500, alone_sample=1024):
     """1D request stream (50-2000 shells, 2/5/10/20 levels, 64/128/256
     channels): model solves/s with every request queued at once (arrival rate
     far above capacity), p50/p99 latency at 0.5x and 0.8x of that capacity
-    with Poisson arrivals, and the same requests solved one at a time through a
-    single-model context."""
+    with Poisson arrivals, and the first `alone_sample` requests of the same
+    stream solved one at a time through a single-model context."""
     import numpy as np
 
     import paper_2009_12609_amd as miloc
@@ -334,7 +369,8 @@ def serve_bench(n_req=512, seed=5001, tol=1e-6, max_iter=500):
     ctx.run(max_iter, tol=tol)
     t0 = time.perf_counter()
     lat1 = []
-    for r in reqs:
+    n_alone = min(n_req, alone_sample)
+    for r in reqs[:n_alone]:
         ts = time.perf_counter()
         ctx.load_molecule(r.mol)
         ctx.load_model_1d(r.model)
@@ -359,8 +395,9 @@ def serve_bench(n_req=512, seed=5001, tol=1e-6, max_iter=500):
         "saturation_tick_s": busy_sat,
         "peak_resident": int(st["peak_active"]),
         "latency": lat_runs,
-        "one_at_a_time": {"value": n_req / el1, "p50_service_s": _pct(lat1, 50)},
-        "speedup": cap / (n_req / el1),
+        "one_at_a_time": {"value": n_alone / el1, "p50_service_s": _pct(lat1, 50),
+                          "requests": n_alone, "sample": f"the first {n_alone} requests of the stream"},
+        "speedup": cap / (n_alone / el1),
         "stream": f"seed {seed}: shells U[50,2000], levels {{2,5,10,20}}, channels {{64,128,256}}, +-2 km/s",
     }
 
@@ -372,7 +409,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128, help="grid size (128 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", type=int, default=512, metavar="N_REQ",
+    ap.add_argument("--serve", type=int, default=5000, metavar="N_REQ",
                     help="run the 1D request stream with N_REQ requests ('serving' object; 0 = skip)")
     ap.add_argument("--octree", type=int, default=2, metavar="STEPS",
                     help="time STEPS iterations of the octree workload ('octree' object; 0 = skip)")
@@ -432,7 +469,7 @@ def main():
     hbm_gbs = bytes_per_launch / (march_ms * 1e-3) / 1e9
     nwin = mean_window_channels(w)
     flops_per_launch = steps_per_launch * nwin * FLOPS_PER_CHANNEL
-    achieved = flops_per_launch / (march_ms * 1e-3) / 1e12
+    alu_tflops = flops_per_launch / (march_ms * 1e-3) / 1e12
     src_hash = kernel_source_hash()
     traffic, valu_busy = measured_counters(src_hash)
 
@@ -464,19 +501,17 @@ def main():
             "march_updates_per_s": updates / (cnt["march_ms"] * 1e-3),
         },
         "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP32_PEAK_TFLOPS,
+            "bound": "hbm",
+            "achieved": hbm_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": hbm_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
-            "valu_busy": valu_busy,
             "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true,false>",
-            "flops_per_channel_update": FLOPS_PER_CHANNEL,
-            "window_channels_mean": nwin,
-            "hbm_algorithmic_gbs": hbm_gbs,
-            "hbm_algorithmic_frac": hbm_gbs / HBM_PEAK_GBS,
             "bytes_per_step": BYTES_PER_STEP,
+            "steps_per_launch": steps_per_launch,
+            "march_ms_per_launch": march_ms,
+            "alu_view": alu_view(alu_tflops, valu_busy, nwin),
             "kernel_source_hash": src_hash,
         },
     }
@@ -490,7 +525,7 @@ def main():
     if args.serve > 0:
         out["serving"] = serve_bench(args.serve)
     if not args.no_cpu_baseline and N == 128:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, gpu_value=out["config"]["march_updates_per_s"])
     print(json.dumps(out), flush=True)
 
 

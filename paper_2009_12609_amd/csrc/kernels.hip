@@ -380,6 +380,86 @@ __device__ __forceinline__ void window_loop(T* __restrict__ I, int lane, int clo
     }
 }
 
+// One channel's radiative update (Sect. 2, Eq. (3) in intensity form) from
+// its profile value ec and 1 - beta: the two partial sums of the step and
+// I <- I + ec beta (el - kl I), i.e. I e^-tau + S (1 - e^-tau).
+__device__ __forceinline__ void channel_update(float* __restrict__ p, float ec, float omb, float kl, float el,
+                                               float& sj, float& sl)
+{
+    const float Iin = *p;
+    const float u = fmaf(-ec, omb, ec);            // ec beta
+    sj = fmaf(Iin, u, sj);
+    sl = fmaf(ec, omb, sl);
+    *p = fmaf(u, fmaf(-kl, Iin, el), Iin);
+}
+
+// 1 - beta for the optical-depth class of a step: CLS 0 when every |tau| is
+// below 1e-3 (two series terms, relative truncation error < tau^2/12 < 1e-7),
+// CLS 1 below 1e-2 (three terms), CLS 2 any tau.
+template <int CLS>
+__device__ __forceinline__ float omb_class(float tau)
+{
+    if constexpr (CLS == 0) return tau * fmaf(tau, -1.0f / 6.0f, 0.5f);
+    else if constexpr (CLS == 1) return omb_thin(tau);
+    else return omb_any(tau);
+}
+
+// The lane group's passes over the window of one step, FP32 single Gaussian:
+// the first NU passes unrolled (channel lane + i LANES, constant LDS offsets
+// from rl = I + clo + lane, profile argument xl + i hstep), any further ones
+// in a loop.  The NU intensities are read before any is used, whether their
+// channel is in the window or not (one wait for all of them; a value outside
+// the window is never used): every march keeps at least kVecTailPadWords
+// words of its LDS allocation after each channel vector.
+template <int LANES, int CLS>
+__device__ __forceinline__ void window_passes_f32(float* __restrict__ rl, int lane, int nwin, float xl, float hstep,
+                                                  float x0, float ibs, float kl, float el, float& sj, float& sl)
+{
+    constexpr int NU = LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4);
+    static_assert(NU * LANES <= kVecTailPadWords, "unconditional reads must stay in the LDS allocation");
+    float Iv[NU];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) Iv[i] = rl[i * LANES];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        if (lane + i * LANES < nwin) {
+            const float xs = fmaf((float)i, hstep, xl);
+            const float ec = fast_exp2(-xs * xs);
+            const float omb = omb_class<CLS>(kl * ec);
+            const float u = fmaf(-ec, omb, ec);
+            sj = fmaf(Iv[i], u, sj);
+            sl = fmaf(ec, omb, sl);
+            rl[i * LANES] = fmaf(u, fmaf(-kl, Iv[i], el), Iv[i]);
+        }
+    }
+    for (int j = lane + NU * LANES; j < nwin; j += LANES) {
+        const float xs = fmaf((float)j, ibs, x0);
+        const float ec = fast_exp2(-xs * xs);
+        channel_update(rl + (j - lane), ec, omb_class<CLS>(kl * ec), kl, el, sj, sl);
+    }
+}
+
+// FP32 single-Gaussian form of window_loop: the optical-depth class is voted
+// once per step for the wavefront (no per-channel branch), the maser check
+// as in window_loop.
+template <int LANES>
+__device__ __forceinline__ void window_f32(float* __restrict__ I, int lane, int clo, int nwin, float x0, float ibs,
+                                           float kl, float el, float& sj, float& sl, unsigned* __restrict__ maser)
+{
+    float* __restrict__ rl = I + clo + lane;
+    const float xl = fmaf((float)lane, ibs, x0);
+    const float hstep = (float)LANES * ibs;
+    const float akl = fabsf(kl);
+    if (__all(akl < 1e-3f)) {
+        window_passes_f32<LANES, 0>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
+    } else if (__all(akl < 1e-2f)) {
+        window_passes_f32<LANES, 1>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
+    } else {
+        if (kl < (float)kMaserTauMin) *maser = 1u;
+        window_passes_f32<LANES, 2>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
+    }
+}
+
 // With HF the component count picks, once per step (it is uniform), a loop
 // whose profile sum is unrolled over exactly 1..4 components, or over 8 or
 // all register components with zero-strength padding.
@@ -389,7 +469,10 @@ __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int
                                                 unsigned* __restrict__ maser)
 {
     if constexpr (!HF) {
-        window_loop<LANES, T, 0>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
+        if constexpr (std::is_same<T, float>::value)
+            window_f32<LANES>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, maser);
+        else
+            window_loop<LANES, T, 0>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
     } else {
         constexpr int R = HfRegs<T>::kReg;
         const int n = hf->n;
@@ -1521,7 +1604,7 @@ template <typename T>
 int rays_per_block(int lanes, int nch)
 {
     int rpb = 256 / lanes;
-    while (rpb > 1 && (size_t)rpb * nch * sizeof(T) > 65536) rpb >>= 1;
+    while (rpb > 1 && (size_t)rpb * nch * sizeof(T) + kVecTailPadWords * sizeof(float) > 65536) rpb >>= 1;
     return rpb;
 }
 
@@ -1556,8 +1639,9 @@ hipError_t do_march1d(hipStream_t s, March1DArgs<T> a)
     const int rpb = rays_per_block<T>(LANES, a.nch);
     const dim3 grid((a.nrays + rpb - 1) / rpb, a.ntr);
     a.acc_lds_bytes = (int)((((size_t)a.n * 2 * sizeof(double)) + 15) & ~(size_t)15);
-    a.lds_acc = ACCUM && ((size_t)a.acc_lds_bytes + (size_t)rpb * a.nch * sizeof(T) <= 65536) ? 1 : 0;
-    const size_t shm = (a.lds_acc ? (size_t)a.acc_lds_bytes : 0) + (size_t)rpb * a.nch * sizeof(T);
+    const size_t vec_bytes = (size_t)rpb * a.nch * sizeof(T) + kVecTailPadWords * sizeof(float);
+    a.lds_acc = ACCUM && ((size_t)a.acc_lds_bytes + vec_bytes <= 65536) ? 1 : 0;
+    const size_t shm = (a.lds_acc ? (size_t)a.acc_lds_bytes : 0) + vec_bytes;
     hipLaunchKernelGGL((march1d_kernel<T, LANES, ACCUM, HF>), grid, dim3(rpb * LANES), shm, s, a);
     return hipGetLastError();
 }

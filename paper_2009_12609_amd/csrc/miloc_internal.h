@@ -28,6 +28,12 @@ constexpr int kMaxTrans = kMaxLevels * (kMaxLevels - 1) / 2;
 // overflows near -88.
 constexpr double kMaserTauMin = -40.0;
 
+// Words of a march workgroup's LDS allocation that lie after each channel
+// vector (the next vector, the queues or padding): the FP32 channel passes
+// read up to this many words past the start of a step's window
+// unconditionally and use only the values inside it.
+constexpr int kVecTailPadWords = 64;
+
 // Molecule constants on the device (read through uniform loads).
 struct MolDev {
     int L, T;

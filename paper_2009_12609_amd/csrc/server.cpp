@@ -56,12 +56,13 @@ constexpr size_t kNoRes = ~(size_t)0;
 // channels; the smaller ones let more workgroups share a CU (160 KB of LDS:
 // 8, 6, 5, 4, 3 and 2 workgroups) when the resident models are smaller.
 constexpr int kLdsTiers = 6;
-constexpr int kTierLds[kLdsTiers] = {20480, 27136, 32768, 40960, 53248, 65536};
+constexpr int kTierLds[kLdsTiers] = {20480, 27136, 32768, 40960, 53248, 65792};
 
 // LDS bytes the tick's march kernel needs for one resident model.
 constexpr int march_lds_need(int n, int nch)
 {
-    return (int)((((size_t)n * 2 * sizeof(double)) + 15) & ~(size_t)15) + kRaysPerBlock * nch * (int)sizeof(float);
+    return (int)((((size_t)n * 2 * sizeof(double)) + 15) & ~(size_t)15) + kRaysPerBlock * nch * (int)sizeof(float) +
+           kVecTailPadWords * (int)sizeof(float);
 }
 static_assert(march_lds_need(kMaxServeShells, kMaxServeChannels) <= kTierLds[kLdsTiers - 1],
               "the largest LDS tier must hold the largest served model");
