@@ -73,6 +73,12 @@ def lib():
                                   ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp, dp,
                                   ctypes.c_int, dp, dp]
+        L.orc1d_core_entry.restype = None
+        L.orc1d_core_entry.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int, dp, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc1d_march_core.restype = None
+        L.orc1d_march_core.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int, dp, dp, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.orc3d_main_axis.restype = ctypes.c_int
         L.orc3d_main_axis.argtypes = [dp]
         L.orc3d_walk.restype = ctypes.c_int
@@ -454,6 +460,113 @@ def run_1d(mol, model, spec, T_bg, n_iter, use_ali=True, x0=None, tol=None,
                         shape=hfs.get(t))
 
     return _iterate(prob, march, n_iter, use_ali, x0, tol, record)
+
+
+def core_entry_1d(R, vr, bD, kappa, eta, impact, K, spec, I_bg):
+    """Intensity [n_rays, n_ch] each ray carries when it reaches the core
+    boundary R[K] on its way in (rows of rays that do not reach it are 0)."""
+    R, vr, bD, kappa, eta, impact = map(_f64, (R, vr, bD, kappa, eta, impact))
+    out = np.zeros(impact.shape[0] * spec.n_channels)
+    lib().orc1d_core_entry(R.shape[0], _dp(R), _dp(vr), _dp(bD), _dp(kappa), _dp(eta), impact.shape[0],
+                           _dp(impact), int(K), spec.n_channels, float(spec.v_min), float(spec.dv),
+                           float(I_bg), _dp(out))
+    return out.reshape(impact.shape[0], spec.n_channels)
+
+
+def march_core_1d(R, vr, bD, kappa, eta, impact, area, K, spec, I_enter):
+    """Raw sums (Jraw, Lraw) of the core pieces of the rays (shells 0..K),
+    each ray starting from its row of I_enter at the core boundary."""
+    R, vr, bD, kappa, eta, impact, area = map(_f64, (R, vr, bD, kappa, eta, impact, area))
+    I_enter = _f64(I_enter)
+    J, Lm = np.zeros(R.shape[0]), np.zeros(R.shape[0])
+    lib().orc1d_march_core(R.shape[0], _dp(R), _dp(vr), _dp(bD), _dp(kappa), _dp(eta), impact.shape[0],
+                           _dp(impact), _dp(area), int(K), spec.n_channels, float(spec.v_min),
+                           float(spec.dv), _dp(I_enter), _dp(J), _dp(Lm))
+    return J, Lm
+
+
+def core_extent(mol, model, spec, x, n_mol, bD, tau_min):
+    """Outermost shell of the optically thick core: the largest k whose
+    line-centre optical depth to the model's surface along the radius,
+    tau_k = sum_{k' >= k} kappa_k' (R_k' - R_k'-1) / (b_k' sqrt(pi)) (static
+    gas), reaches tau_min in some transition; -1 when none does."""
+    kap, _ = prepare(mol, x, n_mol)
+    R = _f64(model.r_out)
+    dr = np.diff(np.concatenate([[0.0], R]))
+    tau_shell = kap * dr / (_f64(bD) * SQRT_PI)
+    tau_out = np.cumsum(tau_shell[:, ::-1], axis=1)[:, ::-1]
+    hit = np.nonzero(np.max(tau_out, axis=0) >= tau_min)[0]
+    return int(hit[-1]) if hit.size else -1
+
+
+def run_1d_sub(mol, model, spec, T_bg, n_iter, n_sub, tau_min, x0=None, tol=None, record=True,
+               core=None):
+    """ALI iteration of a 1D model with sub-iterations in its optically thick
+    core (the paper's Sect. 4: populations updated more frequently where the
+    lines are thick; equilibrium and ALI form of Sect. 2).
+
+    Each iteration: (1) every transition is marched along every ray with the
+    current populations and every shell is solved, exactly as run_1d does
+    (delta is this solve's maximum relative change); (2) the core is the
+    shells 0..K, K = core_extent(the new populations, tau_min) (or the fixed
+    ``core``); with the envelope's new populations held, n_sub times: the
+    core's opacities and emissivities from its current populations, the core
+    pieces of the rays (each from the intensity it enters the core with,
+    computed once per iteration from the envelope), the core shells' solve
+    with those absorbed counts and diagonal operator (normalised by the full
+    ray set's W).  history[i]: x (after the sub-iterations), delta, K."""
+    prob = _Problem(mol, model.n_H2, model.T_kin, model.b_turb, model.abundance, spec, T_bg)
+    R = _f64(model.r_out)
+    impact = equidistant_impacts(R[-1], model.n_rays) if model.impact is None else _f64(model.impact)
+    area = ray_areas_1d(R[-1], impact)
+    vr = _f64(model.v_r)
+    x = lte_populations(mol, prob.T) if x0 is None else _f64(x0).copy()
+    hist = []
+    it_done = 0
+    W = None
+    for it in range(n_iter):
+        kap, eta = prepare(mol, x, prob.n_mol)
+        J = np.zeros((mol.n_trans, x.shape[0]))
+        Lam = np.zeros_like(J)
+        for t in range(mol.n_trans):
+            res = march_1d(R, vr, prob.bD, kap[t], eta[t], impact, area, spec, prob.I_bg[t])
+            W = res.W
+            Wsafe = np.where(W > 0, W, 1.0)
+            J[t] = res.Jraw / Wsafe
+            Lam[t] = res.Lraw / Wsafe
+        Rm = rate_matrix(mol, prob.n_H2, prob.T, J, Lam, True)
+        x_new = se_solve(Rm, x)
+        delta = max_rel_change(x_new, x)
+        if core is None:
+            K = core_extent(mol, model, spec, x_new, prob.n_mol, prob.bD, tau_min)
+        else:
+            K = int(core)
+        if K >= 0 and n_sub > 0:
+            c = slice(0, K + 1)
+            kap_n, eta_n = prepare(mol, x_new, prob.n_mol)
+            I_enter = [core_entry_1d(R, vr, prob.bD, kap_n[t], eta_n[t], impact, K, spec, prob.I_bg[t])
+                       for t in range(mol.n_trans)]
+            Wsafe = np.where(W > 0, W, 1.0)
+            for _ in range(n_sub):
+                kap_c, eta_c = prepare(mol, x_new, prob.n_mol)
+                Jc = np.zeros((mol.n_trans, K + 1))
+                Lc = np.zeros_like(Jc)
+                for t in range(mol.n_trans):
+                    jr, lr = march_core_1d(R, vr, prob.bD, kap_c[t], eta_c[t], impact, area, K, spec,
+                                           I_enter[t])
+                    Jc[t] = (jr / Wsafe)[c]
+                    Lc[t] = (lr / Wsafe)[c]
+                Rc = rate_matrix(mol, prob.n_H2[c], prob.T[c], Jc, Lc, True)
+                x_new[c] = se_solve(Rc, x_new[c])
+        if record:
+            hist.append(dict(x=x_new.copy(), delta=delta, K=K, J=J, Lam=Lam))
+        else:
+            hist.append(dict(delta=delta, K=K))
+        x = x_new
+        it_done = it + 1
+        if tol is not None and delta < tol:
+            break
+    return RunResult(x=x, history=hist, W=W, iters=it_done)
 
 
 def run_3d(mol, model, spec, T_bg, n_iter, dirs=None, use_ali=True, x0=None, tol=None,

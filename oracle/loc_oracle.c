@@ -298,6 +298,75 @@ void orc1d_march(int n, const double* R, const double* vr, const double* bD,
     accum_reduce_free(acc, nt, n, Jraw, Lraw, Wraw, Eraw, cons);
 }
 
+/* Sub-iterations in an optically thick core (the paper's Sect. 4 suggests
+ * updating the populations more often where the lines are thick).  The core
+ * is the inner ball of shells 0..K.  A ray reaches it when its innermost
+ * shell is inside it (R[K] > b); its path inside the core is one contiguous
+ * piece of its step list: inwards from R[K], the two tangent halves, outwards
+ * back to R[K].
+ *
+ * orc1d_core_entry: the intensity each ray carries when it reaches R[K] on
+ * its way in (the march of its envelope steps only, from I_bg), into
+ * I_enter[j*nch + c] for the rays that reach the core (others untouched).
+ *
+ * orc1d_march_core: the core piece of every ray that reaches the core, with
+ * the same steps and weights as orc1d_march, starting from I_enter; raw
+ * per-shell sums into Jraw, Lraw (all n entries written; zero outside the
+ * core). */
+void orc1d_core_entry(int n, const double* R, const double* vr, const double* bD,
+                      const double* kappa, const double* eta, int n_rays, const double* impact,
+                      int K, int nch, double vmin, double dv, double I_bg, double* I_enter)
+{
+    const shape_t shape = shape_of(0, NULL, NULL);
+    int* shell = (int*)malloc(sizeof(int) * 2 * (size_t)n);
+    double* s = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    double* mu = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    for (int j = 0; j < n_rays; ++j) {
+        if (!(R[K] > impact[j])) continue;
+        int ns = orc1d_ray_steps(n, R, impact[j], shell, s, mu);
+        double* I = I_enter + (size_t)j * nch;
+        for (int c = 0; c < nch; ++c) I[c] = I_bg;
+        for (int i = 0; i < ns && shell[i] > K; ++i) {
+            int k = shell[i];
+            double sj, sl, se;
+            cell_step(&shape, nch, vmin, dv, I, kappa[k], eta[k], bD[k], vr[k] * mu[i], s[i], &sj, &sl, &se);
+        }
+    }
+    free(shell);
+    free(s);
+    free(mu);
+}
+
+void orc1d_march_core(int n, const double* R, const double* vr, const double* bD,
+                      const double* kappa, const double* eta, int n_rays, const double* impact,
+                      const double* area, int K, int nch, double vmin, double dv, const double* I_enter,
+                      double* Jraw, double* Lraw)
+{
+    const shape_t shape = shape_of(0, NULL, NULL);
+    int* shell = (int*)malloc(sizeof(int) * 2 * (size_t)n);
+    double* s = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    double* mu = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    double* I = (double*)malloc(sizeof(double) * (size_t)nch);
+    for (int k = 0; k < n; ++k) Jraw[k] = Lraw[k] = 0.0;
+    for (int j = 0; j < n_rays; ++j) {
+        if (!(R[K] > impact[j])) continue;
+        int ns = orc1d_ray_steps(n, R, impact[j], shell, s, mu);
+        for (int c = 0; c < nch; ++c) I[c] = I_enter[(size_t)j * nch + c];
+        for (int i = 0; i < ns; ++i) {
+            int k = shell[i];
+            if (k > K) continue;             /* envelope steps: before and after the core piece */
+            double sj, sl, se;
+            cell_step(&shape, nch, vmin, dv, I, kappa[k], eta[k], bD[k], vr[k] * mu[i], s[i], &sj, &sl, &se);
+            Jraw[k] += area[j] * s[i] * sj;
+            Lraw[k] += area[j] * s[i] * sl;
+        }
+    }
+    free(shell);
+    free(s);
+    free(mu);
+    free(I);
+}
+
 /* ========================================================================= */
 /* 3D regular grid (Sect. 2.2)                                                */
 /* ========================================================================= */
