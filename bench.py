@@ -301,6 +301,39 @@ def lattice_bench(steps=2, warmup=1, n_refine=2):
     return out
 
 
+def subiter_bench(n_sub=3, tau_min=0.1, tol=1e-6, max_iter=500):
+    """Core sub-iterations on the thick variant of the 1000-shell Plummer
+    cloud (abundance 1e-6, line-centre depth ~60 through the centre): wall
+    time and iterations to a maximum relative change of tol, plain ALI and
+    with n_sub sub-iterations per iteration in the core whose radial depth to
+    the surface reaches tau_min."""
+    import paper_2009_12609_amd as miloc
+    import synth
+
+    w = synth.workload_1d_plummer(n_shells=1000, abundance=1.0e-6)
+    out = {"workload": f"{w.name} with abundance 1e-6 (thick), to {tol:g}", "n_sub": n_sub, "tau_min": tau_min}
+    for name, ns in (("plain", 0), ("one_subiteration", 1), ("subiterations", n_sub)):
+        ctx = miloc.Context(0)
+        ctx.load_molecule(w.mol)
+        ctx.load_model_1d(w.model)
+        ctx.set_spectral(w.spec.n_channels, w.spec.v_min, w.spec.dv)
+        ctx.set_background(w.T_bg)
+        ctx.set_subiterations(ns, tau_min)
+        ctx.run(1)                      # geometry and buffers, outside the timing
+        ctx.init_lte()
+        ctx.reset_counters()
+        t0 = time.perf_counter()
+        it, d = ctx.run(max_iter, tol=tol)
+        el = time.perf_counter() - t0
+        cnt = ctx.counters()
+        ctx.close()
+        out[name] = {"iterations": it, "last_delta": d, "wall_s": el,
+                     "ray_cell_steps": cnt["ray_steps"], "march_ms": cnt["march_ms"]}
+    out["speedup"] = out["plain"]["wall_s"] / out["subiterations"]["wall_s"]
+    out["speedup_one"] = out["plain"]["wall_s"] / out["one_subiteration"]["wall_s"]
+    return out
+
+
 def _pct(a, q):
     import numpy as np
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
@@ -419,6 +452,9 @@ def main():
     ap.add_argument("--lattice", type=int, default=0, metavar="STEPS",
                     help="time STEPS iterations of a two-level octree with the scheme's rays and with the "
                          "brute-force lattice ('lattice' object; 0 = skip, the default)")
+    ap.add_argument("--subiter", type=int, default=3, metavar="N_SUB",
+                    help="thick 1000-shell cloud to 1e-6 with and without N_SUB core sub-iterations "
+                         "('subiterations' object; 0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -522,6 +558,8 @@ def main():
         out["octree"] = octree_bench(args.octree)
     if args.lattice > 0:
         out["lattice"] = lattice_bench(args.lattice)
+    if args.subiter > 0:
+        out["subiterations"] = subiter_bench(args.subiter)
     if args.serve > 0:
         out["serving"] = serve_bench(args.serve)
     if not args.no_cpu_baseline and N == 128:

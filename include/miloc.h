@@ -193,6 +193,25 @@ miloc_status miloc_octree_schedule(const miloc_model3d* model, int n_dir, const 
                                    int64_t* n_steps, int64_t* n_trees, int* max_depth, uint32_t* steps_out,
                                    int64_t* trees_out);
 
+/* Device memory a context holds for a model, host computation only (no
+ * device or context needed): exactly one of m1 (1D) and m3 (3D) is given,
+ * with the species' level and transition counts, the channel count, the 3D
+ * ray directions (dirs[3*n_dir], or NULL for the 48 HEALPix ones) and the
+ * march precision (MILOC_MARCH_FP32 / _FP64).  Octrees need the step count
+ * of their ray schedule (oct_steps, from miloc_octree_schedule with the same
+ * directions); it is ignored otherwise.  *fixed_bytes: populations,
+ * opacities, sums and per-cell data, the channel-window table and the ray
+ * tables (for octrees including 2 GiB for the saved-intensity stacks, their
+ * cap); *sums_bytes: the 3D per-step partial sums of a march launch of one
+ * transition (0 in 1D).  A context refuses, with MILOC_ENOMEM and before
+ * allocating them, a 3D model whose fixed bytes plus one launch's sums
+ * exceed the free device memory (or MILOC_DEVICE_BUDGET_GB, an environment
+ * cap in GB for tests); with room, the launches take as many transitions as
+ * fit (see MILOC_STEP_BUFFER_GB).  MILOC_EINVAL for invalid arguments. */
+miloc_status miloc_model_footprint(const miloc_model1d* m1, const miloc_model3d* m3, int n_levels, int n_trans,
+                                   int n_channels, int n_dir, const double* dirs, int precision, int64_t oct_steps,
+                                   size_t* fixed_bytes, size_t* sums_bytes);
+
 /* Velocity channels (Sect. 2: a regular velocity grid per ray):
  * centres v_c = v_min + (c + 1/2) dv, c = 0..n_channels-1 (8..4096).  The
  * band must contain every cell's line out to 5 Doppler widths at any
@@ -249,6 +268,23 @@ miloc_status miloc_set_directions(miloc_ctx* ctx, int n_dir, const double* dirs)
  * FP64 accumulation) or MILOC_MARCH_FP64 (everything in FP64). */
 typedef enum { MILOC_MARCH_FP32 = 0, MILOC_MARCH_FP64 = 1 } miloc_march_precision;
 miloc_status miloc_set_march_precision(miloc_ctx* ctx, int precision);
+
+/* Sub-iterations in the optically thick core of a 1D model (the paper's
+ * Sect. 4 proposes updating the populations more often where the lines are
+ * thick).  After every iteration's global solve, the core -- shells 0..K,
+ * K the outermost shell whose radial line-centre optical depth to the
+ * model's surface (static gas, the new populations, any transition) reaches
+ * tau_min -- is iterated n_sub more times on its own: the rays that reach
+ * it march their inward envelope steps once (the intensity they enter the
+ * core with, from the envelope's new populations, which stay fixed), then
+ * n_sub times the core pieces of those rays are marched from those entry
+ * intensities and the core shells are solved (ALI form, weights W of the
+ * full ray set).  The convergence measure stays that of the global solve.
+ * The fixed point is that of plain ALI; thick cores need fewer iterations.
+ * n_sub = 0 (default) turns it off.  miloc_run returns MILOC_EINVAL when
+ * n_sub > 0 with a 3D model, use_ali = 0 or a hyperfine multiplet.  Errors
+ * here: MILOC_EINVAL for n_sub outside 0..1000 or a non-finite tau_min. */
+miloc_status miloc_set_subiterations(miloc_ctx* ctx, int n_sub, double tau_min);
 
 /* ------------------------------------------------------------- iteration */
 /* Populations = Boltzmann distribution at T_kin in every cell (LTE start,

@@ -94,6 +94,10 @@ SIGNATURES = {
     "miloc_load_model_3d": (ctypes.c_int, [_vp, ctypes.POINTER(Model3DStruct)]),
     "miloc_octree_schedule": (ctypes.c_int, [ctypes.POINTER(Model3DStruct), ctypes.c_int, _dp, ctypes.c_int,
                                              _i64p, _i64p, _ip, ctypes.POINTER(ctypes.c_uint32), _i64p]),
+    "miloc_model_footprint": (ctypes.c_int, [ctypes.POINTER(Model1DStruct), ctypes.POINTER(Model3DStruct),
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                             ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t),
+                                             ctypes.POINTER(ctypes.c_size_t)]),
     "miloc_set_spectral": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
     "miloc_set_background": (ctypes.c_int, [_vp, ctypes.c_double]),
     "miloc_set_hyperfine": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
@@ -101,6 +105,7 @@ SIGNATURES = {
     "miloc_set_directions_healpix": (ctypes.c_int, [_vp, ctypes.c_int]),
     "miloc_set_directions": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "miloc_set_march_precision": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "miloc_set_subiterations": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
     "miloc_init_lte": (ctypes.c_int, [_vp]),
     "miloc_set_populations": (ctypes.c_int, [_vp, _dp]),
     "miloc_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _dp]),
@@ -202,6 +207,27 @@ def _model3d_struct(m, keep):
         fc = ctypes.cast(ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))
     return Model3DStruct(n0, nl, float(m.root_cell_cm), counts, fc,
                          *[_ptr(a, ctypes.c_float) for a in arrs])
+
+
+def model_footprint(model, n_levels, n_trans, n_channels, dirs=None, fp64=False, oct_steps=0):
+    """Device bytes a context holds for a model (miloc_model_footprint):
+    (fixed, sums of one launch's transition)."""
+    L = load_library()
+    keep = []
+    m1 = m3 = None
+    if hasattr(model, "r_out"):
+        m1 = _model1d_struct(model, keep)
+    else:
+        m3 = _model3d_struct(model, keep)
+    d = None if dirs is None else _f64(dirs).reshape(-1, 3)
+    fixed, sums = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    rc = L.miloc_model_footprint(ctypes.byref(m1) if m1 else None, ctypes.byref(m3) if m3 else None,
+                                 int(n_levels), int(n_trans), int(n_channels), 0 if d is None else int(d.shape[0]),
+                                 _ptr(d, ctypes.c_double), 1 if fp64 else 0, int(oct_steps),
+                                 ctypes.byref(fixed), ctypes.byref(sums))
+    if rc != OK:
+        raise MilocError(rc, "miloc_model_footprint failed")
+    return fixed.value, sums.value
 
 
 def octree_schedule(model, dirs, plain=False, lattice=False):
@@ -391,6 +417,9 @@ class Context:
     def set_directions(self, dirs):
         d = _f64(dirs).reshape(-1, 3)
         self._check(self._lib.miloc_set_directions(self._h, int(d.shape[0]), _ptr(d, ctypes.c_double)))
+
+    def set_subiterations(self, n_sub: int, tau_min: float = 0.1):
+        self._check(self._lib.miloc_set_subiterations(self._h, int(n_sub), float(tau_min)))
 
     def set_march_precision(self, fp64: bool):
         self._check(self._lib.miloc_set_march_precision(self._h, MARCH_FP64 if fp64 else MARCH_FP32))

@@ -487,6 +487,10 @@ __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int
 
 }  // namespace
 
+// The step length of a crossing-pattern record (see StepRec).
+__device__ __forceinline__ float step_length(float log2_len) { return fast_exp2(log2_len); }
+__device__ __forceinline__ double step_length(double len) { return len; }
+
 template <typename T, int LANES, bool ACCUM, bool HF>
 __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
 {
@@ -583,15 +587,16 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
         }
         const int clo = as_int(wv.z);
         const int nwin = as_int(wv.w);
-        const T kl = kv.x * rec.len;      // tau at the line centre
-        const T el = kv.y * rec.len;
+        const T len = step_length(rec.len);
+        const T kl = kv.x * len;          // tau at the line centre
+        const T el = kv.y * len;
         T sj = 0, sl = 0;
         window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr, p.maser);
         if (ACCUM) {
             // every lane forms the weighted sums (the wavefront issues them
             // either way); only the group's last lane, which holds the
             // total, stores them
-            const T wgt = aw * rec.len;
+            const T wgt = aw * len;
             T2 v;
             v.x = wgt * group_sum<LANES>(sj);
             v.y = wgt * group_sum<LANES>(sl);
@@ -610,6 +615,204 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
     }
     if (!ACCUM && p.Iout && ray_ok) {
         T* out = p.Iout + ((size_t)q * p.rays_per_dir + r) * p.nch;
+        for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
+    }
+}
+
+namespace {
+
+// The lane group's passes over one step's window with the step length folded
+// into the profile, e_c' = e_c len = exp2(log2 len - x^2): then tau = khat e_c',
+// the emission ehat e_c' beta and both sums come out multiplied by the length
+// (otherwise as window_passes_f32).
+template <int LANES, int CLS>
+__device__ __forceinline__ void window_passes_folded(float* __restrict__ rl, int lane, int nwin, float xl,
+                                                     float hstep, float x0, float ibs, float l2len, float kh,
+                                                     float eh, float& sj, float& sl)
+{
+    constexpr int NU = LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4);
+    static_assert(NU * LANES <= kVecTailPadWords, "unconditional reads must stay in the LDS allocation");
+    float Iv[NU];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) Iv[i] = rl[i * LANES];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        if (lane + i * LANES < nwin) {
+            const float xs = fmaf((float)i, hstep, xl);
+            const float ec = fast_exp2(fmaf(-xs, xs, l2len));
+            const float omb = omb_class<CLS>(kh * ec);
+            const float u = fmaf(-ec, omb, ec);
+            sj = fmaf(Iv[i], u, sj);
+            sl = fmaf(ec, omb, sl);
+            rl[i * LANES] = fmaf(u, fmaf(-kh, Iv[i], eh), Iv[i]);
+        }
+    }
+    for (int j = lane + NU * LANES; j < nwin; j += LANES) {
+        const float xs = fmaf((float)j, ibs, x0);
+        const float ec = fast_exp2(fmaf(-xs, xs, l2len));
+        channel_update(rl + (j - lane), ec, omb_class<CLS>(kh * ec), kh, eh, sj, sl);
+    }
+}
+
+// One transverse move with periodic re-entry (as move_transverse), the
+// wrap-around corrections held in vector registers.
+__device__ __forceinline__ void move_wrap(int& c, int& idx, int s, int wrap_c, int d_step, int d_wrap, int N,
+                                          bool& restart)
+{
+    c += s;
+    const bool wrap = (unsigned)c >= (unsigned)N;
+    c -= wrap ? wrap_c : 0;
+    idx += wrap ? d_wrap : d_step;
+    restart |= wrap;
+}
+
+// A value the compiler keeps in a vector register (so that selects against
+// it need no per-use copy from a scalar register).
+__device__ __forceinline__ int in_vgpr(int v)
+{
+    int r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+    return r;
+}
+
+}  // namespace
+
+// The FP32 single-Gaussian regular-grid march (the same rays, steps, sums and
+// outputs as march3d_kernel<float, LANES, ACCUM, false>), arranged for
+// instruction count:
+//  * step records carry log2 of the length, absorbed by the profile exponent
+//    (window_passes_folded); the optical-depth class of a step is voted on
+//    |khat| times the direction's longest step, a bound on |tau|;
+//  * the ray weight |d_m| multiplies the queued sums when they are written;
+//  * the cell data of the coming steps are loaded into a ring of register
+//    sets, several steps ahead, so no prefetched value is copied;
+//  * the transverse wrap-around corrections sit in vector registers.
+template <int LANES, bool ACCUM>
+__global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
+{
+    const int rpb = blockDim.x / LANES;
+    const int lane = threadIdx.x % LANES;
+    const int rib = threadIdx.x / LANES;
+    int bid = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+    const int t = p.trans_offset + bid % p.ntr;
+    bid /= p.ntr;
+    const int q = bid / p.blocks_per_dir;
+    const int r = (bid - q * p.blocks_per_dir) * rpb + rib;
+    extern __shared__ unsigned char smem_raw[];
+    StepRec<float>* __restrict__ sst = reinterpret_cast<StepRec<float>*>(smem_raw);
+    float* __restrict__ I = reinterpret_cast<float*>(smem_raw + p.step_lds_bytes) + (size_t)rib * p.ich;
+
+    const DirDev D = p.dirs[q];
+    for (int i = threadIdx.x; i < D.nsteps; i += blockDim.x) sst[i] = p.steps[D.step0 + i];
+    __syncthreads();
+    const int rpw = 64 / LANES;
+    const int r_first = r - (rib % rpw);
+    if (r_first >= p.rays_per_dir) return;
+    const bool ray_ok = r < p.rays_per_dir;
+    const int rr = ray_ok ? r : p.rays_per_dir - 1;
+
+    const int N = p.N;
+    const int i0 = rr % N, j0 = rr / N;
+    int ca = i0, cb = j0;
+    int idx = D.start_off + i0 * D.sta + j0 * D.stb;
+    const int wrap_a = in_vgpr(D.sa * N), wrap_b = in_vgpr(D.sb * N);
+    const int da = in_vgpr(D.sa * D.sta), db = in_vgpr(D.sb * D.stb);
+    const int dwa = in_vgpr(-D.sa * (N - 1) * D.sta), dwb = in_vgpr(-D.sb * (N - 1) * D.stb);
+    const float Ibg = p.Ibg[t];
+    const int ts = p.ntr_total;
+    const float4* __restrict__ win = p.win + (size_t)q * p.nc;
+    const float2* __restrict__ ke = p.ke + t;
+    float2* __restrict__ E = p.E ? p.E + (size_t)(t - p.trans_offset) * p.e_tstride + (size_t)D.step0 * p.rays_per_dir
+                                 : nullptr;
+    const float aw = (float)D.aw;
+    const float kthin0 = (float)(1.0e-3 / D.maxlen);     // |khat| below: every |tau| < 1e-3
+    const float kthin1 = (float)(1.0e-2 / D.maxlen);
+    const int ns = D.nsteps;
+    for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+
+    float2* __restrict__ qw = reinterpret_cast<float2*>(smem_raw + p.queue_lds_offset) + (size_t)(rib - rib % rpw) * LANES;
+    const int wl = threadIdx.x & 63;
+    const int q_ray = wl % rpw, q_step = wl / rpw;
+    int qn = 0, qs0 = 0;
+
+    // the cell data of step s are loaded while step s - 1 is computed
+    auto fetch = [&](int s, float& l2len, bool& restart, float4& wv, float2& kv) {
+        const StepRec<float> rec = sst[s];
+        restart = false;
+        if (rec.flags & 1) idx += D.stride_m;
+        if (rec.flags & 2) move_wrap(ca, idx, D.sa, wrap_a, da, dwa, N, restart);
+        if (rec.flags & 4) move_wrap(cb, idx, D.sb, wrap_b, db, dwb, N, restart);
+        l2len = rec.len;
+        wv = win[(unsigned)idx];
+        kv = ke[(size_t)(unsigned)idx * (unsigned)ts];
+    };
+    auto step = [&](int s, float l2len, bool restart, const float4& wv, const float2& kv) {
+        if (restart) {
+            // side exit: re-entry on the opposite face with the background (Sect. 2.2)
+            for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+        }
+        const int clo = as_int(wv.z);
+        const int nwin = as_int(wv.w);
+        float* __restrict__ rl = I + clo + lane;
+        const float xl = fmaf((float)lane, wv.y, wv.x);
+        const float hstep = (float)LANES * wv.y;
+        const float akh = fabsf(kv.x);
+        float sj = 0.0f, sl = 0.0f;
+        if (__all(akh < kthin0)) {
+            window_passes_folded<LANES, 0>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+        } else if (__all(akh < kthin1)) {
+            window_passes_folded<LANES, 1>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+        } else {
+            if (kv.x * fast_exp2(l2len) < (float)kMaserTauMin) *p.maser = 1u;
+            window_passes_folded<LANES, 2>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+        }
+        if (ACCUM) {
+            float2 v;
+            v.x = group_sum<LANES>(sj);
+            v.y = group_sum<LANES>(sl);
+            keep_here(v.x);
+            keep_here(v.y);
+            if (lane == LANES - 1) qw[qn * rpw + (rib % rpw)] = v;
+            ++qn;
+            if (qn == LANES || s == ns - 1) {
+                const int rq = r_first + q_ray;
+                if (q_step < qn && rq < p.rays_per_dir) {
+                    float2 o = qw[q_step * rpw + q_ray];
+                    o.x *= aw;
+                    o.y *= aw;
+                    E[(size_t)(qs0 + q_step) * p.rays_per_dir + rq] = o;
+                }
+                qs0 += qn;
+                qn = 0;
+            }
+        }
+    };
+
+    // a ring of kPrefetch register sets: set i holds step s0 + i; once that
+    // step is done the set takes step s0 + i + kPrefetch, so each step's cell
+    // loads are issued kPrefetch - 1 steps of work before they are used
+    constexpr int kPrefetch = 4;
+    float l2r[kPrefetch];
+    bool rsr[kPrefetch];
+    float4 wvr[kPrefetch];
+    float2 kvr[kPrefetch];
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i)
+        if (i < ns) fetch(i, l2r[i], rsr[i], wvr[i], kvr[i]);
+    for (int s0 = 0; s0 < ns; s0 += kPrefetch) {
+#pragma unroll
+        for (int i = 0; i < kPrefetch; ++i) {
+            const int s = s0 + i;
+            if (s < ns) {
+                step(s, l2r[i], rsr[i], wvr[i], kvr[i]);
+                if (s + kPrefetch < ns) fetch(s + kPrefetch, l2r[i], rsr[i], wvr[i], kvr[i]);
+            }
+        }
+    }
+    if (!ACCUM && p.Iout && ray_ok) {
+        float* out = p.Iout + ((size_t)q * p.rays_per_dir + r) * p.nch;
         for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
     }
 }
@@ -1032,13 +1235,29 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
         const double a = p.area[j];
         const int kmin = p.kmin[j];
         const int nin = n - 1 - kmin;
-        const int nsteps = 2 * nin + 2;
-        const T2* __restrict__ rec = p.steps + p.ray_off[j];
+        // the ray's steps s0 .. s0 + nsteps - 1: all of them, or (core
+        // sub-iterations) its inward steps outside the core or its steps
+        // inside the core (inwards from R[core_k], the tangent halves,
+        // outwards back to R[core_k]); a ray of such a launch reaches the core
+        int s0 = 0, nsteps = 2 * nin + 2;
+        if (p.seg == kSegEnvelopeIn) {
+            nsteps = n - 1 - p.core_k;
+        } else if (p.seg == kSegCore) {
+            s0 = n - 1 - p.core_k;
+            nsteps = 2 * (p.core_k - kmin) + 2;
+        }
+        const T2* __restrict__ rec = p.steps + p.ray_off[j] + s0;
         const T Ibg = p.Ibg[t];
         HfRegs<T> hfr;
         if constexpr (HF) hfr.load(p.hf + (size_t)t * p.hfk, p.hfk);
-        for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
-        auto shell_of = [&](int s) {
+        if (p.seg == kSegCore) {
+            const T* __restrict__ src = p.Ient + ((size_t)(t - p.trans_offset) * p.nrays + j) * p.nch;
+            for (int c = lane; c < p.nch; c += LANES) I[c] = src[c];
+        } else {
+            for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+        }
+        auto shell_of = [&](int sl) {
+            const int s = sl + s0;
             return s < nin ? n - 1 - s : (s <= nin + 1 ? kmin : kmin + (s - nin - 1));
         };
         T2 mine = rec[lane < nsteps ? lane : 0];
@@ -1624,12 +1843,21 @@ hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
     const dim3 grid(a.blocks_per_dir * a.n_dir * a.ntr);
     const size_t shm = (size_t)a.queue_lds_offset + (size_t)rpb * LANES * 2 * sizeof(T);
     if (shm > 163840) return hipErrorInvalidValue;
-    if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)march3d_kernel<T, LANES, ACCUM, HF>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
+    if constexpr (std::is_same<T, float>::value && !HF) {
+        if (shm > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void*)march3d_f32_kernel<LANES, ACCUM>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((march3d_f32_kernel<LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
+    } else {
+        if (shm > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void*)march3d_kernel<T, LANES, ACCUM, HF>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((march3d_kernel<T, LANES, ACCUM, HF>), grid, dim3(rpb * LANES), shm, s, a);
     }
-    hipLaunchKernelGGL((march3d_kernel<T, LANES, ACCUM, HF>), grid, dim3(rpb * LANES), shm, s, a);
     return hipGetLastError();
 }
 

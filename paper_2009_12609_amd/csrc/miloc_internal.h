@@ -67,11 +67,14 @@ struct DirDev {
     int step0, nsteps;    // slice of the step table
     int m, fwd;           // main axis, 1 if d_m > 0
     int lstart0;          // offset of this direction's N+1 layer starts
+    double maxlen;        // longest step of the pattern (cell units)
 };
 
+// One step of a regular-grid crossing pattern.  FP32 marches store log2 of
+// the length (their profile exponent absorbs it), FP64 marches the length.
 template <typename T>
 struct StepRec {
-    T len;                // path length in cell units
+    T len;                // path length in cell units (FP32: its base-2 logarithm)
     int flags;            // moves before this step: 1 = main axis, 2 = axis a, 4 = axis b
 };
 
@@ -141,7 +144,19 @@ struct March1DArgs {
     int hfk;
     double hf_lo, hf_hi;                 // lowest / highest component offset (channels; <= 0, >= 0)
     unsigned* maser;                     // as in March3DArgs
+    // Part of each ray marched (sub-iterations in an optically thick core of
+    // shells 0..core_k; the launch then covers only rays that reach it):
+    // kSegWhole the whole ray from I_bg; kSegEnvelopeIn its inward steps
+    // outside the core, from I_bg, leaving in Iout the intensity it enters
+    // the core with; kSegCore its steps inside the core, from Ient.
+    int seg;
+    int core_k;
+    const T* Ient;                       // kSegCore: [ntr][nrays][nch] entry intensities
 };
+
+constexpr int kSegWhole = 0;
+constexpr int kSegEnvelopeIn = 1;
+constexpr int kSegCore = 2;
 
 struct SEArgs {
     int nc, L, ntr, use_ali, bs;

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -35,24 +36,51 @@ constexpr double kSqrtLog2e = 1.2011224087864498;   // sqrt(log2(e))
 constexpr double kWindowK32 = 5.0;
 constexpr double kWindowK64 = 6.5;
 
+// A device region that DevBufs carve their storage from instead of calling
+// hipMalloc, while it is installed on the calling thread (the allocation-free
+// entry point installs the library's static scratch for the duration of one
+// call).  Bump allocation in 256-byte units; nothing is returned before the
+// region is uninstalled.
+struct ScratchCarve {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    bool overflow = false;
+};
+thread_local ScratchCarve* tls_carve = nullptr;
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool carved = false;                 // storage from a ScratchCarve (not freed)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && !carved) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        carved = false;
     }
     hipError_t ensure(size_t n)
     {
         if (n == 0) n = 8;
         if (p && bytes == n) return hipSuccess;
         release();
+        if (ScratchCarve* sc = tls_carve) {
+            const size_t off = (sc->used + 255) & ~(size_t)255;
+            if (off > sc->size || n > sc->size - off) {
+                sc->overflow = true;
+                return hipErrorOutOfMemory;
+            }
+            p = sc->base + off;
+            sc->used = off + n;
+            bytes = n;
+            carved = true;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(&p, n);
         if (e != hipSuccess) { p = nullptr; return e; }
         bytes = n;
@@ -126,6 +154,13 @@ struct miloc_ctx {
     double chalf = 0;
     double Kw = 0;
     int n_dir_dev = 0;
+    // sub-iterations in the optically thick core of a 1D model
+    int n_sub = 0;
+    double sub_tau_min = 0.0;
+    double sums_budget = 0.0;            // device bytes left for the 3D per-step sums (check_fits)
+    int sub_last_k = -1;                 // core extent of the last iteration (-1: none)
+    std::vector<int> kmin_host;          // innermost shell of each ray (1D)
+    DevBuf d_ient, d_sflags;             // core entry intensities; flags of the core solves
     std::vector<DirDev> dir_host;
     // hyperfine multiplets per transition: offsets (cm/s) and strengths
     // normalised to sum 1; empty = single Gaussian
@@ -136,6 +171,20 @@ struct miloc_ctx {
     DevBuf d_hf;                 // [T][hfk] {offset / dv, strength}, zero-strength padding
 
     miloc_counters ctr{};
+
+    // device bytes held in the context's buffers
+    size_t device_bytes() const
+    {
+        const DevBuf* all[] = {&d_mol, &d_x, &d_xnew, &d_nH2, &d_T, &d_q, &d_nmolLb, &d_cellv, &d_ke, &d_acc,
+                               &d_Ibg, &d_Ibg64, &d_zero, &d_dirs, &d_steps, &d_flags, &d_R, &d_vrdv, &d_area,
+                               &d_vel, &d_bD, &d_win, &d_lstart, &d_moves, &d_qlist, &d_E, &d_osteps, &d_olen64,
+                               &d_otrees, &d_oaw, &d_ostack, &d_ocounter, &d_ocell_off, &d_ocell_steps, &d_oE,
+                               &d_1steps, &d_1off, &d_1kmin, &d_los_b, &d_los_steps, &d_los_off, &d_los_kmin,
+                               &d_los_out, &d_hf, &d_ient, &d_sflags};
+        size_t n = 0;
+        for (const DevBuf* b : all) n += b->carved ? 0 : b->bytes;
+        return n;
+    }
 };
 
 namespace {
@@ -153,6 +202,23 @@ miloc_status fail(miloc_ctx* c, miloc_status code, const std::string& msg)
             return fail((ctx), _e == hipErrorOutOfMemory ? MILOC_ENOMEM : MILOC_EDEVICE,     \
                         std::string(#expr) + ": " + hipGetErrorString(_e));                 \
     } while (0)
+
+// Timing events of a context; the allocation-free call runs on a context
+// without events (and keeps no timings): there a record is skipped, a wait
+// on an event waits for the stream and an elapsed time reads 0.
+hipError_t ev_record(miloc_ctx* c, int i)
+{
+    return c->ev[i] ? hipEventRecord(c->ev[i], c->stream) : hipSuccess;
+}
+hipError_t ev_sync(miloc_ctx* c, int i)
+{
+    return c->ev[i] ? hipEventSynchronize(c->ev[i]) : hipStreamSynchronize(c->stream);
+}
+hipError_t ev_elapsed(miloc_ctx* c, float* ms, int a, int b)
+{
+    *ms = 0.0f;
+    return c->ev[a] && c->ev[b] ? hipEventElapsedTime(ms, c->ev[a], c->ev[b]) : hipSuccess;
+}
 
 bool finite_all(const double* a, int64_t n)
 {
@@ -194,6 +260,72 @@ struct CellView {
     double bt(int64_t k) const { return c->kind == 1 ? c->bt[k] : (double)c->f_bt[k]; }
     double X(int64_t k) const { return c->kind == 1 ? c->X[k] : (double)c->f_X[k]; }
 };
+
+// Device bytes a context holds for a model (kind 1: shells, 3: regular
+// grid, 4: octree): `fixed` for the populations, opacities, sums, per-cell
+// data, the channel-window table and the ray tables, `sums` for the 3D
+// march's per-step partial sums per transition of a launch.  steps: ray-cell
+// steps of one transition (1D rays, the regular grid's crossing patterns per
+// representative ray, or the octree schedule); rays: 1D rays, or rays per
+// direction of a regular grid; trees: octree work units.
+struct Footprint {
+    size_t fixed = 0;
+    size_t sums = 0;
+};
+
+Footprint footprint_of(int kind, int64_t nc, int L, int T, int nch, int n_dir, bool fp64, int64_t steps,
+                       int64_t rays, int64_t trees)
+{
+    const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+    const size_t c = (size_t)nc;
+    Footprint f;
+    f.fixed = sizeof(MolDev) + 16 + 2 * c * L * sizeof(double) + 4 * c * sizeof(double) +
+              (size_t)T * c * (2 * tsz + sizeof(double2)) + (size_t)3 * T * sizeof(double);
+    if (kind == 1) {
+        f.fixed += c * (2 * sizeof(double) + 2 * tsz) + (size_t)rays * (2 * sizeof(double) + sizeof(int64_t) + sizeof(int)) +
+                   (size_t)steps * 2 * tsz;
+        return f;
+    }
+    f.fixed += c * (sizeof(float4) + sizeof(double)) + (size_t)n_dir * c * 4 * tsz + (size_t)n_dir * sizeof(DirDev);
+    if (kind == 3) {
+        const int64_t N = (int64_t)std::llround(std::cbrt((double)nc));
+        f.fixed += (size_t)steps * (sizeof(StepRec<double>) + sizeof(int2)) + (size_t)n_dir * (N + 1) * sizeof(int);
+        f.sums = (size_t)steps * (size_t)rays * 2 * tsz;
+    } else {
+        // cell step lists, step records (+ FP64 lengths), work units, and at
+        // most 2 GiB of saved-vector stacks
+        f.fixed += (c + 1) * sizeof(int64_t) + (size_t)steps * (sizeof(uint32_t) + sizeof(uint2)) +
+                   (fp64 ? (size_t)steps * sizeof(double) : 0) + (size_t)trees * sizeof(OctTreeRec) +
+                   ((size_t)2 << 30);
+        // FP32 rows hold an even number of transitions (16-byte rows)
+        f.sums = (size_t)steps * 2 * tsz * (fp64 ? 1 : 2);
+    }
+    return f;
+}
+
+// Refuses (MILOC_ENOMEM, before the model's static arrays are allocated) a
+// model whose arrays and tables plus one transition's per-step sums exceed
+// the device memory this context can use: the free memory plus what it holds
+// already, capped by MILOC_DEVICE_BUDGET_GB when set.  *sums_budget receives
+// the bytes left for the per-step sums.
+miloc_status check_fits(miloc_ctx* c, const Footprint& f, double* sums_budget)
+{
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+    double avail = (double)free_b + (double)c->device_bytes();
+    if (const char* ev = std::getenv("MILOC_DEVICE_BUDGET_GB")) avail = std::min(avail, std::atof(ev) * 1e9);
+    const double need = (double)f.fixed + (double)f.sums;
+    if (need > avail) {
+        char buf[320];
+        std::snprintf(buf, sizeof buf,
+                      "the model needs %.3f GB of device memory (%.3f GB of arrays and ray tables, %.3f GB of "
+                      "per-step sums for one transition); %.3f GB are available",
+                      need * 1e-9, (double)f.fixed * 1e-9, (double)f.sums * 1e-9, avail * 1e-9);
+        return fail(c, MILOC_ENOMEM, buf);
+    }
+    *sums_budget = avail - (double)f.fixed;
+    return MILOC_OK;
+}
 
 // Molecule and per-cell base arrays (needs molecule + model).
 miloc_status ensure_base(miloc_ctx* c)
@@ -260,12 +392,20 @@ void pack_cell_static(miloc_ctx* c, const std::vector<double>& b, std::vector<ch
     }
 }
 
+// The length field of a regular-grid step record (see StepRec).
+template <typename TT>
+TT step_len_rec(double len)
+{
+    if (sizeof(TT) == sizeof(double)) return (TT)len;
+    return (TT)std::log2(len);
+}
+
 template <typename TT>
 miloc_status upload_steps(miloc_ctx* c, const std::vector<double>& len, const std::vector<int>& fl)
 {
     std::vector<StepRec<TT>> st(len.size());
     for (size_t i = 0; i < len.size(); ++i) {
-        st[i].len = (TT)len[i];
+        st[i].len = step_len_rec<TT>(len[i]);
         st[i].flags = fl[i];
     }
     HIPCHK(c, c->d_steps.ensure(std::max<size_t>(1, st.size()) * sizeof(StepRec<TT>)));
@@ -329,6 +469,7 @@ void build_patterns(int N, const std::vector<double>& dirs, std::vector<DirDev>&
         D.m = P.m;
         D.fwd = fwd ? 1 : 0;
         D.lstart0 = lstart ? (int)lstart->size() : 0;
+        D.maxlen = P.len.empty() ? 0.0 : *std::max_element(P.len.begin(), P.len.end());
         len.insert(len.end(), P.len.begin(), P.len.end());
         fl.insert(fl.end(), P.flags.begin(), P.flags.end());
         if (lstart) lstart->insert(lstart->end(), P.layer_start.begin(), P.layer_start.end());
@@ -364,6 +505,10 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
     const std::string e = octree_schedule(c->oct, c->dirs, c->oct_lattice ? OctRays::Lattice : OctRays::Scheme,
                                           host_threads(), S, fp64, c->nc);
     if (!e.empty()) return fail(c, MILOC_EINVAL, e);
+    miloc_status fit = check_fits(c, footprint_of(4, c->nc, c->L, c->T, c->nch, nd, fp64, S.n_steps, 0,
+                                                  (int64_t)S.trees.size()),
+                                  &c->sums_budget);
+    if (fit != MILOC_OK) return fit;
     HIPCHK(c, c->d_ocell_off.ensure(S.cell_off.size() * sizeof(int64_t)));
     HIPCHK(c, hipMemcpy(c->d_ocell_off.p, S.cell_off.data(), S.cell_off.size() * sizeof(int64_t),
                         hipMemcpyHostToDevice));
@@ -377,6 +522,7 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
         // transitions go in one launch when they fit
         double budget_gb = 160.0;
         if (const char* ev = std::getenv("MILOC_STEP_BUFFER_GB")) budget_gb = std::atof(ev);
+        budget_gb = std::min(budget_gb, c->sums_budget * 1e-9);
         const size_t per_t = (size_t)std::max<int64_t>(1, S.n_steps) * 2 * (fp64 ? sizeof(double) : sizeof(float));
         // FP32 rows padded to an even number of transitions (16-byte rows)
         auto stride_of = [&](int tc) { return fp64 ? tc : (tc + 1) / 2 * 2; };
@@ -568,6 +714,10 @@ miloc_status ensure_static(miloc_ctx* c)
         c->dir_host = dd;
         c->n_dir_dev = (int)dd.size();
         c->total_steps = (int64_t)len.size();
+        st = check_fits(c, footprint_of(3, nc, c->L, c->T, c->nch, (int)dd.size(), fp64, c->total_steps,
+                                        (int64_t)N * N, 0),
+                        &c->sums_budget);
+        if (st != MILOC_OK) return st;
         HIPCHK(c, c->d_lstart.ensure(lst.size() * sizeof(int)));
         HIPCHK(c, hipMemcpy(c->d_lstart.p, lst.data(), lst.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCHK(c, c->d_moves.ensure(mvs.size() * sizeof(int2)));
@@ -625,8 +775,7 @@ miloc_status ensure_static(miloc_ctx* c)
             HIPCHK(c, hipStreamSynchronize(c->stream));
         }
         std::vector<int64_t> o;
-        std::vector<int> km;
-        c->steps_per_trans = (double)shell_ray_layout(n, Rn.data(), c->nrays, bn.data(), o, km);
+        c->steps_per_trans = (double)shell_ray_layout(n, Rn.data(), c->nrays, bn.data(), o, c->kmin_host);
     }
     std::vector<double> q(nc), nmolLb(nc);
     for (int64_t k = 0; k < nc; ++k) {
@@ -696,6 +845,7 @@ miloc_status ensure_static(miloc_ctx* c)
         // per-step partial sums: as many transitions per march launch as fit the budget
         double budget_gb = 16.0;
         if (const char* ev = std::getenv("MILOC_STEP_BUFFER_GB")) budget_gb = std::atof(ev);
+        budget_gb = std::min(budget_gb, c->sums_budget * 1e-9);
         const size_t per_t = (size_t)c->total_steps * c->N * c->N * 2 * tsz;
         int tc = (int)std::min<double>((double)c->T, std::floor(budget_gb * 1e9 / (double)per_t));
         c->trans_chunk = tc < 1 ? 1 : tc;
@@ -726,6 +876,133 @@ void invalidate_model(miloc_ctx* c)
     c->dirty = true;
     c->has_pops = false;
     c->has_rad = false;
+}
+
+// March arguments of a 1D model's own ray set (every ray from I_bg, all of
+// its steps, accumulation into acc).
+template <typename TT>
+void fill_march1d(miloc_ctx* c, int ntr, int toff, March1DArgs<TT>& a)
+{
+    a.n = (int)c->nc;
+    a.nrays = c->nrays;
+    a.nch = c->nch;
+    a.ntr = ntr;
+    a.trans_offset = toff;
+    a.steps = c->d_1steps.as<typename V2<TT>::type>();
+    a.ray_off = c->d_1off.as<long long>();
+    a.kmin = c->d_1kmin.as<int>();
+    a.area = c->d_area.as<double>();
+    a.shellv = c->d_cellv.as<typename V2<TT>::type>();
+    a.ke = c->d_ke.as<typename V2<TT>::type>();
+    a.Ibg = c->d_Ibg.as<TT>();
+    a.acc = c->d_acc.as<double2>();
+    a.chalf = c->chalf;
+    a.Kw = (TT)c->Kw;
+    a.Iout = nullptr;
+    a.ntr_total = c->T;
+    a.hf = c->hfk ? c->d_hf.as<typename V2<TT>::type>() : nullptr;
+    a.hfk = c->hfk;
+    a.hf_lo = c->hf_lo;
+    a.hf_hi = c->hf_hi;
+    a.maser = maser_flag(c);
+    a.seg = kSegWhole;
+    a.core_k = 0;
+    a.Ient = nullptr;
+}
+
+// Sub-iterations in the optically thick core of a 1D model (the paper's
+// Sect. 4: populations updated more often where the lines are thick), after
+// an iteration's global solve has left the new populations in d_x: the core
+// is the shells 0..K, K the outermost shell whose radial line-centre optical
+// depth to the surface (static gas, these populations, any transition)
+// reaches sub_tau_min.  The rays that reach the core march their inward
+// envelope steps once (the intensity they enter the core with; the envelope's
+// populations stay as solved), then n_sub times: the core's opacities and
+// emissivities, the core pieces of those rays from their entry intensities
+// with the absorbed counts and the diagonal operator accumulated for the core
+// shells, and the core shells' ALI solve (W of the full ray set).  Adds the
+// marched ray-cell steps (per transition) to *steps.
+template <typename TT>
+miloc_status core_subiterations(miloc_ctx* c, double* steps)
+{
+    using T2 = typename V2<TT>::type;
+    const bool fp64 = sizeof(TT) == sizeof(double);
+    const int n = (int)c->nc;
+    c->sub_last_k = -1;
+    HIPCHK(c, launch_prepare(c->stream, n, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
+                             c->d_nmolLb.as<double>(), nullptr, c->d_ke.p, fp64));
+    std::vector<T2> ke((size_t)n * c->T);
+    HIPCHK(c, hipMemcpyAsync(ke.data(), c->d_ke.p, ke.size() * sizeof(T2), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // khat = kappa R_out / (b sqrt(pi)) and radii in units of R_out: the
+    // line-centre depth of shell k is khat (R_k - R_k-1)
+    int K = -1;
+    std::vector<double> tau(c->T, 0.0);
+    for (int k = n - 1; k >= 0 && K < 0; --k) {
+        const double dr = c->Rn[k] - (k > 0 ? c->Rn[k - 1] : 0.0);
+        for (int t = 0; t < c->T; ++t) {
+            tau[t] += (double)ke[(size_t)k * c->T + t].x * dr;
+            if (tau[t] >= c->sub_tau_min) K = k;
+        }
+    }
+    c->sub_last_k = K;
+    if (K < 0) return MILOC_OK;
+    // the rays that reach the core (sorted by impact parameter: a prefix)
+    int nr = 0;
+    double core_steps = 0.0;
+    while (nr < c->nrays && c->kmin_host[nr] <= K) {
+        core_steps += 2.0 * (K - c->kmin_host[nr]) + 2.0;
+        ++nr;
+    }
+    if (nr == 0) return MILOC_OK;
+    HIPCHK(c, c->d_ient.ensure((size_t)c->T * nr * c->nch * sizeof(TT)));
+    HIPCHK(c, c->d_sflags.ensure(16));
+    HIPCHK(c, hipMemsetAsync(c->d_sflags.p, 0, 16, c->stream));
+    March1DArgs<TT> a{};
+    fill_march1d(c, c->T, 0, a);
+    a.nrays = nr;
+    a.core_k = K;
+    a.seg = kSegEnvelopeIn;
+    a.Iout = c->d_ient.as<TT>();
+    HIPCHK(c, launch_march1d(c->stream, a, c->lanes, false));
+    *steps += (double)nr * (n - 1 - K);
+    a.seg = kSegCore;
+    a.Iout = nullptr;
+    a.Ient = c->d_ient.as<TT>();
+    for (int m = 0; m < c->n_sub; ++m) {
+        if (m > 0)
+            HIPCHK(c, launch_prepare(c->stream, K + 1, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
+                                     c->d_nmolLb.as<double>(), nullptr, c->d_ke.p, fp64));
+        HIPCHK(c, hipMemsetAsync(c->d_acc.p, 0, (size_t)(K + 1) * c->T * sizeof(double2), c->stream));
+        HIPCHK(c, launch_march1d(c->stream, a, c->lanes, true));
+        SEArgs se{};
+        se.nc = K + 1;
+        se.L = c->L;
+        se.ntr = c->T;
+        se.use_ali = 1;
+        se.mol = c->d_mol.as<MolDev>();
+        se.x_old = c->d_x.as<double>();
+        se.x_new = c->d_xnew.as<double>();
+        se.nH2 = c->d_nH2.as<double>();
+        se.Tkin = c->d_T.as<double>();
+        se.q = c->d_q.as<double>();
+        se.acc = c->d_acc.as<double2>();
+        se.delta_bits = c->d_sflags.as<unsigned long long>();
+        se.bad = reinterpret_cast<unsigned int*>(c->d_sflags.as<char>() + 8);
+        HIPCHK(c, launch_se(c->stream, se));
+        HIPCHK(c, hipMemcpyAsync(c->d_x.p, c->d_xnew.p, (size_t)(K + 1) * c->L * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c->stream));
+        *steps += core_steps;
+    }
+    unsigned long long fl[2] = {0, 0};
+    unsigned maser = 0;
+    HIPCHK(c, hipMemcpyAsync(fl, c->d_sflags.p, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&maser, maser_flag(c), sizeof maser, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (maser) return fail(c, MILOC_ENUMERIC, "maser: a step's line-centre optical depth fell below -40");
+    if (fl[1] & 0xffffffffu)
+        return fail(c, MILOC_ENUMERIC, "non-finite or negative populations from a core sub-iteration solve");
+    return MILOC_OK;
 }
 
 template <typename TT>
@@ -767,29 +1044,16 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         e = launch_march3d(c->stream, a, c->lanes, accum, max_steps);
     } else {
         March1DArgs<TT> a{};
-        a.n = (int)c->nc;
+        fill_march1d(c, ntr, toff, a);
         a.nrays = bimp_override ? nrays_override : c->nrays;
-        a.nch = c->nch;
-        a.ntr = ntr;
-        a.trans_offset = toff;
-        a.steps = ray_steps ? reinterpret_cast<const typename V2<TT>::type*>(ray_steps->p)
-                            : c->d_1steps.as<typename V2<TT>::type>();
-        a.ray_off = ray_steps ? ray_off->as<long long>() : c->d_1off.as<long long>();
-        a.kmin = ray_steps ? ray_kmin->as<int>() : c->d_1kmin.as<int>();
-        a.area = bimp_override ? bimp_override : c->d_area.as<double>();
-        a.shellv = c->d_cellv.as<typename V2<TT>::type>();
-        a.ke = c->d_ke.as<typename V2<TT>::type>();
+        if (ray_steps) {
+            a.steps = reinterpret_cast<const typename V2<TT>::type*>(ray_steps->p);
+            a.ray_off = ray_off->as<long long>();
+            a.kmin = ray_kmin->as<int>();
+        }
+        if (bimp_override) a.area = bimp_override;
         a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
-        a.acc = c->d_acc.as<double2>();
-        a.chalf = c->chalf;
-        a.Kw = (TT)c->Kw;
         a.Iout = Iout;
-        a.ntr_total = c->T;
-        a.hf = c->hfk ? c->d_hf.as<typename V2<TT>::type>() : nullptr;
-        a.hfk = c->hfk;
-        a.hf_lo = c->hf_lo;
-        a.hf_hi = c->hf_hi;
-        a.maser = maser_flag(c);
         // lines of sight run alone: 64 lanes shorten each step's channel loop
         e = launch_march1d(c->stream, a, accum ? c->lanes : 64, accum);
     }
@@ -1046,6 +1310,57 @@ miloc_status miloc_octree_schedule(const miloc_model3d* m, int n_dir, const doub
     return MILOC_OK;
 }
 
+miloc_status miloc_model_footprint(const miloc_model1d* m1, const miloc_model3d* m3, int n_levels, int n_trans,
+                                   int n_channels, int n_dir, const double* dirs, int precision, int64_t oct_steps,
+                                   size_t* fixed_bytes, size_t* sums_bytes)
+{
+    if ((m1 == nullptr) == (m3 == nullptr) || !fixed_bytes || !sums_bytes) return MILOC_EINVAL;
+    if (n_levels < 2 || n_levels > kMaxLevels || n_trans < 1 || n_trans > kMaxTrans || n_channels < 1)
+        return MILOC_EINVAL;
+    if (precision != MILOC_MARCH_FP32 && precision != MILOC_MARCH_FP64) return MILOC_EINVAL;
+    const bool fp64 = precision == MILOC_MARCH_FP64;
+    Footprint f;
+    if (m1) {
+        const int n = m1->n_shells;
+        if (n < 1 || n > 65536 || !m1->r_out_cm || m1->n_rays < 1 || m1->n_rays > 65536) return MILOC_EINVAL;
+        const double R = m1->r_out_cm[n - 1];
+        if (!(R > 0)) return MILOC_EINVAL;
+        std::vector<double> Rn(n), bn(m1->n_rays);
+        for (int k = 0; k < n; ++k) Rn[k] = m1->r_out_cm[k] / R;
+        Rn[n - 1] = 1.0;
+        for (int j = 0; j < m1->n_rays; ++j)
+            bn[j] = m1->impact_cm ? m1->impact_cm[j] / R : (j + 0.5) / m1->n_rays;
+        std::vector<int64_t> off;
+        std::vector<int> km;
+        const int64_t steps = shell_ray_layout(n, Rn.data(), m1->n_rays, bn.data(), off, km);
+        f = footprint_of(1, n, n_levels, n_trans, n_channels, 0, fp64, steps, m1->n_rays, 0);
+    } else {
+        const int N = m3->n0[0];
+        if (N < 1 || N > 1024 || m3->n0[1] != N || m3->n0[2] != N || m3->n_oct_levels < 0) return MILOC_EINVAL;
+        std::vector<double> dv = dirs ? std::vector<double>(dirs, dirs + 3 * (size_t)std::max(0, n_dir))
+                                      : healpix_directions(2);
+        const int nd = (int)dv.size() / 3;
+        if (nd < 1 || nd > 1024) return MILOC_EINVAL;
+        if (m3->n_oct_levels == 0) {
+            if (N < 2) return MILOC_EINVAL;
+            std::vector<DirDev> dd;
+            std::vector<double> len;
+            std::vector<int> fl;
+            build_patterns(N, dv, dd, len, fl, nullptr);
+            f = footprint_of(3, (int64_t)N * N * N, n_levels, n_trans, n_channels, nd, fp64, (int64_t)len.size(),
+                             (int64_t)N * N, 0);
+        } else {
+            if (!m3->n_cells_per_level || oct_steps < 0) return MILOC_EINVAL;
+            int64_t nc = 0;
+            for (int l = 0; l < m3->n_oct_levels; ++l) nc += m3->n_cells_per_level[l];
+            f = footprint_of(4, nc, n_levels, n_trans, n_channels, nd, fp64, oct_steps, 0, (int64_t)nd * N * N);
+        }
+    }
+    *fixed_bytes = f.fixed;
+    *sums_bytes = f.sums;
+    return MILOC_OK;
+}
+
 miloc_status miloc_set_spectral(miloc_ctx* c, int n_channels, double v_min_cms, double dv_cms)
 {
     miloc_status s = check_ctx(c);
@@ -1138,6 +1453,17 @@ miloc_status miloc_set_directions(miloc_ctx* c, int n_dir, const double* dirs)
     return MILOC_OK;
 }
 
+miloc_status miloc_set_subiterations(miloc_ctx* c, int n_sub, double tau_min)
+{
+    if (!c) return MILOC_EINVAL;
+    c->err.clear();
+    if (n_sub < 0 || n_sub > 1000) return fail(c, MILOC_EINVAL, "n_sub must be in 0..1000");
+    if (!std::isfinite(tau_min)) return fail(c, MILOC_EINVAL, "tau_min must be finite");
+    c->n_sub = n_sub;
+    c->sub_tau_min = tau_min;
+    return MILOC_OK;
+}
+
 miloc_status miloc_set_march_precision(miloc_ctx* c, int precision)
 {
     miloc_status s = check_ctx(c);
@@ -1197,6 +1523,13 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
     if (s) return s;
     if (max_iter < 1) return fail(c, MILOC_EINVAL, "max_iter must be >= 1");
     if (!std::isfinite(tol)) return fail(c, MILOC_EINVAL, "tol must be finite");
+    if (c->n_sub > 0) {
+        if (c->kind != 1) return fail(c, MILOC_EINVAL, "core sub-iterations are for 1D models");
+        if (!use_ali) return fail(c, MILOC_EINVAL, "core sub-iterations need the ALI form (use_ali != 0)");
+        for (int t = 0; t < c->T; ++t)
+            if (!c->hf_v[t].empty())
+                return fail(c, MILOC_EINVAL, "core sub-iterations are for single-Gaussian lines");
+    }
     s = ensure_static(c);
     if (s) return s;
     if (!c->has_pops) {
@@ -1211,27 +1544,27 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
     for (; it < max_iter; ++it) {
         // convergence maximum, failure counter and maser flag of this iteration
         HIPCHK(c, hipMemsetAsync(c->d_flags.p, 0, 16, c->stream));
-        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        HIPCHK(c, ev_record(c, 0));
         HIPCHK(c, launch_prepare(c->stream, (int)nc, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
                                  c->d_nmolLb.as<double>(), nullptr, c->d_ke.p, fp64));
         HIPCHK(c, hipMemsetAsync(c->d_acc.p, 0, c->d_acc.bytes, c->stream));
-        HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+        HIPCHK(c, ev_record(c, 1));
         float t_march = 0, t_gather = 0;
         if (c->kind == 3) {
             for (int t0 = 0; t0 < c->T; t0 += c->trans_chunk) {
                 const int nt = std::min(c->trans_chunk, c->T - t0);
-                if (t0 > 0) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+                if (t0 > 0) HIPCHK(c, ev_record(c, 1));
                 s = fp64 ? launch_march<double>(c, nt, t0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
                          : launch_march<float>(c, nt, t0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
                 if (s) return s;
-                HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+                HIPCHK(c, ev_record(c, 4));
                 s = fp64 ? launch_gathers<double>(c, t0, nt) : launch_gathers<float>(c, t0, nt);
                 if (s) return s;
-                HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
-                HIPCHK(c, hipEventSynchronize(c->ev[5]));
+                HIPCHK(c, ev_record(c, 5));
+                HIPCHK(c, ev_sync(c, 5));
                 float a = 0, b = 0;
-                HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[4]));
-                HIPCHK(c, hipEventElapsedTime(&b, c->ev[4], c->ev[5]));
+                HIPCHK(c, ev_elapsed(c, &a, 1, 4));
+                HIPCHK(c, ev_elapsed(c, &b, 4, 5));
                 t_march += a;
                 t_gather += b;
                 c->ctr.march_launches += 1;
@@ -1239,14 +1572,14 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
         } else if (c->kind == 4) {
             for (int t0 = 0; t0 < c->T; t0 += c->trans_chunk) {
                 const int nt = std::min(c->trans_chunk, c->T - t0);
-                if (t0 > 0) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+                if (t0 > 0) HIPCHK(c, ev_record(c, 1));
                 s = fp64 ? launch_oct<double>(c, nt, t0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
                                               c->d_oaw.as<double>(), c->d_win.p, c->oct_groups,
                                               c->d_olen64.as<double>())
                          : launch_oct<float>(c, nt, t0, true, nullptr, c->d_osteps, c->d_otrees, c->oct_trees,
                                              c->d_oaw.as<double>(), c->d_win.p, c->oct_groups, nullptr);
                 if (s) return s;
-                HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+                HIPCHK(c, ev_record(c, 4));
                 if (fp64) {
                     GatherOctArgs<double> g{c->nc, nt, t0, c->T, c->d_ocell_off.as<long long>(),
                                             c->d_ocell_steps.as<unsigned>(), c->d_oE.as<double2>(),
@@ -1258,11 +1591,11 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
                                            c->oct_estride, c->d_acc.as<double2>()};
                     HIPCHK(c, launch_gather_oct(c->stream, g));
                 }
-                HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
-                HIPCHK(c, hipEventSynchronize(c->ev[5]));
+                HIPCHK(c, ev_record(c, 5));
+                HIPCHK(c, ev_sync(c, 5));
                 float a = 0, b = 0;
-                HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[4]));
-                HIPCHK(c, hipEventElapsedTime(&b, c->ev[4], c->ev[5]));
+                HIPCHK(c, ev_elapsed(c, &a, 1, 4));
+                HIPCHK(c, ev_elapsed(c, &b, 4, 5));
                 t_march += a;
                 t_gather += b;
                 c->ctr.march_launches += 1;
@@ -1271,12 +1604,12 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
             s = fp64 ? launch_march<double>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0)
                      : launch_march<float>(c, c->T, 0, true, nullptr, false, nullptr, nullptr, 0, nullptr, 0);
             if (s) return s;
-            HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
-            HIPCHK(c, hipEventSynchronize(c->ev[4]));
-            HIPCHK(c, hipEventElapsedTime(&t_march, c->ev[1], c->ev[4]));
+            HIPCHK(c, ev_record(c, 4));
+            HIPCHK(c, ev_sync(c, 4));
+            HIPCHK(c, ev_elapsed(c, &t_march, 1, 4));
             c->ctr.march_launches += 1;
         }
-        HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+        HIPCHK(c, ev_record(c, 2));
         SEArgs a{};
         a.nc = (int)nc;
         a.L = c->L;
@@ -1292,13 +1625,13 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
         a.delta_bits = c->d_flags.as<unsigned long long>();
         a.bad = reinterpret_cast<unsigned int*>(c->d_flags.as<char>() + 8);
         HIPCHK(c, launch_se(c->stream, a));
-        HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+        HIPCHK(c, ev_record(c, 3));
         unsigned long long flags[2] = {0, 0};
         HIPCHK(c, hipMemcpyAsync(flags, c->d_flags.p, 16, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         float t01 = 0, t23 = 0;
-        HIPCHK(c, hipEventElapsedTime(&t01, c->ev[0], c->ev[1]));
-        HIPCHK(c, hipEventElapsedTime(&t23, c->ev[2], c->ev[3]));
+        HIPCHK(c, ev_elapsed(c, &t01, 0, 1));
+        HIPCHK(c, ev_elapsed(c, &t23, 2, 3));
         c->ctr.prepare_ms += t01;
         c->ctr.march_ms += t_march;
         c->ctr.accumulate_ms += t_gather;
@@ -1319,6 +1652,22 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
         }
         std::memcpy(&delta, &flags[0], sizeof(double));
         std::swap(c->d_x.p, c->d_xnew.p);
+        if (c->n_sub > 0) {
+            double sub_steps = 0.0;
+            HIPCHK(c, ev_record(c, 0));
+            s = fp64 ? core_subiterations<double>(c, &sub_steps) : core_subiterations<float>(c, &sub_steps);
+            if (s) {
+                if (iters_done) *iters_done = it;
+                return s;
+            }
+            HIPCHK(c, ev_record(c, 1));
+            HIPCHK(c, ev_sync(c, 1));
+            float t_sub = 0;
+            HIPCHK(c, ev_elapsed(c, &t_sub, 0, 1));
+            c->ctr.march_ms += t_sub;
+            c->ctr.ray_steps += sub_steps * c->T;
+            c->ctr.channel_updates += sub_steps * c->T * c->nch;
+        }
         if (tol > 0 && delta < tol) {
             converged = true;
             ++it;
@@ -1451,7 +1800,7 @@ miloc_status miloc_get_spectra(miloc_ctx* c, int trans, int n_los, const double*
             HIPCHK(c, hipMemcpy(extra2.p, st.data(), st.size() * sizeof(st[0]), hipMemcpyHostToDevice));
         } else {
             std::vector<StepRec<float>> st(len.size());
-            for (size_t i = 0; i < len.size(); ++i) { st[i].len = (float)len[i]; st[i].flags = fl[i]; }
+            for (size_t i = 0; i < len.size(); ++i) { st[i].len = step_len_rec<float>(len[i]); st[i].flags = fl[i]; }
             HIPCHK(c, extra2.ensure(st.size() * sizeof(st[0])));
             HIPCHK(c, hipMemcpy(extra2.p, st.data(), st.size() * sizeof(st[0]), hipMemcpyHostToDevice));
         }
