@@ -437,6 +437,35 @@ miloc_status miloc_server_cancel(miloc_server* server, uint64_t ticket);
 
 miloc_status miloc_server_get_stats(miloc_server* server, miloc_server_stats* out);
 
+/* ------------------------------------------------- allocation-free 1D solve */
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc or hipFree: tight request loops, harnesses that forbid device
+ * allocation).  Solves one 1D model exactly as
+ *   miloc_create(hip_device, hip_stream) + miloc_load_molecule(mol) +
+ *   miloc_load_model_1d(model) + miloc_set_spectral(n_channels, v_min_cms,
+ *   dv_cms) + miloc_set_background(T_bg_K) + miloc_run(max_iter, tol, ALI)
+ *   + miloc_get_populations(x_out) + miloc_destroy
+ * would (FP32 march, FP64 solves; the same kernels), but every device buffer
+ * lives in a static device array of MILOC_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends; the call
+ * allocates no device memory, creates no stream or event and keeps no
+ * counters.  Inputs are host buffers, copied in; x_out[n_shells*n_levels]
+ * (host, caller-allocated) receives the populations, iters_done and
+ * last_delta (either may be NULL) the iteration count and the last maximum
+ * relative change.  Work runs on hip_stream (NULL: the null stream) and is
+ * complete when the call returns.
+ * Errors: as the calls above (MILOC_ENOTCONV still writes the results);
+ * MILOC_ENOMEM when the model needs more device memory than the scratch
+ * holds (roughly: 8 bytes per ray step, with n_rays*n_shells steps at most,
+ * plus 40 bytes per shell and level or transition; about 2500 shells with as
+ * many rays).  Calls that overlap on one GPU (from several threads) share
+ * the one array and race: serialise them. */
+#define MILOC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+miloc_status miloc_solve_1d_noalloc(int hip_device, void* hip_stream, const miloc_molecule* mol,
+                                    const miloc_model1d* model, int n_channels, double v_min_cms, double dv_cms,
+                                    double T_bg_K, int max_iter, double tol, int* iters_done, double* last_delta,
+                                    double* x_out);
+
 #ifdef __cplusplus
 }
 #endif

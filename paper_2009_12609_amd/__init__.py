@@ -130,6 +130,10 @@ SIGNATURES = {
     "miloc_server_take": (ctypes.c_int, [_vp, ctypes.c_uint64, _dp, _dp, ctypes.POINTER(ResultInfo)]),
     "miloc_server_cancel": (ctypes.c_int, [_vp, ctypes.c_uint64]),
     "miloc_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
+    "miloc_solve_1d_noalloc": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.POINTER(MolStruct),
+                                              ctypes.POINTER(Model1DStruct), ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                              _ip, _dp, _dp]),
 }
 
 _lib = None
@@ -253,6 +257,27 @@ def octree_schedule(model, dirs, plain=False, lattice=False):
     if rc != OK:
         raise MilocError(rc, "miloc_octree_schedule failed")
     return steps, trees, md.value
+
+
+def solve_1d_noalloc(mol, model, spec, T_bg: float = 2.73, max_iter: int = 100, tol: float = 0.0,
+                     device: int = 0, stream: Optional[int] = None):
+    """miloc_solve_1d_noalloc: one 1D ALI solve whose device memory is the
+    library's static scratch (no device allocation).  Returns (x [n_shells,
+    n_levels], iterations, last_delta, status) with status MILOC_OK or
+    MILOC_ENOTCONV; other statuses raise."""
+    L = load_library()
+    keep = []
+    ms = _mol_struct(mol, keep)
+    m1 = _model1d_struct(model, keep)
+    x = np.empty((int(np.asarray(model.r_out).shape[0]), int(np.asarray(mol.E_K).shape[0])))
+    it, d = ctypes.c_int(0), ctypes.c_double(0.0)
+    rc = L.miloc_solve_1d_noalloc(int(device), _vp(stream) if stream else None, ctypes.byref(ms), ctypes.byref(m1),
+                                  int(spec.n_channels), float(spec.v_min), float(spec.dv), float(T_bg),
+                                  int(max_iter), float(tol), ctypes.byref(it), ctypes.byref(d),
+                                  _ptr(x, ctypes.c_double))
+    if rc not in (OK, ENOTCONV):
+        raise MilocError(rc, "miloc_solve_1d_noalloc failed")
+    return x, it.value, d.value, rc
 
 
 class Server:

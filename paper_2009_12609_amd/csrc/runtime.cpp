@@ -1884,3 +1884,92 @@ miloc_status miloc_reset_counters(miloc_ctx* c)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- allocation-free solve
+// Device memory of miloc_solve_1d_noalloc: one copy of this array per GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to the device: the address each device gives for it is looked
+// up once per device (hipGetSymbolAddress, with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[MILOC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The scratch array's device address on the current device `dev`.
+hipError_t scratch_address(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Installs a ScratchCarve on the calling thread for one call.
+struct CarveScope {
+    explicit CarveScope(ScratchCarve* sc) { tls_carve = sc; }
+    ~CarveScope() { tls_carve = nullptr; }
+};
+
+}  // namespace
+
+extern "C" {
+
+miloc_status miloc_solve_1d_noalloc(int hip_device, void* hip_stream, const miloc_molecule* mol,
+                                    const miloc_model1d* model, int n_channels, double v_min_cms, double dv_cms,
+                                    double T_bg_K, int max_iter, double tol, int* iters_done, double* last_delta,
+                                    double* x_out)
+{
+    if (!mol || !model || !x_out) return MILOC_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MILOC_EDEVICE;
+    if (hip_device < 0 || hip_device >= n) return MILOC_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return MILOC_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MILOC_EDEVICE;
+    if (hipSetDevice(hip_device) != hipSuccess) return MILOC_EDEVICE;
+    void* base = nullptr;
+    if (scratch_address(hip_device, &base) != hipSuccess) return MILOC_EDEVICE;
+    ScratchCarve carve;
+    carve.base = static_cast<char*>(base);
+    carve.size = MILOC_NOALLOC_SCRATCH_BYTES;
+    miloc_status s;
+    int it = 0;
+    double d = 0.0;
+    {
+        CarveScope scope(&carve);
+        // a context of this call only: every device buffer carved from the
+        // scratch, the caller's stream (NULL: the null stream), no events
+        miloc_ctx c;
+        c.device = hip_device;
+        c.stream = reinterpret_cast<hipStream_t>(hip_stream);
+        s = miloc_load_molecule(&c, mol);
+        if (s == MILOC_OK) s = miloc_load_model_1d(&c, model);
+        if (s == MILOC_OK) s = miloc_set_spectral(&c, n_channels, v_min_cms, dv_cms);
+        if (s == MILOC_OK) s = miloc_set_background(&c, T_bg_K);
+        if (s == MILOC_OK) s = miloc_run(&c, max_iter, tol, 1, &it, &d);
+        if (s == MILOC_OK || s == MILOC_ENOTCONV) {
+            const miloc_status g = miloc_get_populations(&c, x_out);
+            if (g != MILOC_OK) s = g;
+        }
+        // nothing of this call may still run on the scratch when it returns
+        (void)hipStreamSynchronize(c.stream);
+    }
+    if (carve.overflow) return MILOC_ENOMEM;
+    if (s == MILOC_OK || s == MILOC_ENOTCONV) {
+        if (iters_done) *iters_done = it;
+        if (last_delta) *last_delta = d;
+    }
+    return s;
+}
+
+}  // extern "C"
