@@ -334,6 +334,37 @@ def subiter_bench(n_sub=3, tau_min=0.1, tol=1e-6, max_iter=500):
     return out
 
 
+def batching_bench(steps=5):
+    """1D march layouts on the 1000-shell Plummer cloud (10-level rotor, 256
+    channels, FP32): every (ray, transition) pair on its own, and all
+    transitions of a ray in one pass sharing its steps and line profile."""
+    import paper_2009_12609_amd as miloc
+    import synth
+
+    w = synth.workload_1d_plummer(n_shells=1000)
+    out = {"workload": w.name, "steps": steps}
+    for name, on in (("per_transition", False), ("all_transitions", True)):
+        ctx = miloc.Context(0)
+        ctx.load_molecule(w.mol)
+        ctx.load_model_1d(w.model)
+        ctx.set_spectral(w.spec.n_channels, w.spec.v_min, w.spec.dv)
+        ctx.set_background(w.T_bg)
+        ctx.set_transition_batching(on)
+        ctx.run(1)
+        ctx.init_lte()
+        ctx.reset_counters()
+        t0 = time.perf_counter()
+        ctx.run(steps)
+        el = time.perf_counter() - t0
+        cnt = ctx.counters()
+        ctx.close()
+        out[name] = {"ms_per_iteration": el * 1e3 / steps, "march_ms_per_iteration": cnt["march_ms"] / steps,
+                     "march_updates_per_s": cnt["channel_updates"] / (cnt["march_ms"] * 1e-3)}
+    out["march_speedup"] = (out["per_transition"]["march_ms_per_iteration"] /
+                            out["all_transitions"]["march_ms_per_iteration"])
+    return out
+
+
 def _pct(a, q):
     import numpy as np
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
@@ -455,6 +486,8 @@ def main():
     ap.add_argument("--subiter", type=int, default=3, metavar="N_SUB",
                     help="thick 1000-shell cloud to 1e-6 with and without N_SUB core sub-iterations "
                          "('subiterations' object; 0 = skip)")
+    ap.add_argument("--batching", type=int, default=5, metavar="STEPS",
+                    help="1000-shell cloud, STEPS iterations per 1D march layout ('batching' object; 0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -560,6 +593,8 @@ def main():
         out["lattice"] = lattice_bench(args.lattice)
     if args.subiter > 0:
         out["subiterations"] = subiter_bench(args.subiter)
+    if args.batching > 0:
+        out["batching"] = batching_bench(args.batching)
     if args.serve > 0:
         out["serving"] = serve_bench(args.serve)
     if not args.no_cpu_baseline and N == 128:

@@ -264,6 +264,18 @@ miloc_status miloc_set_directions_healpix(miloc_ctx* ctx, int nside);
  * stands for a solid angle 4 pi / n_dir. */
 miloc_status miloc_set_directions(miloc_ctx* ctx, int n_dir, const double* dirs);
 
+/* How a 1D model's iterations march the transitions (Sect. 4 of the paper
+ * proposes processing all transitions at the same time instead of repeating
+ * the ray tracing per transition): on = 0 (default) one launch covers every
+ * (ray, transition) pair independently; on = 1 one wavefront marches one ray
+ * for four transitions at once, sharing the ray's steps, the shells' data and
+ * the line profile of each step (the same in velocity units for every
+ * transition), with the absorbed counts summed by FP64 device atomics.  The
+ * results are the same to FP32 (FP64) rounding.  Lines of sight, core
+ * sub-iterations and hyperfine multiplets march per transition.  Ignored
+ * for 3D models.  MILOC_EINVAL unless on is 0 or 1. */
+miloc_status miloc_set_transition_batching(miloc_ctx* ctx, int on);
+
 /* Arithmetic of the ray march: MILOC_MARCH_FP32 (default; FP32 intensities,
  * FP64 accumulation) or MILOC_MARCH_FP64 (everything in FP64). */
 typedef enum { MILOC_MARCH_FP32 = 0, MILOC_MARCH_FP64 = 1 } miloc_march_precision;

@@ -106,6 +106,7 @@ SIGNATURES = {
     "miloc_set_directions": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "miloc_set_march_precision": (ctypes.c_int, [_vp, ctypes.c_int]),
     "miloc_set_subiterations": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
+    "miloc_set_transition_batching": (ctypes.c_int, [_vp, ctypes.c_int]),
     "miloc_init_lte": (ctypes.c_int, [_vp]),
     "miloc_set_populations": (ctypes.c_int, [_vp, _dp]),
     "miloc_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _dp]),
@@ -445,6 +446,9 @@ class Context:
 
     def set_subiterations(self, n_sub: int, tau_min: float = 0.1):
         self._check(self._lib.miloc_set_subiterations(self._h, int(n_sub), float(tau_min)))
+
+    def set_transition_batching(self, on: bool):
+        self._check(self._lib.miloc_set_transition_batching(self._h, 1 if on else 0))
 
     def set_march_precision(self, fp64: bool):
         self._check(self._lib.miloc_set_march_precision(self._h, MARCH_FP64 if fp64 else MARCH_FP32))

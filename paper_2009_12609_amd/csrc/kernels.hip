@@ -1410,6 +1410,125 @@ __global__ __launch_bounds__(256) void march1d_kernel(March1DArgs<T> p)
     march1d_block<T, LANES, ACCUM, false, HF>(p, blockIdx.x * rpb, p.trans_offset + blockIdx.y, smem_raw);
 }
 
+// All transitions of a ray in one pass (the paper's Sect. 4 names this
+// alternative to repeating the ray tracing per transition): one wavefront
+// marches one 1D ray for kTbGroups transitions at once, a group of 16 lanes
+// per transition.  The step records, the shell's data and the channel window
+// are the wavefront's, and the line profile of each step (the same for every
+// transition in velocity units) is evaluated once by the whole wavefront into
+// LDS and read by every group.  The per-step sums of each transition go to
+// the FP64 sums with device atomics.
+namespace {
+constexpr int kTbGroups = 4;
+constexpr int kTbLanes = 16;
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(256) void march1d_tb_kernel(March1DArgs<T> p)
+{
+    using T2 = typename V2<T>::type;
+    extern __shared__ unsigned char smem_raw[];
+    const int wid = threadIdx.x >> 6;                 // wavefront of the block
+    const int wl = threadIdx.x & 63;                  // lane in the wavefront
+    const int g = wl / kTbLanes;                      // group = transition slot
+    const int lane = wl % kTbLanes;
+    const int j = blockIdx.x * (blockDim.x >> 6) + wid;
+    const int t = p.trans_offset + blockIdx.y * kTbGroups + g;
+    const bool t_ok = t < p.trans_offset + p.ntr;
+    const int tt = t_ok ? t : p.trans_offset;
+    const int stride = p.nch + kVecTailPadWords;
+    T* __restrict__ base = reinterpret_cast<T*>(smem_raw) + (size_t)wid * (kTbGroups + 1) * stride;
+    T* __restrict__ I = base + (size_t)g * stride;
+    T* __restrict__ prof = base + (size_t)kTbGroups * stride;
+    if (j >= p.nrays) return;                         // the whole wavefront
+    const int n = p.n;
+    const int ts = p.ntr_total;
+    const double a = p.area[j];
+    const int kmin = p.kmin[j];
+    const int nin = n - 1 - kmin;
+    const int nsteps = 2 * nin + 2;
+    const T2* __restrict__ rec = p.steps + p.ray_off[j];
+    const T Ibg = p.Ibg[tt];
+    for (int c = lane; c < p.nch; c += kTbLanes) I[c] = Ibg;
+    auto shell_of = [&](int s) {
+        return s < nin ? n - 1 - s : (s <= nin + 1 ? kmin : kmin + (s - nin - 1));
+    };
+    // records arrive 64 at a time, one per lane of the wavefront
+    T2 mine = rec[wl < nsteps ? wl : 0];
+    T2 r_n;
+    r_n.x = __shfl(mine.x, 0, 64);
+    r_n.y = __shfl(mine.y, 0, 64);
+    int k_n = shell_of(0);
+    T2 sv_n = p.shellv[k_n];
+    T2 kev_n = p.ke[(size_t)k_n * ts + tt];
+    for (int s = 0; s < nsteps; ++s) {
+        const T2 r = r_n;
+        const int k = k_n;
+        const T2 sv = sv_n;
+        const T2 kev = kev_n;
+        if (s + 1 < nsteps) {
+            const int q = (s + 1) & 63;
+            if (q == 0) mine = rec[s + 1 + wl < nsteps ? s + 1 + wl : s + 1];
+            r_n.x = __shfl(mine.x, q, 64);
+            r_n.y = __shfl(mine.y, q, 64);
+            k_n = shell_of(s + 1);
+            sv_n = p.shellv[k_n];
+            kev_n = p.ke[(size_t)k_n * ts + tt];
+        }
+        int clo, chi;
+        T frac;
+        window<T>((double)r.y, p.chalf, p.Kw, sv.y, p.nch, clo, chi, frac);
+        const int nwin = chi - clo + 1;
+        const T ibs = sv.y;
+        const T x0 = frac * ibs;
+        // the profile of the step, once for all transitions
+        for (int jj = wl; jj < nwin; jj += 64) {
+            const T xs = (T)jj * ibs + x0;
+            prof[jj] = fast_exp2(-xs * xs);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const T tl = r.x;
+        const T kl = t_ok ? kev.x * tl : (T)0;
+        const T el = t_ok ? kev.y * tl : (T)0;
+        T sj = 0, sl = 0;
+        T* __restrict__ row = I + clo;
+        const bool thin = __all(kl < (T)1e-3 && kl > (T)-1e-3);
+        if (!thin && kl < (T)kMaserTauMin) *p.maser = 1u;
+        if (thin) {
+            for (int jj = lane; jj < nwin; jj += kTbLanes) {
+                const T ec = prof[jj];
+                const T tau = kl * ec;
+                const T omb = std::is_same<T, float>::value ? tau * ((T)0.5 - tau * (T)(1.0 / 6.0)) : omb_any(tau);
+                const T Iin = row[jj];
+                const T u = ec - ec * omb;
+                sj += Iin * u;
+                sl += ec * omb;
+                row[jj] = Iin + u * (el - kl * Iin);
+            }
+        } else {
+            for (int jj = lane; jj < nwin; jj += kTbLanes) {
+                const T ec = prof[jj];
+                const T omb = omb_any(kl * ec);
+                const T Iin = row[jj];
+                const T u = ec - ec * omb;
+                sj += Iin * u;
+                sl += ec * omb;
+                row[jj] = Iin + u * (el - kl * Iin);
+            }
+        }
+        sj = group_sum<kTbLanes>(sj);
+        sl = group_sum<kTbLanes>(sl);
+        keep_here(sj);
+        keep_here(sl);
+        if (lane == kTbLanes - 1 && t_ok) {
+            const double wgt = a * (double)tl;
+            unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].x, wgt * (double)sj);
+            unsafeAtomicAdd(&p.acc[(size_t)k * ts + t].y, wgt * (double)sl);
+        }
+        __builtin_amdgcn_wave_barrier();              // prof and the vectors are rewritten next step
+    }
+}
+
 // ---------------------------------------------------------------- SE solve
 // One thread per cell.  The (L+1) x L augmented matrix lives in LDS with the
 // thread index fastest, M[(row*(L+1) + col)*bs + tid].
@@ -1946,6 +2065,30 @@ hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes,
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes, bool accum)
 {
     return dispatch1d<double>(s, a, lanes, accum);
+}
+
+template <typename T>
+hipError_t do_march1d_tb(hipStream_t s, const March1DArgs<T>& a)
+{
+    constexpr int kWaves = 4;                          // rays per block
+    const size_t shm = (size_t)kWaves * (kTbGroups + 1) * (a.nch + kVecTailPadWords) * sizeof(T);
+    if (shm > 163840) return hipErrorInvalidValue;
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)march1d_tb_kernel<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((a.nrays + kWaves - 1) / kWaves, (a.ntr + kTbGroups - 1) / kTbGroups);
+    hipLaunchKernelGGL(march1d_tb_kernel<T>, grid, dim3(64 * kWaves), shm, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_march1d_all_transitions(hipStream_t s, const March1DArgs<float>& a)
+{
+    return do_march1d_tb<float>(s, a);
+}
+hipError_t launch_march1d_all_transitions(hipStream_t s, const March1DArgs<double>& a)
+{
+    return do_march1d_tb<double>(s, a);
 }
 
 template <typename T>

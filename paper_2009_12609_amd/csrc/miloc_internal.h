@@ -297,6 +297,11 @@ hipError_t launch_shell_weights(hipStream_t s, int n, const double* R, int nrays
 hipError_t launch_ray_steps(hipStream_t s, int n, const double* R, int nrays, const double* b, const int* kmin,
                             const long long* off, const double* vr_dv, void* out, bool fp64);
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<float>& a, int lanes, bool accum);
+// All transitions of each ray in one pass (a wavefront per ray, four
+// transitions per wavefront sharing the step's profile), with accumulation
+// into acc by FP64 atomics; whole rays from I_bg only (seg = kSegWhole).
+hipError_t launch_march1d_all_transitions(hipStream_t s, const March1DArgs<float>& a);
+hipError_t launch_march1d_all_transitions(hipStream_t s, const March1DArgs<double>& a);
 hipError_t launch_march1d(hipStream_t s, const March1DArgs<double>& a, int lanes, bool accum);
 hipError_t launch_se(hipStream_t s, const SEArgs& a);
 hipError_t launch_gather3d(hipStream_t s, const Gather3DArgs<float>& a);

@@ -158,6 +158,7 @@ struct miloc_ctx {
     int n_sub = 0;
     double sub_tau_min = 0.0;
     double sums_budget = 0.0;            // device bytes left for the 3D per-step sums (check_fits)
+    int tbatch = 0;                      // 1D: all transitions of a ray in one pass
     int sub_last_k = -1;                 // core extent of the last iteration (-1: none)
     std::vector<int> kmin_host;          // innermost shell of each ray (1D)
     DevBuf d_ient, d_sflags;             // core entry intensities; flags of the core solves
@@ -1054,8 +1055,12 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
         if (bimp_override) a.area = bimp_override;
         a.Ibg = accum ? c->d_Ibg.as<TT>() : c->d_zero.as<TT>();
         a.Iout = Iout;
-        // lines of sight run alone: 64 lanes shorten each step's channel loop
-        e = launch_march1d(c->stream, a, accum ? c->lanes : 64, accum);
+        if (accum && c->tbatch && !a.hf) {
+            e = launch_march1d_all_transitions(c->stream, a);
+        } else {
+            // lines of sight run alone: 64 lanes shorten each step's channel loop
+            e = launch_march1d(c->stream, a, accum ? c->lanes : 64, accum);
+        }
     }
     HIPCHK(c, e);
     return MILOC_OK;
@@ -1461,6 +1466,15 @@ miloc_status miloc_set_subiterations(miloc_ctx* c, int n_sub, double tau_min)
     if (!std::isfinite(tau_min)) return fail(c, MILOC_EINVAL, "tau_min must be finite");
     c->n_sub = n_sub;
     c->sub_tau_min = tau_min;
+    return MILOC_OK;
+}
+
+miloc_status miloc_set_transition_batching(miloc_ctx* c, int on)
+{
+    if (!c) return MILOC_EINVAL;
+    c->err.clear();
+    if (on != 0 && on != 1) return fail(c, MILOC_EINVAL, "on must be 0 or 1");
+    c->tbatch = on;
     return MILOC_OK;
 }
 
