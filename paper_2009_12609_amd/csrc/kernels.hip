@@ -621,37 +621,49 @@ __global__ __launch_bounds__(256) void march3d_kernel(March3DArgs<T> p)
 
 namespace {
 
-// The lane group's passes over one step's window with the step length folded
-// into the profile, e_c' = e_c len = exp2(log2 len - x^2): then tau = khat e_c',
-// the emission ehat e_c' beta and both sums come out multiplied by the length
-// (otherwise as window_passes_f32).
+// The lane group's passes over one step's window, FP32 single Gaussian,
+// with the step length folded into the profile, e_c' = e_c len =
+// exp2(log2 len - x^2): then tau = khat e_c', and the emission ehat e_c' beta
+// and both sums come out multiplied by the length.  No branch per channel:
+// the first NU channels of every lane are computed whether they lie in the
+// window or not, with the profile of a channel outside it set to 0, which
+// leaves its intensity as it was (I + 0 (ehat - khat I) = I) and adds nothing
+// to the sums.  The channel vector must be followed by at least NU LANES
+// words of its own (finite) padding, so that these writes never reach
+// another ray's vector.
 template <int LANES, int CLS>
-__device__ __forceinline__ void window_passes_folded(float* __restrict__ rl, int lane, int nwin, float xl,
-                                                     float hstep, float x0, float ibs, float l2len, float kh,
-                                                     float eh, float& sj, float& sl)
+__device__ __forceinline__ void window_passes_pred(float* __restrict__ rl, int lane, int nwin, float xl,
+                                                   float hstep, float x0, float ibs, float l2len, float kh,
+                                                   float eh, float& sj, float& sl)
 {
     constexpr int NU = LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4);
-    static_assert(NU * LANES <= kVecTailPadWords, "unconditional reads must stay in the LDS allocation");
     float Iv[NU];
 #pragma unroll
     for (int i = 0; i < NU; ++i) Iv[i] = rl[i * LANES];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
-        if (lane + i * LANES < nwin) {
-            const float xs = fmaf((float)i, hstep, xl);
-            const float ec = fast_exp2(fmaf(-xs, xs, l2len));
-            const float omb = omb_class<CLS>(kh * ec);
-            const float u = fmaf(-ec, omb, ec);
-            sj = fmaf(Iv[i], u, sj);
-            sl = fmaf(ec, omb, sl);
-            rl[i * LANES] = fmaf(u, fmaf(-kh, Iv[i], eh), Iv[i]);
-        }
+        const float xs = fmaf((float)i, hstep, xl);
+        const float e = fast_exp2(fmaf(-xs, xs, l2len));
+        const float ec = lane + i * LANES < nwin ? e : 0.0f;
+        const float omb = omb_class<CLS>(kh * ec);
+        const float u = fmaf(-ec, omb, ec);
+        sj = fmaf(Iv[i], u, sj);
+        sl = fmaf(ec, omb, sl);
+        rl[i * LANES] = fmaf(u, fmaf(-kh, Iv[i], eh), Iv[i]);
     }
     for (int j = lane + NU * LANES; j < nwin; j += LANES) {
         const float xs = fmaf((float)j, ibs, x0);
         const float ec = fast_exp2(fmaf(-xs, xs, l2len));
         channel_update(rl + (j - lane), ec, omb_class<CLS>(kh * ec), kh, eh, sj, sl);
     }
+}
+
+// Words of padding after each channel vector of march3d_f32_kernel: the
+// predicated passes' reach (NU LANES), rounded so that the vectors of
+// consecutive rays start 8 banks apart.
+__host__ __device__ constexpr int f32_vec_gap(int lanes)
+{
+    return (lanes >= 64 ? 1 : (lanes >= 32 ? 2 : 4)) * lanes + 8;
 }
 
 // One transverse move with periodic re-entry (as move_transverse), the
@@ -681,11 +693,15 @@ __device__ __forceinline__ int in_vgpr(int v)
 // outputs as march3d_kernel<float, LANES, ACCUM, false>), arranged for
 // instruction count:
 //  * step records carry log2 of the length, absorbed by the profile exponent
-//    (window_passes_folded); the optical-depth class of a step is voted on
+//    (window_passes_pred); the optical-depth class of a step is voted on
 //    |khat| times the direction's longest step, a bound on |tau|;
-//  * the ray weight |d_m| multiplies the queued sums when they are written;
+//  * the channel passes are predicated rather than branched per channel;
+//  * the ray weight |d_m| multiplies the queued sums when they are written,
+//    and 8- and 16-lane groups queue them in registers;
 //  * the cell data of the coming steps are loaded into a ring of register
-//    sets, several steps ahead, so no prefetched value is copied;
+//    sets, several steps ahead, so no prefetched value is copied, and every
+//    turn of the ring issues the same loads, so each step waits for its own
+//    data only;
 //  * the transverse wrap-around corrections sit in vector registers.
 template <int LANES, bool ACCUM>
 __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
@@ -730,20 +746,37 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     const float kthin0 = (float)(1.0e-3 / D.maxlen);     // |khat| below: every |tau| < 1e-3
     const float kthin1 = (float)(1.0e-2 / D.maxlen);
     const int ns = D.nsteps;
-    for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+    // the padding after the vector is written too: the predicated passes
+    // read it and must find finite values there
+    for (int c = lane; c < p.ich; c += LANES) I[c] = Ibg;
 
+    // Per-step sums {len sum_c e_c I_c beta_c, len sum_c e_c (1 - beta_c)}
+    // wait in registers (lane k of a group holds the k-th step since the
+    // last write; 8- and 16-lane group sums end in every lane of the group)
+    // or, for wider groups, in an LDS queue; every LANES steps they are
+    // written to E[step][ray] with the ray weight, rays of one step side by
+    // side.
+    constexpr bool kRegQueue = LANES <= 16;
     float2* __restrict__ qw = reinterpret_cast<float2*>(smem_raw + p.queue_lds_offset) + (size_t)(rib - rib % rpw) * LANES;
     const int wl = threadIdx.x & 63;
     const int q_ray = wl % rpw, q_step = wl / rpw;
     int qn = 0, qs0 = 0;
+    float qx = 0.0f, qy = 0.0f;
 
-    // the cell data of step s are loaded while step s - 1 is computed
+    // The cell data of step s are loaded while earlier steps are computed.
+    // Past the last step the ray stays in its last cell and that cell's data
+    // are loaded again (never used): every fetch issues the same two loads,
+    // so the waits before a step can count the loads issued after its own
+    // instead of waiting for all of them.
     auto fetch = [&](int s, float& l2len, bool& restart, float4& wv, float2& kv) {
-        const StepRec<float> rec = sst[s];
+        const bool live = s < ns;
+        const StepRec<float> rec = sst[live ? s : ns - 1];
         restart = false;
-        if (rec.flags & 1) idx += D.stride_m;
-        if (rec.flags & 2) move_wrap(ca, idx, D.sa, wrap_a, da, dwa, N, restart);
-        if (rec.flags & 4) move_wrap(cb, idx, D.sb, wrap_b, db, dwb, N, restart);
+        if (live) {
+            if (rec.flags & 1) idx += D.stride_m;
+            if (rec.flags & 2) move_wrap(ca, idx, D.sa, wrap_a, da, dwa, N, restart);
+            if (rec.flags & 4) move_wrap(cb, idx, D.sb, wrap_b, db, dwb, N, restart);
+        }
         l2len = rec.len;
         wv = win[(unsigned)idx];
         kv = ke[(size_t)(unsigned)idx * (unsigned)ts];
@@ -761,53 +794,79 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
         const float akh = fabsf(kv.x);
         float sj = 0.0f, sl = 0.0f;
         if (__all(akh < kthin0)) {
-            window_passes_folded<LANES, 0>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 0>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else if (__all(akh < kthin1)) {
-            window_passes_folded<LANES, 1>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 1>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else {
             if (kv.x * fast_exp2(l2len) < (float)kMaserTauMin) *p.maser = 1u;
-            window_passes_folded<LANES, 2>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 2>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         }
         if (ACCUM) {
-            float2 v;
-            v.x = group_sum<LANES>(sj);
-            v.y = group_sum<LANES>(sl);
-            keep_here(v.x);
-            keep_here(v.y);
-            if (lane == LANES - 1) qw[qn * rpw + (rib % rpw)] = v;
-            ++qn;
-            if (qn == LANES || s == ns - 1) {
-                const int rq = r_first + q_ray;
-                if (q_step < qn && rq < p.rays_per_dir) {
-                    float2 o = qw[q_step * rpw + q_ray];
-                    o.x *= aw;
-                    o.y *= aw;
-                    E[(size_t)(qs0 + q_step) * p.rays_per_dir + rq] = o;
+            const float tx = group_sum<LANES>(sj);
+            const float ty = group_sum<LANES>(sl);
+            if constexpr (kRegQueue) {
+                const bool mine = lane == qn;
+                qx = mine ? tx : qx;
+                qy = mine ? ty : qy;
+                ++qn;
+                if (qn == LANES || s == ns - 1) {
+                    if (lane < qn && ray_ok)
+                        E[(size_t)(qs0 + lane) * p.rays_per_dir + r] = make_float2(qx * aw, qy * aw);
+                    qs0 += qn;
+                    qn = 0;
                 }
-                qs0 += qn;
-                qn = 0;
+            } else {
+                float2 v;
+                v.x = tx;
+                v.y = ty;
+                keep_here(v.x);
+                keep_here(v.y);
+                if (lane == LANES - 1) qw[qn * rpw + (rib % rpw)] = v;
+                ++qn;
+                if (qn == LANES || s == ns - 1) {
+                    const int rq = r_first + q_ray;
+                    if (q_step < qn && rq < p.rays_per_dir) {
+                        float2 o = qw[q_step * rpw + q_ray];
+                        o.x *= aw;
+                        o.y *= aw;
+                        E[(size_t)(qs0 + q_step) * p.rays_per_dir + rq] = o;
+                    }
+                    qs0 += qn;
+                    qn = 0;
+                }
             }
         }
     };
 
     // a ring of kPrefetch register sets: set i holds step s0 + i; once that
     // step is done the set takes step s0 + i + kPrefetch, so each step's cell
-    // loads are issued kPrefetch - 1 steps of work before they are used
+    // loads are issued kPrefetch - 1 steps of work before they are used.
+    // Whole turns of the ring run without conditions; the last ns mod
+    // kPrefetch steps take the sets in order, shifting the ring.
     constexpr int kPrefetch = 4;
     float l2r[kPrefetch];
     bool rsr[kPrefetch];
     float4 wvr[kPrefetch];
     float2 kvr[kPrefetch];
+    if (ns > 0) {
 #pragma unroll
-    for (int i = 0; i < kPrefetch; ++i)
-        if (i < ns) fetch(i, l2r[i], rsr[i], wvr[i], kvr[i]);
-    for (int s0 = 0; s0 < ns; s0 += kPrefetch) {
+        for (int i = 0; i < kPrefetch; ++i) fetch(i, l2r[i], rsr[i], wvr[i], kvr[i]);
+        int s0 = 0;
+        for (; s0 + kPrefetch <= ns; s0 += kPrefetch) {
 #pragma unroll
-        for (int i = 0; i < kPrefetch; ++i) {
-            const int s = s0 + i;
-            if (s < ns) {
-                step(s, l2r[i], rsr[i], wvr[i], kvr[i]);
-                if (s + kPrefetch < ns) fetch(s + kPrefetch, l2r[i], rsr[i], wvr[i], kvr[i]);
+            for (int i = 0; i < kPrefetch; ++i) {
+                step(s0 + i, l2r[i], rsr[i], wvr[i], kvr[i]);
+                fetch(s0 + i + kPrefetch, l2r[i], rsr[i], wvr[i], kvr[i]);
+            }
+        }
+        for (; s0 < ns; ++s0) {
+            step(s0, l2r[0], rsr[0], wvr[0], kvr[0]);
+#pragma unroll
+            for (int i = 0; i + 1 < kPrefetch; ++i) {
+                l2r[i] = l2r[i + 1];
+                rsr[i] = rsr[i + 1];
+                wvr[i] = wvr[i + 1];
+                kvr[i] = kvr[i + 1];
             }
         }
     }
@@ -1949,9 +2008,11 @@ int rays_per_block(int lanes, int nch)
 template <typename T, int LANES, bool ACCUM, bool HF>
 hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
 {
+    constexpr bool kF32 = std::is_same<T, float>::value && !HF;
     // Channel vectors are padded by 16 words so that the rays of one
-    // wavefront start in different LDS banks.
-    a.ich = a.nch + 16;
+    // wavefront start in different LDS banks; the FP32 single-Gaussian
+    // kernel's predicated passes need their reach after each vector.
+    a.ich = a.nch + (kF32 ? f32_vec_gap(LANES) : 16);
     // whole wavefronts only (the queue flush uses every lane of a wavefront)
     const int rpw = 64 / LANES;
     int rpb = 256 / LANES;
@@ -1960,9 +2021,11 @@ hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
     a.step_lds_bytes = (int)(((size_t)max_steps * sizeof(StepRec<T>) + 15) & ~(size_t)15);
     a.queue_lds_offset = a.step_lds_bytes + (int)((size_t)rpb * a.ich * sizeof(T));
     const dim3 grid(a.blocks_per_dir * a.n_dir * a.ntr);
-    const size_t shm = (size_t)a.queue_lds_offset + (size_t)rpb * LANES * 2 * sizeof(T);
+    // the FP32 kernel with 8 or 16 lanes queues its sums in registers
+    const bool lds_queue = !(kF32 && LANES <= 16);
+    const size_t shm = (size_t)a.queue_lds_offset + (lds_queue ? (size_t)rpb * LANES * 2 * sizeof(T) : 0);
     if (shm > 163840) return hipErrorInvalidValue;
-    if constexpr (std::is_same<T, float>::value && !HF) {
+    if constexpr (kF32) {
         if (shm > 65536) {
             hipError_t e = hipFuncSetAttribute((const void*)march3d_f32_kernel<LANES, ACCUM>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
