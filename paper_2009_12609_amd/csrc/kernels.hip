@@ -626,12 +626,14 @@ namespace {
 // exp2(log2 len - x^2): then tau = khat e_c', and the emission ehat e_c' beta
 // and both sums come out multiplied by the length.  No branch per channel:
 // the first NU channels of every lane are computed whether they lie in the
-// window or not, with the profile of a channel outside it set to 0, which
-// leaves its intensity as it was (I + 0 (ehat - khat I) = I) and adds nothing
-// to the sums.  The channel vector must be followed by at least NU LANES
-// words of its own (finite) padding, so that these writes never reach
-// another ray's vector.
-template <int LANES, int CLS>
+// window or not.  With MASK the profile of a channel outside the window is
+// set to 0, which leaves its intensity as it was (I + 0 (ehat - khat I) = I)
+// and adds nothing to the sums; the channel vector must then be followed by
+// at least NU LANES words of its own (finite) padding, so that these writes
+// never reach another ray's vector.  Without MASK (allowed when the window
+// start plus NU LANES stays inside the band) the extra channels are updated
+// with their true profile values, below e^-25 of the peak past the cut.
+template <int LANES, int CLS, bool MASK>
 __device__ __forceinline__ void window_passes_pred(float* __restrict__ rl, int lane, int nwin, float xl,
                                                    float hstep, float x0, float ibs, float l2len, float kh,
                                                    float eh, float& sj, float& sl)
@@ -642,9 +644,12 @@ __device__ __forceinline__ void window_passes_pred(float* __restrict__ rl, int l
     for (int i = 0; i < NU; ++i) Iv[i] = rl[i * LANES];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
-        const float xs = fmaf((float)i, hstep, xl);
+        const float xs = i == 0 ? xl : fmaf((float)i, hstep, xl);
         const float e = fast_exp2(fmaf(-xs, xs, l2len));
-        const float ec = lane + i * LANES < nwin ? e : 0.0f;
+        // MASK = false: every one of the NU LANES channels lies in the band,
+        // and those past the window's cut take their (negligible) profile
+        // values, as the channels of a march without a cut would
+        const float ec = !MASK || lane + i * LANES < nwin ? e : 0.0f;
         const float omb = omb_class<CLS>(kh * ec);
         const float u = fmaf(-ec, omb, ec);
         sj = fmaf(Iv[i], u, sj);
@@ -745,6 +750,8 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     const float aw = (float)D.aw;
     const float kthin0 = (float)(1.0e-3 / D.maxlen);     // |khat| below: every |tau| < 1e-3
     const float kthin1 = (float)(1.0e-2 / D.maxlen);
+    // channels one lane group's unrolled passes reach from the window start
+    constexpr int kReach = (LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4)) * LANES;
     const int ns = D.nsteps;
     // the padding after the vector is written too: the predicated passes
     // read it and must find finite values there
@@ -768,16 +775,32 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     // are loaded again (never used): every fetch issues the same two loads,
     // so the waits before a step can count the loads issued after its own
     // instead of waiting for all of them.
+    // The step records are read from LDS 64 at a time, one per lane of the
+    // wavefront, and each step takes its own with a lane read (no LDS access
+    // and no wait per step).
+    // (The empty asm uses make the read complete where it is issued rather
+    // than before every later lane read.)
+    int rb = 0;
+    StepRec<float> vrec = sst[wl < ns ? wl : ns - 1];
+    keep_here(vrec.len);
+    keep_here(vrec.flags);
     auto fetch = [&](int s, float& l2len, bool& restart, float4& wv, float2& kv) {
         const bool live = s < ns;
-        const StepRec<float> rec = sst[live ? s : ns - 1];
+        const int si = live ? s : ns - 1;
+        if (si - rb >= 64) {
+            rb += 64;
+            vrec = sst[rb + wl < ns ? rb + wl : ns - 1];
+            keep_here(vrec.len);
+            keep_here(vrec.flags);
+        }
+        const int flags = __builtin_amdgcn_readlane(vrec.flags, si - rb);
         restart = false;
         if (live) {
-            if (rec.flags & 1) idx += D.stride_m;
-            if (rec.flags & 2) move_wrap(ca, idx, D.sa, wrap_a, da, dwa, N, restart);
-            if (rec.flags & 4) move_wrap(cb, idx, D.sb, wrap_b, db, dwb, N, restart);
+            if (flags & 1) idx += D.stride_m;
+            if (flags & 2) move_wrap(ca, idx, D.sa, wrap_a, da, dwa, N, restart);
+            if (flags & 4) move_wrap(cb, idx, D.sb, wrap_b, db, dwb, N, restart);
         }
-        l2len = rec.len;
+        l2len = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vrec.len), si - rb));
         wv = win[(unsigned)idx];
         kv = ke[(size_t)(unsigned)idx * (unsigned)ts];
     };
@@ -792,14 +815,17 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
         const float xl = fmaf((float)lane, wv.y, wv.x);
         const float hstep = (float)LANES * wv.y;
         const float akh = fabsf(kv.x);
+        const bool in_band = clo + kReach <= p.nch;
         float sj = 0.0f, sl = 0.0f;
-        if (__all(akh < kthin0)) {
-            window_passes_pred<LANES, 0>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+        if (__all(akh < kthin0 && in_band)) {
+            window_passes_pred<LANES, 0, false>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+        } else if (__all(akh < kthin0)) {
+            window_passes_pred<LANES, 0, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else if (__all(akh < kthin1)) {
-            window_passes_pred<LANES, 1>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 1, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else {
             if (kv.x * fast_exp2(l2len) < (float)kMaserTauMin) *p.maser = 1u;
-            window_passes_pred<LANES, 2>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 2, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         }
         if (ACCUM) {
             const float tx = group_sum<LANES>(sj);
