@@ -576,7 +576,7 @@ def main():
             "unit": "GB/s",
             "frac": hbm_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": f"march3d_kernel<float,{cnt['march_lanes']},true,false>",
+            "kernel": f"march3d_f32_kernel<{cnt['march_lanes']},true>",
             "bytes_per_step": BYTES_PER_STEP,
             "steps_per_launch": steps_per_launch,
             "march_ms_per_launch": march_ms,
