@@ -752,6 +752,7 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     const float kthin1 = (float)(1.0e-2 / D.maxlen);
     // channels one lane group's unrolled passes reach from the window start
     constexpr int kReach = (LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4)) * LANES;
+    const int nch_reach = p.nch - kReach;
     const int ns = D.nsteps;
     // the padding after the vector is written too: the predicated passes
     // read it and must find finite values there
@@ -815,13 +816,16 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
         const float xl = fmaf((float)lane, wv.y, wv.x);
         const float hstep = (float)LANES * wv.y;
         const float akh = fabsf(kv.x);
-        const bool in_band = clo + kReach <= p.nch;
+        // lane masks of the class tests, combined as masks (the ballot of a
+        // combined condition would be rebuilt from a lane value)
+        const unsigned long long all_lanes = __builtin_amdgcn_read_exec();
+        const unsigned long long in_band = __builtin_amdgcn_ballot_w64(clo <= nch_reach);
         float sj = 0.0f, sl = 0.0f;
-        if (__all(akh < kthin0 && in_band)) {
+        if ((__builtin_amdgcn_ballot_w64(akh < kthin0) & in_band) == all_lanes) {
             window_passes_pred<LANES, 0, false>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
-        } else if (__all(akh < kthin0)) {
+        } else if (__builtin_amdgcn_ballot_w64(akh < kthin0) == all_lanes) {
             window_passes_pred<LANES, 0, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
-        } else if (__all(akh < kthin1)) {
+        } else if (__builtin_amdgcn_ballot_w64(akh < kthin1) == all_lanes) {
             window_passes_pred<LANES, 1, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else {
             if (kv.x * fast_exp2(l2len) < (float)kMaserTauMin) *p.maser = 1u;
