@@ -368,10 +368,13 @@ miloc_status miloc_reset_counters(miloc_ctx* ctx);
 
 /* ----------------------------------------------------------------- serving */
 /* A request loop for 1D models (continuous batching).  Requests are queued by
- * miloc_server_submit (inputs copied before return) and admitted by a worker
- * thread of the server when one of max_slots slots is free and the request's
- * device footprint fits in the remaining part of hbm_budget_bytes (first fit
- * in arrival order).  Each tick advances every resident model by one ALI
+ * miloc_server_submit (inputs copied before return) and admitted by an
+ * admission thread of the server when one of max_slots slots is free and the
+ * request's device footprint fits in the remaining part of hbm_budget_bytes
+ * (first fit in arrival order); admission (host image, upload, device set-up
+ * on a stream of its own) runs while the worker thread's ticks run, and the
+ * model joins at the next tick after it.  Each tick advances every resident
+ * model by one ALI
  * iteration (Sect. 2: march all transitions, FP32 with FP64 accumulation; FP64
  * equilibrium solves; FP64 convergence test per model) through one captured
  * HIP graph; models join and leave between ticks.  A model finishes when its
@@ -401,10 +404,12 @@ typedef struct {
 } miloc_server_stats;
 
 /* hbm_budget_bytes (>= 1 MiB) is allocated up front as the arena of resident
- * models; max_slots in 1..4096.  The worker thread starts immediately. */
+ * models; max_slots in 1..4096.  The worker and admission threads start
+ * immediately. */
 miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int max_slots, miloc_server** out);
 
-/* Stops the worker after the current tick; queued requests are dropped. */
+/* Stops the admission and worker threads (after the current admission round
+ * and tick); queued requests are dropped. */
 void miloc_server_destroy(miloc_server* server);
 
 const char* miloc_server_last_error(const miloc_server* server);

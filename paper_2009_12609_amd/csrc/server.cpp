@@ -1,16 +1,18 @@
 // server.cpp -- 1D request loop (continuous batching) of libmiloc.
 //
 // Requests (a molecule, a shell model, a channel grid, a tolerance) are
-// queued by miloc_server_submit and admitted by a worker thread when a slot is
-// free and their device footprint fits the HBM budget (first fit in arrival
-// order).  Every tick advances every resident model by one ALI iteration
-// (Sect. 2: march all transitions, then solve the statistical equilibrium of
-// every shell): one captured HIP graph of four model-indexed kernels that walk
-// device work lists, so models of different sizes, level counts and channel
-// counts share the same launches and the graph never needs re-capturing.
-// Between ticks the worker reads each model's maximum relative change,
-// retires converged or failed models (final spectra, populations to the
-// host), frees their memory and admits waiting requests.
+// queued by miloc_server_submit and admitted by an admission thread when a
+// slot is free and their device footprint fits the HBM budget (first fit in
+// arrival order): host image, upload and admission kernels on a stream of its
+// own, concurrently with the ticks.  Every tick advances every ready resident
+// model by one ALI iteration (Sect. 2: march all transitions, then solve the
+// statistical equilibrium of every shell): one captured HIP graph of four
+// model-indexed kernels that walk device work lists, so models of different
+// sizes, level counts and channel counts share the same launches and the
+// graph never needs re-capturing.  Between ticks the worker thread reads each
+// model's maximum relative change, retires converged or failed models (final
+// spectra, populations to the host), frees their memory and takes in the
+// admissions that have become ready.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -135,6 +137,7 @@ struct Request {
     // life cycle
     int state = 0;            // 0 queued, 1 active, 2 done, 3 failed, 4 cancelled
     bool cancel_req = false;  // cancel asked while active: the worker retires it
+    bool ready = false;       // admitted on the device: the worker ticks it
     int iters = 0;
     double last_delta = INFINITY;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -245,6 +248,9 @@ struct miloc_server {
     bool stop = false;
     bool device_error = false;
     std::thread worker;
+    std::thread admitter;
+    hipStream_t adm_stream = nullptr;    // admission uploads and kernels
+    bool adm_new = false;                // admissions became ready since the worker looked
     miloc_server_stats stats{};
 };
 
@@ -341,7 +347,7 @@ bool admit_host(Request* r, char* img)
     return true;
 }
 
-// Admission, device part, queued on the server stream: one upload of the
+// Admission, device part, queued on the admission stream: one upload of the
 // host image into the request's arena block, the ray steps and q (from the
 // ray-sampled shell volumes) computed on the device, and the model
 // descriptor.  img must stay untouched until the stream has drained.
@@ -351,15 +357,15 @@ bool admit_device(miloc_server* S, Request* r, const char* img)
     char* base = static_cast<char*>(S->arena_mem) + r->off;
     auto dptr = [&](size_t o) { return static_cast<void*>(base + o); };
     const int n = r->n;
-    if (hipMemcpyAsync(base, img, lay.up_end, hipMemcpyHostToDevice, S->stream) != hipSuccess) {
+    if (hipMemcpyAsync(base, img, lay.up_end, hipMemcpyHostToDevice, S->adm_stream) != hipSuccess) {
         r->error = "upload failed";
         return false;
     }
-    if (launch_ray_steps(S->stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays + 1,
+    if (launch_ray_steps(S->adm_stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays + 1,
                          static_cast<const double*>(dptr(lay.b)), static_cast<const int*>(dptr(lay.kmin)),
                          static_cast<const long long*>(dptr(lay.roff)), static_cast<const double*>(dptr(lay.vrdv)),
                          dptr(lay.steps), false) != hipSuccess ||
-        launch_shell_weights(S->stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays,
+        launch_shell_weights(S->adm_stream, n, static_cast<const double*>(dptr(lay.R)), r->nrays,
                              static_cast<const double*>(dptr(lay.b)), static_cast<const double*>(dptr(lay.area)),
                              static_cast<double*>(dptr(lay.q)), static_cast<const double*>(dptr(lay.bsq)),
                              r->dv) != hipSuccess) {
@@ -415,15 +421,16 @@ bool admit_device(miloc_server* S, Request* r, const char* img)
     return true;
 }
 
-// Upload the model table and the work lists of the current resident set.
-bool rebuild_tables(miloc_server* S)
+// Upload the model table and the work lists of the ready resident set
+// (res: by slot, nullptr where no ready model).
+bool rebuild_tables(miloc_server* S, const std::vector<Request*>& res)
 {
     std::vector<ServeModel> models(S->max_slots);
     std::vector<int4> march, spectra;
     std::vector<int2> cell, se;
     int need = 0;
     for (int sl = 0; sl < S->max_slots; ++sl) {
-        Request* r = S->active[sl];
+        Request* r = res[sl];
         if (!r) continue;
         need = std::max(need, march_lds_need(r->n, r->nch));
         models[sl] = r->desc;
@@ -467,18 +474,24 @@ void take_results(Request* r, const float* sp)
             r->spectra[(size_t)t * r->nch + c] = (double)sp[(size_t)t * r->nch + c] * r->Iscale[t];
 }
 
-void worker_loop(miloc_server* S)
+// Admission thread: takes queued requests in arrival order while a slot,
+// room in the arena and room in the pinned staging area are free, builds
+// their host images (in parallel), uploads them and runs the admission
+// kernels on its own stream, and hands them to the worker once the stream
+// has drained.  It runs while the worker's ticks run, so a request arriving
+// mid-tick is admitted during that tick rather than after it.
+void admit_loop(miloc_server* S)
 {
     (void)hipSetDevice(S->device);
-    bool dirty = true;
-    std::vector<unsigned long long> flags(2 * (size_t)S->max_slots);
     for (;;) {
         std::vector<Request*> to_admit;
         std::vector<size_t> img_off;              // host images in the pinned staging area
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // admission: a free slot and room in the arena, first fit in arrival
-            // order, as many as the staging area holds this round
+            if (S->stop || S->device_error) return;
+            // a free slot and room in the arena, first fit in arrival order,
+            // as many as the staging area holds this round; the slot is held
+            // (not yet ready) while the admission runs
             size_t staged_bytes = 0;
             for (auto it = S->queue.begin(); it != S->queue.end();) {
                 Request* r = *it;
@@ -496,73 +509,109 @@ void worker_loop(miloc_server* S)
                 r->off = off;
                 r->slot = slot;
                 r->state = 1;
+                r->ready = false;
                 r->t_admit = now_s();
                 S->active[slot] = r;
                 S->stats.admitted++;
                 to_admit.push_back(r);
                 it = S->queue.erase(it);
             }
-            int n_active = 0;
-            for (Request* r : S->active) n_active += r ? 1 : 0;
-            S->stats.active = n_active;
-            S->stats.queued = (int64_t)S->queue.size();
-            S->stats.peak_active = std::max<int64_t>(S->stats.peak_active, n_active);
-            if (n_active == 0 && to_admit.empty()) {
-                if (S->stop) return;
+            if (to_admit.empty()) {
                 S->cv.wait_for(lk, std::chrono::milliseconds(20));
                 continue;
             }
         }
-        if (!to_admit.empty()) {
-            // all admissions of this round share two stream synchronisations
-            auto fail_admission = [&](Request* r) {
-                std::lock_guard<std::mutex> lk(S->mu);
-                r->state = 3;
-                r->status = MILOC_EDEVICE;
-                r->t_done = now_s();
-                S->arena.release(r->off, r->bytes);
-                S->active[r->slot] = nullptr;
-                S->stats.failed++;
-            };
-            // host images of all new requests in parallel, then one upload and
-            // two kernels each, and a single synchronisation
-            std::vector<char> host_ok(to_admit.size(), 0);
-            {
-                const size_t nw = std::min<size_t>(to_admit.size(),
-                                                   std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
-                std::vector<std::thread> pool;
-                std::atomic<size_t> next{0};
-                for (size_t w = 0; w < nw; ++w)
-                    pool.emplace_back([&]() {
-                        for (size_t i = next++; i < to_admit.size(); i = next++)
-                            host_ok[i] = admit_host(to_admit[i], S->h_stage + img_off[i]) ? 1 : 0;
-                    });
-                for (auto& t : pool) t.join();
+        auto fail_admission = [&](Request* r) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->active[r->slot] != r) return;
+            r->state = 3;
+            r->status = MILOC_EDEVICE;
+            r->t_done = now_s();
+            S->arena.release(r->off, r->bytes);
+            S->active[r->slot] = nullptr;
+            S->stats.failed++;
+        };
+        // host images of all new requests in parallel, then one upload and
+        // two kernels each, and a single synchronisation of the admission stream
+        std::vector<char> host_ok(to_admit.size(), 0);
+        {
+            const size_t nw = std::min<size_t>(to_admit.size(),
+                                               std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+            std::vector<std::thread> pool;
+            std::atomic<size_t> next{0};
+            for (size_t w = 0; w < nw; ++w)
+                pool.emplace_back([&]() {
+                    for (size_t i = next++; i < to_admit.size(); i = next++)
+                        host_ok[i] = admit_host(to_admit[i], S->h_stage + img_off[i]) ? 1 : 0;
+                });
+            for (auto& t : pool) t.join();
+        }
+        for (size_t i = 0; i < to_admit.size(); ++i) {
+            Request* r = to_admit[i];
+            if (!host_ok[i] || !admit_device(S, r, S->h_stage + img_off[i])) {
+                fail_admission(r);
+                to_admit[i] = nullptr;
             }
-            for (size_t i = 0; i < to_admit.size(); ++i) {
-                Request* r = to_admit[i];
-                if (!host_ok[i] || !admit_device(S, r, S->h_stage + img_off[i])) fail_admission(r);
-            }
-            const bool ok = hipStreamSynchronize(S->stream) == hipSuccess;
+        }
+        const bool ok = hipStreamSynchronize(S->adm_stream) == hipSuccess;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
             if (!ok) {
-                std::lock_guard<std::mutex> lk(S->mu);
                 S->device_error = true;
                 sfail(S, MILOC_EDEVICE, "admission upload failed");
-                for (Request*& r : S->active)
-                    if (r) { r->state = 3; r->status = MILOC_EDEVICE; r->t_done = now_s(); r = nullptr; }
                 S->stop = true;
                 S->cv.notify_all();
                 return;
             }
-            S->cv.notify_all();
-            dirty = true;
+            for (Request* r : to_admit)
+                if (r && S->active[r->slot] == r && r->state == 1) r->ready = true;
+            S->adm_new = true;
+        }
+        S->cv.notify_all();
+    }
+}
+
+// Worker thread: ticks over the ready resident models.
+void worker_loop(miloc_server* S)
+{
+    (void)hipSetDevice(S->device);
+    bool dirty = true;
+    std::vector<unsigned long long> flags(2 * (size_t)S->max_slots);
+    // the ready residents by slot, taken under the lock: the admission thread
+    // fills free slots meanwhile, the worker alone retires ready ones
+    std::vector<Request*> res(S->max_slots, nullptr);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->adm_new) {
+                S->adm_new = false;
+                dirty = true;
+            }
+            int n_active = 0, n_ready = 0;
+            for (int sl = 0; sl < S->max_slots; ++sl) {
+                Request* r = S->active[sl];
+                res[sl] = r && r->ready ? r : nullptr;
+                n_active += r ? 1 : 0;
+                n_ready += res[sl] ? 1 : 0;
+            }
+            S->stats.active = n_active;
+            S->stats.queued = (int64_t)S->queue.size();
+            S->stats.peak_active = std::max<int64_t>(S->stats.peak_active, n_active);
+            if (S->device_error) return;
+            if (n_ready == 0) {
+                // held slots are admissions in flight: wait for them
+                if (S->stop && n_active == 0) return;
+                S->cv.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
         }
         if (dirty) {
-            if (!rebuild_tables(S)) {
+            if (!rebuild_tables(S, res)) {
                 std::lock_guard<std::mutex> lk(S->mu);
                 S->device_error = true;
                 sfail(S, MILOC_EDEVICE, "work-list upload failed");
                 S->stop = true;
+                S->cv.notify_all();
                 return;
             }
             dirty = false;
@@ -577,7 +626,7 @@ void worker_loop(miloc_server* S)
         // results of the models whose spectra run in this tick: into the
         // pinned result area while it has room, else into the request
         size_t res_used = 0;
-        for (Request* r : S->active) {
+        for (Request* r : res) {
             if (!r || r->phase != 1 || e != hipSuccess) continue;
             const size_t sp_bytes = (size_t)r->T * r->nch * sizeof(float);
             const size_t x_bytes = (size_t)r->n * r->L * sizeof(double);
@@ -641,7 +690,7 @@ void worker_loop(miloc_server* S)
                 retired = true;
             };
             for (int sl = 0; sl < S->max_slots; ++sl) {
-                Request* r = S->active[sl];
+                Request* r = res[sl];
                 if (!r) continue;
                 if (r->phase == 1) {               // its spectra ran in this tick
                     retire(r);
@@ -696,6 +745,7 @@ miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int ma
     S->cap_cell = (size_t)max_slots * (kMaxServeShells / 256 + 1);
     S->cap_se = (size_t)max_slots * (kMaxServeShells / kSeBs + 1);
     bool ok = hipStreamCreate(&S->stream) == hipSuccess;
+    ok = ok && hipStreamCreate(&S->adm_stream) == hipSuccess;
     ok = ok && hipMalloc(&S->arena_mem, hbm_budget_bytes) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_models), max_slots * sizeof(ServeModel)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&S->d_march), S->cap_march * sizeof(int4)) == hipSuccess;
@@ -746,6 +796,7 @@ miloc_status miloc_server_create(int hip_device, size_t hbm_budget_bytes, int ma
     }
     miloc_server* raw = S.release();
     raw->worker = std::thread(worker_loop, raw);
+    raw->admitter = std::thread(admit_loop, raw);
     *out = raw;
     return MILOC_OK;
 }
@@ -761,8 +812,10 @@ void miloc_server_destroy(miloc_server* S)
             if (r) r->cancel_req = true;
     }
     S->cv.notify_all();
+    if (S->admitter.joinable()) S->admitter.join();
     if (S->worker.joinable()) S->worker.join();
     (void)hipSetDevice(S->device);
+    if (S->adm_stream) (void)hipStreamSynchronize(S->adm_stream);
     if (S->stream) (void)hipStreamSynchronize(S->stream);
     for (int t = 0; t < kLdsTiers; ++t) {
         if (S->graph_exec[t]) (void)hipGraphExecDestroy(S->graph_exec[t]);
@@ -774,6 +827,7 @@ void miloc_server_destroy(miloc_server* S)
         if (b) (void)hipFree(b);
     if (S->h_stage) (void)hipHostFree(S->h_stage);
     if (S->h_res) (void)hipHostFree(S->h_res);
+    if (S->adm_stream) (void)hipStreamDestroy(S->adm_stream);
     if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
 }
