@@ -24,6 +24,7 @@
 // non-zero are touched (App. A.2).  The ray's full channel vector lives in LDS.
 // Per step the group reduces its two partial sums with DPP row operations.
 #include <hip/hip_runtime.h>
+#include <climits>
 #include <math.h>
 
 #include <type_traits>
@@ -439,18 +440,36 @@ __device__ __forceinline__ void window_passes_f32(float* __restrict__ rl, int la
     }
 }
 
+template <int LANES, int CLS, bool MASK>
+__device__ __forceinline__ void window_passes_pred(float* __restrict__ rl, int lane, int nwin, float xl,
+                                                   float hstep, float x0, float ibs, float l2len, float kh,
+                                                   float eh, float& sj, float& sl);
+
+// Channels the unrolled passes of a lane group reach from a window's start.
+template <int LANES>
+constexpr int pass_reach() { return (LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4)) * LANES; }
+
 // FP32 single-Gaussian form of window_loop: the optical-depth class is voted
 // once per step for the wavefront (no per-channel branch), the maser check
-// as in window_loop.
+// as in window_loop.  Thin steps whose window start is at most nch_reach
+// (the band's channel count minus pass_reach) in every lane take the
+// unmasked predicated passes: the channels from the window start to the
+// reach are all updated, those past the cut with their true (negligible)
+// profile values, and all stay inside the vector.
 template <int LANES>
 __device__ __forceinline__ void window_f32(float* __restrict__ I, int lane, int clo, int nwin, float x0, float ibs,
-                                           float kl, float el, float& sj, float& sl, unsigned* __restrict__ maser)
+                                           float kl, float el, float& sj, float& sl, unsigned* __restrict__ maser,
+                                           int nch_reach)
 {
     float* __restrict__ rl = I + clo + lane;
     const float xl = fmaf((float)lane, ibs, x0);
     const float hstep = (float)LANES * ibs;
     const float akl = fabsf(kl);
-    if (__all(akl < 1e-3f)) {
+    const unsigned long long all_lanes = __builtin_amdgcn_read_exec();
+    const unsigned long long thin = __builtin_amdgcn_ballot_w64(akl < 1e-3f);
+    if ((thin & __builtin_amdgcn_ballot_w64(clo <= nch_reach)) == all_lanes) {
+        window_passes_pred<LANES, 0, false>(rl, lane, nwin, xl, hstep, x0, ibs, 0.0f, kl, el, sj, sl);
+    } else if (thin == all_lanes) {
         window_passes_f32<LANES, 0>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
     } else if (__all(akl < 1e-2f)) {
         window_passes_f32<LANES, 1>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
@@ -463,14 +482,15 @@ __device__ __forceinline__ void window_f32(float* __restrict__ I, int lane, int 
 // With HF the component count picks, once per step (it is uniform), a loop
 // whose profile sum is unrolled over exactly 1..4 components, or over 8 or
 // all register components with zero-strength padding.
+// nch_reach: see window_f32 (INT_MIN: never the unmasked passes).
 template <int LANES, typename T, bool HF = false>
 __device__ __forceinline__ void window_channels(T* __restrict__ I, int lane, int clo, int nwin, T x0, T ibs,
                                                 T kl, T el, T& sj, T& sl, const HfRegs<T>* hf,
-                                                unsigned* __restrict__ maser)
+                                                unsigned* __restrict__ maser, int nch_reach = INT_MIN)
 {
     if constexpr (!HF) {
         if constexpr (std::is_same<T, float>::value)
-            window_f32<LANES>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, maser);
+            window_f32<LANES>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, maser, nch_reach);
         else
             window_loop<LANES, T, 0>(I, lane, clo, nwin, x0, ibs, kl, el, sj, sl, hf, maser);
     } else {
@@ -1104,6 +1124,7 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
     SpanStack<LANES, kSpanSlots> spans;
     // deeper stacks than the span registers hold copy whole vectors
     const bool use_spans = p.depth <= kSpanSlots * LANES;
+    const int nch_reach = p.nch - pass_reach<LANES>();
     int lo = 0, hi = p.nch;                       // LDS contents unknown: a full reset first
     // Work units start only at chunk boundaries, which all groups of the
     // wavefront reach together: the records of a chunk are loaded (and the
@@ -1241,13 +1262,16 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const int clo = as_int(wv.z);
             const int nwin = as_int(wv.w);
             if (nwin > 0) {
+                // the unmasked FP32 passes may change every channel up to the
+                // reach: the span covers them whichever passes run
+                const int top = sizeof(T) == 4 && clo <= nch_reach ? clo + pass_reach<LANES>() : clo + nwin;
                 lo = clo < lo ? clo : lo;
-                hi = clo + nwin > hi ? clo + nwin : hi;
+                hi = top > hi ? top : hi;
             }
             const T kl = kv.x * len;
             const T el = kv.y * len;
             T sj = 0, sl = 0;
-            window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr, p.maser);
+            window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr, p.maser, nch_reach);
             if (ACCUM) {
                 const T wgt = aw * len;
                 T2q v;
@@ -1379,7 +1403,7 @@ __device__ __forceinline__ void march1d_block(const March1DArgs<T>& p, int ray0,
             const T tl = r.x;
             T sj = 0, sl = 0;
             window_channels<LANES, T, HF>(I, lane, clo, chi - clo + 1, frac * sv.y, sv.y, kev.x * tl, kev.y * tl,
-                                          sj, sl, &hfr, p.maser);
+                                          sj, sl, &hfr, p.maser, p.nch - pass_reach<LANES>());
             if (ACCUM) {
                 sj = group_sum<LANES>(sj);
                 sl = group_sum<LANES>(sl);
