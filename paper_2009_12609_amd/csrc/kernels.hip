@@ -89,6 +89,30 @@ __device__ __forceinline__ float dpp_add(float v)
     return v + __builtin_bit_cast(float, got);
 }
 
+// The value of v in the lane that DPP control CTRL selects (all rows and banks).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
+                                                                  false));
+}
+
+// Reduce-scatter over a group of 8 lanes: lane l of the group receives the
+// sum over the group's lanes of p[l].  Three butterfly stages (pairs l and
+// 7 - l by the half-row mirror, then l ^ 2 and l ^ 1 by quad permutations),
+// each lane sending the half of its values that its partner keeps.
+__device__ __forceinline__ float reduce_scatter8(const float (&p)[8], int lane)
+{
+    const bool hi = lane & 4, b1 = lane & 2, b0 = lane & 1;
+    float q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = (hi ? p[4 + j] : p[j]) + dpp_mov<0x141>(hi ? p[j] : p[4 + j]);
+    float r[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) r[m] = (b1 ? q[2 + m] : q[m]) + dpp_mov<0x4E>(b1 ? q[m] : q[2 + m]);
+    return (b0 ? r[1] : r[0]) + dpp_mov<0xB1>(b0 ? r[0] : r[1]);
+}
+
 // Keeps v computed where it stands rather than sunk into a following branch
 // that is its only use (an empty asm statement: no instruction).  Used on the
 // group sums: sunk, their last DPP stage cannot be fused into its add.
@@ -785,6 +809,10 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     // written to E[step][ray] with the ray weight, rays of one step side by
     // side.
     constexpr bool kRegQueue = LANES <= 16;
+    // 8-lane groups that accumulate keep instead each lane's own partial sums
+    // of 8 consecutive steps and reduce-scatter them once per 8 steps (lane k
+    // of a group then holds step k's totals): no per-step reduction or queue.
+    constexpr bool kT8 = ACCUM && LANES == 8;
     float2* __restrict__ qw = reinterpret_cast<float2*>(smem_raw + p.queue_lds_offset) + (size_t)(rib - rib % rpw) * LANES;
     const int wl = threadIdx.x & 63;
     const int q_ray = wl % rpw, q_step = wl / rpw;
@@ -825,7 +853,7 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
         wv = win[(unsigned)idx];
         kv = ke[(size_t)(unsigned)idx * (unsigned)ts];
     };
-    auto step = [&](int s, float l2len, bool restart, const float4& wv, const float2& kv) {
+    auto step = [&](int s, float l2len, bool restart, const float4& wv, const float2& kv, float& pj, float& pl) {
         if (restart) {
             // side exit: re-entry on the opposite face with the background (Sect. 2.2)
             for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
@@ -851,7 +879,10 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
             if (kv.x * fast_exp2(l2len) < (float)kMaserTauMin) *p.maser = 1u;
             window_passes_pred<LANES, 2, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         }
-        if (ACCUM) {
+        if constexpr (kT8) {
+            pj = sj;
+            pl = sl;
+        } else if (ACCUM) {
             const float tx = group_sum<LANES>(sj);
             const float ty = group_sum<LANES>(sl);
             if constexpr (kRegQueue) {
@@ -898,25 +929,54 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     bool rsr[kPrefetch];
     float4 wvr[kPrefetch];
     float2 kvr[kPrefetch];
+    auto shift_ring = [&]() {
+#pragma unroll
+        for (int i = 0; i + 1 < kPrefetch; ++i) {
+            l2r[i] = l2r[i + 1];
+            rsr[i] = rsr[i + 1];
+            wvr[i] = wvr[i + 1];
+            kvr[i] = kvr[i + 1];
+        }
+    };
     if (ns > 0) {
 #pragma unroll
         for (int i = 0; i < kPrefetch; ++i) fetch(i, l2r[i], rsr[i], wvr[i], kvr[i]);
         int s0 = 0;
-        for (; s0 + kPrefetch <= ns; s0 += kPrefetch) {
+        float pj[8], pl[8];
+        if constexpr (kT8) {
+            // two turns of the ring per 8 steps, then the sums of the 8 steps
+            for (; s0 + 8 <= ns; s0 += 8) {
 #pragma unroll
-            for (int i = 0; i < kPrefetch; ++i) {
-                step(s0 + i, l2r[i], rsr[i], wvr[i], kvr[i]);
-                fetch(s0 + i + kPrefetch, l2r[i], rsr[i], wvr[i], kvr[i]);
+                for (int i = 0; i < 8; ++i) {
+                    constexpr int M = kPrefetch - 1;
+                    step(s0 + i, l2r[i & M], rsr[i & M], wvr[i & M], kvr[i & M], pj[i], pl[i]);
+                    fetch(s0 + i + kPrefetch, l2r[i & M], rsr[i & M], wvr[i & M], kvr[i & M]);
+                }
+                const float tj = reduce_scatter8(pj, lane);
+                const float tl = reduce_scatter8(pl, lane);
+                if (ray_ok) E[(size_t)(s0 + lane) * p.rays_per_dir + r] = make_float2(tj * aw, tl * aw);
             }
-        }
-        for (; s0 < ns; ++s0) {
-            step(s0, l2r[0], rsr[0], wvr[0], kvr[0]);
+            // the last ns mod 8 steps one at a time, each stored at once
+            for (; s0 < ns; ++s0) {
+                step(s0, l2r[0], rsr[0], wvr[0], kvr[0], pj[0], pl[0]);
+                const float tj = group_sum<LANES>(pj[0]);
+                const float tl = group_sum<LANES>(pl[0]);
+                if (lane == 0 && ray_ok) E[(size_t)s0 * p.rays_per_dir + r] = make_float2(tj * aw, tl * aw);
+                shift_ring();
+                fetch(s0 + kPrefetch, l2r[kPrefetch - 1], rsr[kPrefetch - 1], wvr[kPrefetch - 1],
+                      kvr[kPrefetch - 1]);
+            }
+        } else {
+            for (; s0 + kPrefetch <= ns; s0 += kPrefetch) {
 #pragma unroll
-            for (int i = 0; i + 1 < kPrefetch; ++i) {
-                l2r[i] = l2r[i + 1];
-                rsr[i] = rsr[i + 1];
-                wvr[i] = wvr[i + 1];
-                kvr[i] = kvr[i + 1];
+                for (int i = 0; i < kPrefetch; ++i) {
+                    step(s0 + i, l2r[i], rsr[i], wvr[i], kvr[i], pj[i], pl[i]);
+                    fetch(s0 + i + kPrefetch, l2r[i], rsr[i], wvr[i], kvr[i]);
+                }
+            }
+            for (; s0 < ns; ++s0) {
+                step(s0, l2r[0], rsr[0], wvr[0], kvr[0], pj[0], pl[0]);
+                shift_ring();
             }
         }
     }
