@@ -42,6 +42,10 @@
  *     sums of one march launch (default 16 for regular grids, 160 for
  *     octrees); the transitions of an iteration that do not fit are marched
  *     in further launches.
+ *   - MILOC_WIDE_OFFSETS (set, any value; read at every march launch): the
+ *     FP32 regular-grid march addresses its cell tables with 64-bit offsets
+ *     also where 32-bit ones suffice (grids below 2^24 cells whose tables
+ *     stay below 4 GB).  The results are identical; for testing.
  */
 #ifndef MILOC_H
 #define MILOC_H

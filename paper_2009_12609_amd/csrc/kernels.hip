@@ -25,6 +25,7 @@
 // Per step the group reduces its two partial sums with DPP row operations.
 #include <hip/hip_runtime.h>
 #include <climits>
+#include <cstdlib>
 #include <math.h>
 
 #include <type_traits>
@@ -752,7 +753,7 @@ __device__ __forceinline__ int in_vgpr(int v)
 //    turn of the ring issues the same loads, so each step waits for its own
 //    data only;
 //  * the transverse wrap-around corrections sit in vector registers.
-template <int LANES, bool ACCUM>
+template <int LANES, bool ACCUM, bool OFF32>
 __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
 {
     const int rpb = blockDim.x / LANES;
@@ -787,6 +788,7 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     const int dwa = in_vgpr(-D.sa * (N - 1) * D.sta), dwb = in_vgpr(-D.sb * (N - 1) * D.stb);
     const float Ibg = p.Ibg[t];
     const int ts = p.ntr_total;
+    const unsigned kv_bytes = (unsigned)ts * (unsigned)sizeof(float2);
     const float4* __restrict__ win = p.win + (size_t)q * p.nc;
     const float2* __restrict__ ke = p.ke + t;
     float2* __restrict__ E = p.E ? p.E + (size_t)(t - p.trans_offset) * p.e_tstride + (size_t)D.step0 * p.rays_per_dir
@@ -850,8 +852,17 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
             if (flags & 4) move_wrap(cb, idx, D.sb, wrap_b, db, dwb, N, restart);
         }
         l2len = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vrec.len), si - rb));
-        wv = win[(unsigned)idx];
-        kv = ke[(size_t)(unsigned)idx * (unsigned)ts];
+        if constexpr (OFF32) {
+            // byte offsets below 2^32 from the uniform bases of the two tables
+            // (the launch checks the sizes), the cell index below 2^24
+            wv = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(win) + ((unsigned)idx << 4));
+            // (the masks are no-ops that let the multiply be a 24-bit one)
+            kv = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(ke) +
+                                                  (((unsigned)idx & 0xFFFFFFu) * (kv_bytes & 0xFFFFFFu)));
+        } else {
+            wv = win[(unsigned)idx];
+            kv = ke[(size_t)(unsigned)idx * (unsigned)ts];
+        }
     };
     auto step = [&](int s, float l2len, bool restart, const float4& wv, const float2& kv, float& pj, float& pl) {
         if (restart) {
@@ -2141,11 +2152,23 @@ hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
     if (shm > 163840) return hipErrorInvalidValue;
     if constexpr (kF32) {
         if (shm > 65536) {
-            hipError_t e = hipFuncSetAttribute((const void*)march3d_f32_kernel<LANES, ACCUM>,
+            hipError_t e = hipFuncSetAttribute((const void*)march3d_f32_kernel<LANES, ACCUM, true>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void*)march3d_f32_kernel<LANES, ACCUM, false>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL((march3d_f32_kernel<LANES, ACCUM>), grid, dim3(rpb * LANES), shm, s, a);
+        // 32-bit table offsets while a direction's window table and the
+        // {khat, ehat} table stay below 4 GB and the cells below 2^24
+        const uint64_t nc = (uint64_t)a.nc;
+        const bool off32 = nc < (1u << 24) && nc * sizeof(float4) < (1ull << 32) &&
+                           nc * (uint64_t)a.ntr_total * sizeof(float2) < (1ull << 32) &&
+                           !std::getenv("MILOC_WIDE_OFFSETS");
+        if (off32)
+            hipLaunchKernelGGL((march3d_f32_kernel<LANES, ACCUM, true>), grid, dim3(rpb * LANES), shm, s, a);
+        else
+            hipLaunchKernelGGL((march3d_f32_kernel<LANES, ACCUM, false>), grid, dim3(rpb * LANES), shm, s, a);
     } else {
         if (shm > 65536) {
             hipError_t e = hipFuncSetAttribute((const void*)march3d_kernel<T, LANES, ACCUM, HF>,

@@ -231,6 +231,28 @@ def test_lane_group_widths(kind, lanes, monkeypatch):
     ctx.close()
 
 
+def test_wide_cell_offsets_identical(monkeypatch):
+    """The FP32 regular-grid march addresses its cell tables with 32-bit
+    offsets below 2^24 cells and with 64-bit ones above: both instances,
+    the second forced through MILOC_WIDE_OFFSETS, give identical results
+    (populations, J and Lambda, spectra) on a 13^3 grid."""
+    w = workload_3d(13, seed=113, abundance=3e-7, box_pc=0.1)
+    print("[case] 3d N=13 narrow/wide offsets", flush=True)
+    out = []
+    for wide in (False, True):
+        if wide:
+            monkeypatch.setenv("MILOC_WIDE_OFFSETS", "1")
+        else:
+            monkeypatch.delenv("MILOC_WIDE_OFFSETS", raising=False)
+        ctx = make_ctx(w)
+        ctx.run(3)
+        J, Lam = ctx.radiation()
+        out.append((ctx.populations(), J, Lam, ctx.spectra(0, n_los=13 * 13)))
+        ctx.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_3d_fp64_march():
     w = workload_3d(8, seed=7, abundance=1e-7, n_levels=5, box_pc=0.05, nch=128)
     ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, 3)
