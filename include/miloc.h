@@ -46,6 +46,12 @@
  *     FP32 regular-grid march addresses its cell tables with 64-bit offsets
  *     also where 32-bit ones suffice (grids below 2^24 cells whose tables
  *     stay below 4 GB).  The results are identical; for testing.
+ *   - MILOC_FULL_CHANNEL_VECTORS (set, any value; read when a context first
+ *     marches a regular grid after its windows were built): the FP32
+ *     regular-grid march keeps every ray's whole channel vector in LDS rather
+ *     than only the span of channels the ray's windows reach (which allows
+ *     more workgroups per compute unit).  The results are identical; for
+ *     testing.
  */
 #ifndef MILOC_H
 #define MILOC_H

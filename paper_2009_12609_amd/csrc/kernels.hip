@@ -787,6 +787,8 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     const int da = in_vgpr(D.sa * D.sta), db = in_vgpr(D.sb * D.stb);
     const int dwa = in_vgpr(-D.sa * (N - 1) * D.sta), dwb = in_vgpr(-D.sb * (N - 1) * D.stb);
     const float Ibg = p.Ibg[t];
+    // channel c of the ray lives at I[c - base] (base 0 without a span table)
+    const int base = p.rbase ? p.rbase[(size_t)q * p.rays_per_dir + rr] : 0;
     const int ts = p.ntr_total;
     const unsigned kv_bytes = (unsigned)ts * (unsigned)sizeof(float2);
     const float4* __restrict__ win = p.win + (size_t)q * p.nc;
@@ -867,11 +869,11 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
     auto step = [&](int s, float l2len, bool restart, const float4& wv, const float2& kv, float& pj, float& pl) {
         if (restart) {
             // side exit: re-entry on the opposite face with the background (Sect. 2.2)
-            for (int c = lane; c < p.nch; c += LANES) I[c] = Ibg;
+            for (int c = lane; c < p.ich; c += LANES) I[c] = Ibg;
         }
         const int clo = as_int(wv.z);
         const int nwin = as_int(wv.w);
-        float* __restrict__ rl = I + clo + lane;
+        float* __restrict__ rl = I + (clo - base) + lane;
         const float xl = fmaf((float)lane, wv.y, wv.x);
         const float hstep = (float)LANES * wv.y;
         const float akh = fabsf(kv.x);
@@ -995,6 +997,38 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
         float* out = p.Iout + ((size_t)q * p.rays_per_dir + r) * p.nch;
         for (int c = lane; c < p.nch; c += LANES) out[c] = I[c];
     }
+}
+
+// The channel span of every ray of a direction (grid y = direction, one
+// thread per ray): the ray's cells as march3d steps through them, the lowest
+// first window channel and the highest window start plus max(window, reach).
+__global__ __launch_bounds__(256) void ray_span_kernel(March3DArgs<float> p, int reach, int* __restrict__ rbase,
+                                                       int* __restrict__ wmax)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (r >= p.rays_per_dir) return;
+    const DirDev D = p.dirs[q];
+    const int N = p.N;
+    int ca = r % N, cb = r / N;
+    int idx = D.start_off + ca * D.sta + cb * D.stb;
+    const float4* __restrict__ win = p.win + (size_t)q * p.nc;
+    int lo = INT_MAX, hi = INT_MIN;
+    bool restart = false;
+    for (int s = 0; s < D.nsteps; ++s) {
+        const StepRec<float> rec = p.steps[D.step0 + s];
+        if (rec.flags & 1) idx += D.stride_m;
+        if (rec.flags & 2) move_transverse(ca, idx, D.sa, D.sta, N, restart);
+        if (rec.flags & 4) move_transverse(cb, idx, D.sb, D.stb, N, restart);
+        const float4 wv = win[idx];
+        const int clo = as_int(wv.z), nwin = as_int(wv.w);
+        lo = clo < lo ? clo : lo;
+        const int top = clo + (nwin > reach ? nwin : reach);
+        hi = top > hi ? top : hi;
+    }
+    if (lo > hi) lo = hi = 0;
+    rbase[(size_t)q * p.rays_per_dir + r] = lo;
+    atomicMax(wmax, hi - lo);
 }
 
 // Sum, for every cell and transition, the per-step partial sums of all rays
@@ -2138,6 +2172,9 @@ hipError_t do_march3d(hipStream_t s, March3DArgs<T> a, int max_steps)
     // wavefront start in different LDS banks; the FP32 single-Gaussian
     // kernel's predicated passes need their reach after each vector.
     a.ich = a.nch + (kF32 ? f32_vec_gap(LANES) : 16);
+    // with a span table the vector holds the ray's span only (rounded to 32
+    // words plus 8, so that the rays of a wavefront start 8 banks apart)
+    if (kF32 && ACCUM && a.rbase) a.ich = (a.span_w + 31) / 32 * 32 + 8;
     // whole wavefronts only (the queue flush uses every lane of a wavefront)
     const int rpw = 64 / LANES;
     int rpb = 256 / LANES;
@@ -2228,6 +2265,13 @@ hipError_t dispatch1d(hipStream_t s, const March1DArgs<T>& a, int lanes, bool ac
 }
 }  // namespace
 
+hipError_t launch_ray_spans(hipStream_t s, const March3DArgs<float>& a, int reach, int* rbase, int* wmax)
+{
+    if (a.rays_per_dir <= 0 || a.n_dir <= 0) return hipSuccess;
+    const dim3 grid((a.rays_per_dir + 255) / 256, a.n_dir);
+    hipLaunchKernelGGL(ray_span_kernel, grid, dim3(256), 0, s, a, reach, rbase, wmax);
+    return hipGetLastError();
+}
 hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum,
                           int max_steps)
 {

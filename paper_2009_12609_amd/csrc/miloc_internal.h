@@ -105,6 +105,11 @@ struct March3DArgs {
     const typename V2<T>::type* hf;      // hyperfine components [ntr_total][hfk] {offset / dv, strength}, or null
     int hfk;                             // components per transition (zero-strength padding)
     unsigned* maser;                     // set to 1 by a step with line-centre tau < kMaserTauMin
+    // FP32 single-Gaussian accumulating march only: per (direction, ray) the
+    // lowest channel any window of the ray starts at, or null; a ray's LDS
+    // vector then holds channels base .. base + span_w - 1 only
+    const int* rbase;
+    int span_w;
 };
 
 // Per-cell gather of the per-step partial sums written by march3d, for the
@@ -284,6 +289,13 @@ hipError_t launch_window_table(hipStream_t s, int nc, int n_dir, const DirDev* d
                                double dhi, void* win,
                                bool fp64);
 // max_steps: the longest step list of the launched directions (LDS staging).
+// For every (direction, ray) of a.dirs: the lowest first channel of its
+// steps' windows into rbase[q * rays_per_dir + r], and the largest span of a
+// ray (its highest window start plus max(window, reach), minus the lowest)
+// into *wmax with atomicMax (*wmax must start at 0).
+hipError_t launch_ray_spans(hipStream_t s, const March3DArgs<float>& a, int reach, int* rbase, int* wmax);
+// Channels the unrolled passes of one lane group of the FP32 march reach.
+inline int march_pass_reach(int lanes) { return (lanes >= 64 ? 1 : (lanes >= 32 ? 2 : 4)) * lanes; }
 hipError_t launch_march3d(hipStream_t s, const March3DArgs<float>& a, int lanes, bool accum,
                           int max_steps);
 hipError_t launch_march3d(hipStream_t s, const March3DArgs<double>& a, int lanes, bool accum,

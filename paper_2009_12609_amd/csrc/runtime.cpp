@@ -133,7 +133,7 @@ struct miloc_ctx {
     bool has_pops = false;
     bool has_rad = false;
     DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
-        d_zero, d_dirs, d_steps, d_flags, d_R, d_vrdv, d_area, d_vel, d_bD, d_win, d_lstart, d_moves,
+        d_zero, d_dirs, d_steps, d_flags, d_R, d_vrdv, d_area, d_vel, d_bD, d_win, d_lstart, d_moves, d_rbase, d_spanw,
         d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter, d_ocell_off, d_ocell_steps, d_oE, d_1steps, d_1off, d_1kmin;
     int64_t oct_trees = 0;
     int oct_depth = 0, oct_groups = 0;
@@ -159,6 +159,10 @@ struct miloc_ctx {
     double sub_tau_min = 0.0;
     double sums_budget = 0.0;            // device bytes left for the 3D per-step sums (check_fits)
     int tbatch = 0;                      // 1D: all transitions of a ray in one pass
+    // regular grids, FP32 single line: channel base of every (direction, ray)
+    // (d_rbase) and the largest ray span, for the lane count span_lanes (0:
+    // not built)
+    int span_lanes = 0, span_w = 0;
     int sub_last_k = -1;                 // core extent of the last iteration (-1: none)
     std::vector<int> kmin_host;          // innermost shell of each ray (1D)
     DevBuf d_ient, d_sflags;             // core entry intensities; flags of the core solves
@@ -181,7 +185,7 @@ struct miloc_ctx {
                                &d_vel, &d_bD, &d_win, &d_lstart, &d_moves, &d_qlist, &d_E, &d_osteps, &d_olen64,
                                &d_otrees, &d_oaw, &d_ostack, &d_ocounter, &d_ocell_off, &d_ocell_steps, &d_oE,
                                &d_1steps, &d_1off, &d_1kmin, &d_los_b, &d_los_steps, &d_los_off, &d_los_kmin,
-                               &d_los_out, &d_hf, &d_ient, &d_sflags};
+                               &d_los_out, &d_hf, &d_ient, &d_sflags, &d_rbase, &d_spanw};
         size_t n = 0;
         for (const DevBuf* b : all) n += b->carved ? 0 : b->bytes;
         return n;
@@ -290,7 +294,9 @@ Footprint footprint_of(int kind, int64_t nc, int L, int T, int nch, int n_dir, b
     f.fixed += c * (sizeof(float4) + sizeof(double)) + (size_t)n_dir * c * 4 * tsz + (size_t)n_dir * sizeof(DirDev);
     if (kind == 3) {
         const int64_t N = (int64_t)std::llround(std::cbrt((double)nc));
-        f.fixed += (size_t)steps * (sizeof(StepRec<double>) + sizeof(int2)) + (size_t)n_dir * (N + 1) * sizeof(int);
+        // step records and moves, layer starts, the rays' channel bases
+        f.fixed += (size_t)steps * (sizeof(StepRec<double>) + sizeof(int2)) + (size_t)n_dir * (N + 1) * sizeof(int) +
+                   (size_t)n_dir * (size_t)rays * sizeof(int);
         f.sums = (size_t)steps * (size_t)rays * 2 * tsz;
     } else {
         // cell step lists, step records (+ FP64 lengths), work units, and at
@@ -808,6 +814,7 @@ miloc_status ensure_static(miloc_ctx* c)
         HIPCHK(c, launch_window_table(c->stream, (int)nc, c->n_dir_dev, c->d_dirs.as<DirDev>(),
                                       c->d_vel.as<float4>(), c->d_bD.as<double>(), c->dv, c->chalf,
                                       Kd, c->nch, c->hf_lo, c->hf_hi, c->d_win.p, fp64));
+        c->span_lanes = 0;                // the rays' channel spans follow the windows
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->d_cellv.release();
     } else {
@@ -1006,6 +1013,36 @@ miloc_status core_subiterations(miloc_ctx* c, double* steps)
     return MILOC_OK;
 }
 
+// The channel base of every (direction, ray) of a regular grid and the
+// largest span of a ray (ray_span_kernel), for the current lane count: an
+// FP32 march then keeps only each ray's span in LDS.  span_w stays 0 when the
+// span would not be shorter than the whole padded channel vector.
+miloc_status ensure_spans(miloc_ctx* c)
+{
+    if (c->span_lanes == c->lanes) return MILOC_OK;
+    const size_t rays = (size_t)c->N * c->N;
+    HIPCHK(c, c->d_rbase.ensure((size_t)c->n_dir_dev * rays * sizeof(int)));
+    HIPCHK(c, c->d_spanw.ensure(sizeof(int)));
+    HIPCHK(c, hipMemsetAsync(c->d_spanw.p, 0, sizeof(int), c->stream));
+    March3DArgs<float> a{};
+    a.N = c->N;
+    a.nc = (int)c->nc;
+    a.nch = c->nch;
+    a.rays_per_dir = (int)rays;
+    a.n_dir = c->n_dir_dev;
+    a.dirs = c->d_dirs.as<DirDev>();
+    a.steps = c->d_steps.as<StepRec<float>>();
+    a.win = c->d_win.as<float4>();
+    const int reach = march_pass_reach(c->lanes);
+    HIPCHK(c, launch_ray_spans(c->stream, a, reach, c->d_rbase.as<int>(), c->d_spanw.as<int>()));
+    int w = 0;
+    HIPCHK(c, hipMemcpyAsync(&w, c->d_spanw.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->span_w = (w + 31) / 32 * 32 + 8 < c->nch + reach && !std::getenv("MILOC_FULL_CHANNEL_VECTORS") ? w : 0;
+    c->span_lanes = c->lanes;
+    return MILOC_OK;
+}
+
 template <typename TT>
 miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout, bool zdir,
                           const DirDev* d_dirs_override, const void* steps_override, int nd_override,
@@ -1041,6 +1078,16 @@ miloc_status launch_march(miloc_ctx* c, int ntr, int toff, bool accum, TT* Iout,
             max_steps = c->N;
         } else {
             for (const DirDev& D : c->dir_host) max_steps = std::max(max_steps, D.nsteps);
+        }
+        if constexpr (std::is_same<TT, float>::value) {
+            if (accum && !zdir && !c->hfk) {
+                const miloc_status st = ensure_spans(c);
+                if (st != MILOC_OK) return st;
+                if (c->span_w > 0) {
+                    a.rbase = c->d_rbase.as<int>();
+                    a.span_w = c->span_w;
+                }
+            }
         }
         e = launch_march3d(c->stream, a, c->lanes, accum, max_steps);
     } else {

@@ -253,6 +253,30 @@ def test_wide_cell_offsets_identical(monkeypatch):
         assert np.array_equal(a, b)
 
 
+def test_span_vectors_identical(monkeypatch):
+    """The FP32 regular-grid march keeps only each ray's channel span in LDS
+    (from the lowest window start of its steps): the same populations, J
+    and Lambda as with whole vectors (MILOC_FULL_CHANNEL_VECTORS), for 8 and
+    16 lanes per ray."""
+    w = workload_3d(12, seed=212, abundance=1e-7, box_pc=0.1)
+    for lanes in ("8", "16"):
+        monkeypatch.setenv("MILOC_LANES", lanes)
+        print(f"[case] 3d N=12 span/full vectors lanes={lanes}", flush=True)
+        out = []
+        for full in (False, True):
+            if full:
+                monkeypatch.setenv("MILOC_FULL_CHANNEL_VECTORS", "1")
+            else:
+                monkeypatch.delenv("MILOC_FULL_CHANNEL_VECTORS", raising=False)
+            ctx = make_ctx(w)
+            ctx.run(3)
+            J, Lam = ctx.radiation()
+            out.append((ctx.populations(), J, Lam))
+            ctx.close()
+        for a, b in zip(out[0], out[1]):
+            assert np.array_equal(a, b)
+
+
 def test_3d_fp64_march():
     w = workload_3d(8, seed=7, abundance=1e-7, n_levels=5, box_pc=0.05, nch=128)
     ref = oracle.run_3d(w.mol, w.model, w.spec, w.T_bg, 3)
