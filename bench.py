@@ -60,6 +60,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march3d_regular_128_traffic.json"
 OCT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_oct_64root_L4_traffic.json")
 
 
+def off32_tables(w) -> bool:
+    """Whether the FP32 regular-grid march addresses the cube's tables with
+    32-bit offsets (the launch's own test: fewer than 2^24 cells, tables
+    below 4 GB, MILOC_WIDE_OFFSETS unset)."""
+    nc = int(w.model.n_cells)
+    return (nc < 2 ** 24 and nc * 16 < 2 ** 32 and nc * int(w.mol.n_trans) * 8 < 2 ** 32
+            and "MILOC_WIDE_OFFSETS" not in os.environ)
+
+
 def mean_window_channels(w) -> float:
     """Mean number of channels in a step's window: 2 K b / dv per cell,
     clipped to the band (every cell is crossed about equally often)."""
@@ -576,7 +585,7 @@ def main():
             "unit": "GB/s",
             "frac": hbm_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": f"march3d_f32_kernel<{cnt['march_lanes']},true>",
+            "kernel": f"march3d_f32_kernel<{cnt['march_lanes']},true,{str(off32_tables(w)).lower()}>",
             "bytes_per_step": BYTES_PER_STEP,
             "steps_per_launch": steps_per_launch,
             "march_ms_per_launch": march_ms,
