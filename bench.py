@@ -101,6 +101,22 @@ def measured_counters(src_hash, path=TRAFFIC_FILE):
     return d.get("bytes_per_launch"), d.get("valu_busy")
 
 
+def host_cpu() -> dict:
+    """The host the oracle ran on: CPU model (from /proc/cpuinfo), hardware
+    threads the OS reports, and those this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_model": model, "os_threads": os.cpu_count(), "usable_threads": usable}
+
+
 def cpu_baseline(w, budget_s=8.0, gpu_value=None):
     """Oracle (FP64, all channels) on the same cube, one transition (J=1-0):
     on all host threads, directions added one at a time until ~budget_s of
@@ -139,7 +155,8 @@ def cpu_baseline(w, budget_s=8.0, gpu_value=None):
                      f"full {N}^3 cube, all {w.spec.n_channels} channels ({t_all:.1f} s)",
            "one_thread": {"value": v_one, "cores": 1,
                           "sample": f"as above on one thread, {used_one} direction ({t_one:.1f} s)"},
-           "paper_gpu_vs_one_core": PAPER_SPEEDUPS}
+           "paper_gpu_vs_one_core": PAPER_SPEEDUPS,
+           "host": host_cpu()}
     if gpu_value:
         out["gpu_vs_one_thread"] = gpu_value / v_one
         out["gpu_vs_all_threads"] = gpu_value / v_all
