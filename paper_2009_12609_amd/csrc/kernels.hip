@@ -1221,8 +1221,13 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
     T* __restrict__ I = reinterpret_cast<T*>(smem_raw) + (size_t)grp * p.ich;
     // per-step sums queued in LDS and written LANES at a time (plain stores,
     // gathered per cell afterwards): no device atomics in the march
+    // FP32 with 8 lanes queues the two quad sums of each step of a chunk
+    // (the group sum and the step weight are finished once per chunk), other
+    // instances the weighted group sum
+    constexpr bool kQuad = sizeof(T) == 4 && LANES == 8;
+    constexpr int kQueue = kQuad ? 2 * LANES : LANES;
     T2q* __restrict__ queue = reinterpret_cast<T2q*>(smem_raw + (size_t)(blockDim.x / LANES) * p.ich * sizeof(T)) +
-                              (size_t)grp * LANES;
+                              (size_t)grp * kQueue;
     T* __restrict__ stk = p.stack + gid * (size_t)p.depth * p.ich;
     constexpr int kPer = 16 / (int)sizeof(T);   // channels per 16-byte piece
     constexpr int kSpanSlots = 8;
@@ -1268,6 +1273,12 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         const unsigned c = r.x & kOctCellMask;
         wvv = win[c];
         kvv = ke[(size_t)c * p.ntr_total];
+    };
+    // byte address of the group's first lane for the record broadcasts
+    const int bp_base = (int)(threadIdx.x & ~(unsigned)(LANES - 1)) << 2;
+    auto bcast = [&](auto v, int k) {
+        using V = decltype(v);
+        return __builtin_bit_cast(V, __builtin_amdgcn_ds_bpermute(bp_base + (k << 2), __builtin_bit_cast(int, v)));
     };
     for (;;) {
         if (have) {
@@ -1318,19 +1329,32 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         }
         // every group without a unit has found the counter exhausted
         if (__all(!have)) break;
+        const int s_chunk = s;
         for (int k = 0; k < LANES; ++k) {
             if (!have || s >= tr.n) continue;
-            const unsigned w0 = __shfl(mine.x, k, LANES);
-            T len = (T)__uint_as_float(__shfl(mine.y, k, LANES));
+            const unsigned w0 = bcast(mine.x, k);
+            T len = (T)__uint_as_float(bcast(mine.y, k));
             if (sizeof(T) == 8 && rec64) len = (T)__shfl(mine64, k, LANES);
             T4 wv;
-            wv.x = __shfl(mywv.x, k, LANES);
-            wv.y = __shfl(mywv.y, k, LANES);
-            wv.z = __shfl(mywv.z, k, LANES);
-            wv.w = __shfl(mywv.w, k, LANES);
+            if constexpr (sizeof(T) == 4) {
+                wv.x = bcast(mywv.x, k);
+                wv.y = bcast(mywv.y, k);
+                wv.z = bcast(mywv.z, k);
+                wv.w = bcast(mywv.w, k);
+            } else {
+                wv.x = __shfl(mywv.x, k, LANES);
+                wv.y = __shfl(mywv.y, k, LANES);
+                wv.z = __shfl(mywv.z, k, LANES);
+                wv.w = __shfl(mywv.w, k, LANES);
+            }
             T2 kv;
-            kv.x = __shfl(mykv.x, k, LANES);
-            kv.y = __shfl(mykv.y, k, LANES);
+            if constexpr (sizeof(T) == 4) {
+                kv.x = bcast(mykv.x, k);
+                kv.y = bcast(mykv.y, k);
+            } else {
+                kv.x = __shfl(mykv.x, k, LANES);
+                kv.y = __shfl(mykv.y, k, LANES);
+            }
             const unsigned mode = w0 >> kOctModeShift;
             // Channels outside the span [lo, hi) hold the background: the
             // span grows with each step's window, a new ray takes the span of
@@ -1378,23 +1402,48 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             T sj = 0, sl = 0;
             window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr, p.maser, nch_reach);
             if (ACCUM) {
-                const T wgt = aw * len;
-                T2q v;
-                v.x = wgt * group_sum<LANES>(sj);
-                v.y = wgt * group_sum<LANES>(sl);
-                keep_here(v.x);
-                keep_here(v.y);
-                if (lane == LANES - 1) queue[qn] = v;
-                ++qn;
-                __builtin_amdgcn_wave_barrier();
-                if (qn == LANES || s == tr.n - 1) {
-                    if (lane < qn) Et[(size_t)(qs0 + lane) * p.estride] = queue[lane];
-                    qs0 += qn;
-                    qn = 0;
+                if constexpr (kQuad) {
+                    // every lane of a quad holds the quad's sum; lanes 0 and 4
+                    // queue them for step k
+                    float hj = dpp_add<0xB1, 0xF>((float)sj);
+                    float hl = dpp_add<0xB1, 0xF>((float)sl);
+                    hj = dpp_add<0x4E, 0xF>(hj);
+                    hl = dpp_add<0x4E, 0xF>(hl);
+                    keep_here(hj);
+                    keep_here(hl);
+                    if ((lane & 3) == 0) queue[2 * k + (lane >> 2)] = T2q{(T)hj, (T)hl};
+                } else {
+                    const T wgt = aw * len;
+                    T2q v;
+                    v.x = wgt * group_sum<LANES>(sj);
+                    v.y = wgt * group_sum<LANES>(sl);
+                    keep_here(v.x);
+                    keep_here(v.y);
+                    if (lane == LANES - 1) queue[qn] = v;
+                    ++qn;
+                    __builtin_amdgcn_wave_barrier();
+                    if (qn == LANES || s == tr.n - 1) {
+                        if (lane < qn) Et[(size_t)(qs0 + lane) * p.estride] = queue[lane];
+                        qs0 += qn;
+                        qn = 0;
+                    }
                 }
             }
             __builtin_amdgcn_wave_barrier();
             ++s;
+        }
+        if constexpr (ACCUM && kQuad) {
+            // steps s_chunk .. s - 1 of the unit ran in this chunk: lane k
+            // finishes step k's group sum (the two quad sums, the same
+            // additions as a butterfly) and weight, aw times its own record's
+            // length, and writes its row
+            __builtin_amdgcn_wave_barrier();
+            if (have && lane < s - s_chunk) {
+                const T2q a = queue[2 * lane], b = queue[2 * lane + 1];
+                const T wgt = aw * (T)__uint_as_float(mine.y);
+                Et[(size_t)(s_chunk + lane) * p.estride] = T2q{wgt * (a.x + b.x), wgt * (a.y + b.y)};
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         if (have && s >= tr.n) {
             if (!ACCUM && p.Iout) {
@@ -2367,8 +2416,11 @@ hipError_t do_march_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, boo
 {
     constexpr int kGroupsPerBlock = 256 / LANES;
     const int blocks = (groups + kGroupsPerBlock - 1) / kGroupsPerBlock;
+    // channel vectors, then the per-step queues (two quad sums per step for
+    // FP32 with 8 lanes)
     const size_t shm = (size_t)kGroupsPerBlock * a.ich * sizeof(T) +
-                       (size_t)kGroupsPerBlock * LANES * sizeof(typename V2<T>::type);
+                       (size_t)kGroupsPerBlock * LANES * (sizeof(T) == 4 && LANES == 8 ? 2 : 1) *
+                           sizeof(typename V2<T>::type);
     if (shm > 64 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(a.counter, 0, sizeof(unsigned long long), s);
     if (e != hipSuccess) return e;

@@ -446,26 +446,57 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
     out.cell_steps.clear();
     if (n_cells > 0) {
         if (total > (int64_t)UINT32_MAX) return "octree: more than 2^32 steps";
-        // counting sort of the steps by cell; each thread fills a contiguous
-        // range of steps through per-cell atomic cursors
+        // stable counting sort of the steps by cell: every thread counts the
+        // cells of its own contiguous range of steps, a cell's entries are
+        // laid out thread by thread, and each thread then places its steps in
+        // order, so a cell's list keeps the schedule's step order (and the
+        // per-cell sums their summation order from run to run)
+        const int nf = std::max(1, std::min(n_threads, 16));
+        std::vector<uint32_t> cnt((size_t)nf * (size_t)n_cells, 0u);
+        auto range = [&](int w, int64_t& a, int64_t& b) {
+            a = total * w / nf;
+            b = total * (w + 1) / nf;
+        };
+        auto parallel = [&](auto&& fn) {
+            std::vector<std::thread> th;
+            for (int w = 0; w < nf; ++w) th.emplace_back(fn, w);
+            for (auto& t : th) t.join();
+        };
+        parallel([&](int w) {
+            int64_t a, b;
+            range(w, a, b);
+            uint32_t* cw = cnt.data() + (size_t)w * n_cells;
+            for (int64_t i = a; i < b; ++i) ++cw[out.rec[2 * i] & kOctCellMask];
+        });
         std::vector<int64_t>& off = out.cell_off;
         off.assign(n_cells + 1, 0);
-        for (int64_t i = 0; i < total; ++i) ++off[(out.rec[2 * i] & kOctCellMask) + 1];
+        parallel([&](int w) {
+            for (int64_t k = n_cells * w / nf; k < n_cells * (w + 1) / nf; ++k) {
+                int64_t n = 0;
+                for (int v = 0; v < nf; ++v) n += cnt[(size_t)v * n_cells + k];
+                off[k + 1] = n;
+            }
+        });
         for (int64_t k = 0; k < n_cells; ++k) off[k + 1] += off[k];
-        out.cell_steps.resize(total);
-        std::vector<std::atomic<int64_t>> cur(n_cells);
-        for (int64_t k = 0; k < n_cells; ++k) cur[k].store(off[k], std::memory_order_relaxed);
-        std::vector<std::thread> fill;
-        const int nf = std::max(1, n_threads);
-        for (int w = 0; w < nf; ++w)
-            fill.emplace_back([&, w]() {
-                const int64_t a = total * w / nf, b = total * (w + 1) / nf;
-                for (int64_t i = a; i < b; ++i) {
-                    const uint32_t c = out.rec[2 * i] & kOctCellMask;
-                    out.cell_steps[cur[c].fetch_add(1, std::memory_order_relaxed)] = (uint32_t)i;
+        // per thread and cell, the first entry of that thread's steps in the cell
+        parallel([&](int w) {
+            for (int64_t k = n_cells * w / nf; k < n_cells * (w + 1) / nf; ++k) {
+                int64_t run = off[k];
+                for (int v = 0; v < nf; ++v) {
+                    uint32_t& c = cnt[(size_t)v * n_cells + k];
+                    const uint32_t n = c;
+                    c = (uint32_t)run;
+                    run += n;
                 }
-            });
-        for (auto& t : fill) t.join();
+            }
+        });
+        out.cell_steps.resize(total);
+        parallel([&](int w) {
+            int64_t a, b;
+            range(w, a, b);
+            uint32_t* cw = cnt.data() + (size_t)w * n_cells;
+            for (int64_t i = a; i < b; ++i) out.cell_steps[cw[out.rec[2 * i] & kOctCellMask]++] = (uint32_t)i;
+        });
     }
     return std::string();
 }
