@@ -1180,19 +1180,29 @@ struct SpanStack {
     int v[SLOTS];
     __device__ __forceinline__ void set(int e, int lane, int l, int h)
     {
-        const bool mine = lane == e % LANES;
+        const int sel = lane == e % LANES ? e / LANES : -1;
         const int w = l | (h << 16);
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) v[s] = mine && s == e / LANES ? w : v[s];
+        for (int s = 0; s < SLOTS; ++s) v[s] = s == sel ? w : v[s];
     }
+    // e < SLOTS * LANES: the slot is picked by a binary tree of selects on
+    // the bits of e / LANES
     __device__ __forceinline__ void get(int e, int& l, int& h) const
     {
-        int a = 0;
+        static_assert((SLOTS & (SLOTS - 1)) == 0, "SLOTS is a power of two");
+        const int sl = e / LANES;
+        int a[SLOTS];
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) a = s == e / LANES ? v[s] : a;
-        a = __shfl(a, e % LANES, LANES);
-        l = a & 0xFFFF;
-        h = a >> 16;
+        for (int s = 0; s < SLOTS; ++s) a[s] = v[s];
+#pragma unroll
+        for (int k = 0, n = SLOTS; n > 1; ++k, n /= 2) {
+            const bool b = (sl >> k) & 1;
+#pragma unroll
+            for (int j = 0; j < n / 2; ++j) a[j] = b ? a[2 * j + 1] : a[2 * j];
+        }
+        const int r = __shfl(a[0], e % LANES, LANES);
+        l = r & 0xFFFF;
+        h = r >> 16;
     }
 };
 
@@ -1355,37 +1365,42 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
                 kv.x = __shfl(mykv.x, k, LANES);
                 kv.y = __shfl(mykv.y, k, LANES);
             }
-            const unsigned mode = w0 >> kOctModeShift;
-            // Channels outside the span [lo, hi) hold the background: the
-            // span grows with each step's window, a new ray takes the span of
-            // its saved vector, and only the span is reset or copied.
-            if (mode == kOctModeBg) {
-                for (int c = lo + lane; c < hi; c += LANES) I[c] = Ibg;
-                lo = p.nch;
-                hi = 0;
-            } else if (mode != kOctModeKeep && sp >= 0) {
-                int slo = 0, shi = p.nch;
-                if (use_spans) spans.get(sp, slo, shi);
-                // reset what the saved vector does not cover, then copy it
-                const int r0 = hi < slo ? hi : slo, r1 = lo > shi ? lo : shi;
-                for (int c = lo + lane; c < r0; c += LANES) I[c] = Ibg;
-                for (int c = r1 + lane; c < hi; c += LANES) I[c] = Ibg;
-                if (shi > slo)
-                    copy_pieces<LANES, T>(I, stk + (size_t)sp * p.ich, slo / kPer, (shi + kPer - 1) / kPer, lane);
-                lo = slo;
-                hi = shi;
-                if (mode == kOctModePop) --sp;
-            }
-            if ((w0 & kOctSave) && sp + 1 < p.depth) {
-                ++sp;
-                if (!use_spans) {
-                    lo = 0;
-                    hi = p.nch;
+            // Most steps continue their ray and save nothing (a record's word
+            // is then below kOctSave): one vote over the wavefront skips the
+            // start and save handling.
+            if (__builtin_amdgcn_ballot_w64(w0 >= kOctSave) != 0ull) {
+                const unsigned mode = w0 >> kOctModeShift;
+                // Channels outside the span [lo, hi) hold the background: the
+                // span grows with each step's window, a new ray takes the span of
+                // its saved vector, and only the span is reset or copied.
+                if (mode == kOctModeBg) {
+                    for (int c = lo + lane; c < hi; c += LANES) I[c] = Ibg;
+                    lo = p.nch;
+                    hi = 0;
+                } else if (mode != kOctModeKeep && sp >= 0) {
+                    int slo = 0, shi = p.nch;
+                    if (use_spans) spans.get(sp, slo, shi);
+                    // reset what the saved vector does not cover, then copy it
+                    const int r0 = hi < slo ? hi : slo, r1 = lo > shi ? lo : shi;
+                    for (int c = lo + lane; c < r0; c += LANES) I[c] = Ibg;
+                    for (int c = r1 + lane; c < hi; c += LANES) I[c] = Ibg;
+                    if (shi > slo)
+                        copy_pieces<LANES, T>(I, stk + (size_t)sp * p.ich, slo / kPer, (shi + kPer - 1) / kPer, lane);
+                    lo = slo;
+                    hi = shi;
+                    if (mode == kOctModePop) --sp;
                 }
-                __builtin_amdgcn_wave_barrier();
-                if (hi > lo)
-                    copy_pieces<LANES, T>(stk + (size_t)sp * p.ich, I, lo / kPer, (hi + kPer - 1) / kPer, lane);
-                if (use_spans) spans.set(sp, lane, lo, hi);
+                if ((w0 & kOctSave) && sp + 1 < p.depth) {
+                    ++sp;
+                    if (!use_spans) {
+                        lo = 0;
+                        hi = p.nch;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (hi > lo)
+                        copy_pieces<LANES, T>(stk + (size_t)sp * p.ich, I, lo / kPer, (hi + kPer - 1) / kPer, lane);
+                    if (use_spans) spans.set(sp, lane, lo, hi);
+                }
             }
             __builtin_amdgcn_wave_barrier();
             const int clo = as_int(wv.z);
