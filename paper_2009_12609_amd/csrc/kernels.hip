@@ -1109,32 +1109,41 @@ __global__ __launch_bounds__(256) void gather_oct_kernel(GatherOctArgs<T> p)
         double sj[TILE], sl[TILE];
 #pragma unroll
         for (int q = 0; q < TILE; ++q) sj[q] = sl[q] = 0.0;
-        // the next step's index is loaded with the current step's row
-        unsigned idx_n = a < b ? p.cell_steps[a] : 0u;
-        for (long long i = a; i < b; ++i) {
-            const unsigned idx = idx_n;
-            if (i + 1 < b) idx_n = p.cell_steps[i + 1];
-            const typename V2<T>::type* e = p.E + (size_t)idx * p.estride + t0;
-            if constexpr (sizeof(T) == 4) {
-                const float4* __restrict__ e4 = reinterpret_cast<const float4*>(e);
-                float4 v[TILE / 2];
+        // A cell's steps are listed in step order, which is direction-major:
+        // the threads of a wavefront take the steps of one direction at a
+        // time, so that neighbouring cells read the rows of a ray's
+        // consecutive steps (neighbouring rows) together.  The next step's
+        // index is loaded with the current step's row.
+        long long i = a;
+        unsigned idx_n = i < b ? p.cell_steps[i] : 0xFFFFFFFFu;
+        for (int d = 0; d < p.n_dir; ++d) {
+            const unsigned end = p.dir_off[d + 1];
+            while (idx_n < end) {
+                const unsigned idx = idx_n;
+                ++i;
+                idx_n = i < b ? p.cell_steps[i] : 0xFFFFFFFFu;
+                const typename V2<T>::type* e = p.E + (size_t)idx * p.estride + t0;
+                if constexpr (sizeof(T) == 4) {
+                    const float4* __restrict__ e4 = reinterpret_cast<const float4*>(e);
+                    float4 v[TILE / 2];
 #pragma unroll
-                for (int q = 0; q < TILE / 2; ++q) v[q] = e4[q];
+                    for (int q = 0; q < TILE / 2; ++q) v[q] = e4[q];
 #pragma unroll
-                for (int q = 0; q < TILE / 2; ++q) {
-                    sj[2 * q] += (double)v[q].x;
-                    sl[2 * q] += (double)v[q].y;
-                    sj[2 * q + 1] += (double)v[q].z;
-                    sl[2 * q + 1] += (double)v[q].w;
-                }
-            } else {
-                typename V2<T>::type v[TILE];
+                    for (int q = 0; q < TILE / 2; ++q) {
+                        sj[2 * q] += (double)v[q].x;
+                        sl[2 * q] += (double)v[q].y;
+                        sj[2 * q + 1] += (double)v[q].z;
+                        sl[2 * q + 1] += (double)v[q].w;
+                    }
+                } else {
+                    typename V2<T>::type v[TILE];
 #pragma unroll
-                for (int q = 0; q < TILE; ++q) v[q] = e[q];
+                    for (int q = 0; q < TILE; ++q) v[q] = e[q];
 #pragma unroll
-                for (int q = 0; q < TILE; ++q) {
-                    sj[q] += (double)v[q].x;
-                    sl[q] += (double)v[q].y;
+                    for (int q = 0; q < TILE; ++q) {
+                        sj[q] += (double)v[q].x;
+                        sl[q] += (double)v[q].y;
+                    }
                 }
             }
         }

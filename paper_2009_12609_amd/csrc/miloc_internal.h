@@ -229,7 +229,9 @@ struct GatherOctArgs {
     long long nc;
     int ntr, trans_offset, ntr_total;
     const long long* cell_off;           // [nc + 1]
-    const unsigned* cell_steps;          // step indices grouped by cell
+    const unsigned* cell_steps;          // step indices grouped by cell, ascending
+    const unsigned* dir_off;             // [n_dir + 1]: first step of each direction (steps are direction-major)
+    int n_dir;
     const typename V2<T>::type* E;       // [step][estride]
     int estride;                         // row stride of E (>= ntr; even for FP32: 16-byte rows)
     double2* acc;                        // [nc][ntr_total]

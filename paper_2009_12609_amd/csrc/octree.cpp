@@ -426,8 +426,10 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
     out.trees.reserve((size_t)nd * nroot);
     out.max_depth = 0;
     out.n_rays = 0;
+    out.dir_off.clear();
     for (Part& P : parts) {
         const int64_t base = (int64_t)out.rec.size() / 2;
+        out.dir_off.push_back(base);
         out.rec.insert(out.rec.end(), P.rec.begin(), P.rec.end());
         out.len64.insert(out.len64.end(), P.len64.begin(), P.len64.end());
         std::vector<double>().swap(P.len64);
@@ -440,6 +442,7 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
         std::vector<uint32_t>().swap(P.rec);
     }
     out.n_steps = total;
+    out.dir_off.push_back(total);
     std::stable_sort(out.trees.begin(), out.trees.end(),
                      [](const OctTreeRec& a, const OctTreeRec& b) { return a.n > b.n; });
     out.cell_off.clear();

@@ -31,7 +31,8 @@ struct OctSchedule {
     std::vector<uint32_t> rec;        // 2 words per step
     std::vector<double> len64;        // FP64 step lengths (only when asked for)
     std::vector<int64_t> cell_off;    // per cell: first entry of its steps in cell_steps (+ total)
-    std::vector<uint32_t> cell_steps; // step indices grouped by cell (only when asked for)
+    std::vector<uint32_t> cell_steps; // step indices grouped by cell, ascending (only when asked for)
+    std::vector<int64_t> dir_off;     // first step of each direction (+ total): steps are direction-major
     std::vector<OctTreeRec> trees;
     int max_depth = 0;
     int64_t n_steps = 0;

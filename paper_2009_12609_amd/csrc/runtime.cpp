@@ -134,7 +134,7 @@ struct miloc_ctx {
     bool has_rad = false;
     DevBuf d_mol, d_x, d_xnew, d_nH2, d_T, d_q, d_nmolLb, d_cellv, d_ke, d_acc, d_Ibg, d_Ibg64,
         d_zero, d_dirs, d_steps, d_flags, d_R, d_vrdv, d_area, d_vel, d_bD, d_win, d_lstart, d_moves, d_rbase, d_spanw,
-        d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter, d_ocell_off, d_ocell_steps, d_oE, d_1steps, d_1off, d_1kmin;
+        d_qlist, d_E, d_osteps, d_olen64, d_otrees, d_oaw, d_ostack, d_ocounter, d_ocell_off, d_ocell_steps, d_odir_off, d_oE, d_1steps, d_1off, d_1kmin;
     int64_t oct_trees = 0;
     int oct_depth = 0, oct_groups = 0;
     int64_t total_steps = 0;
@@ -183,7 +183,7 @@ struct miloc_ctx {
         const DevBuf* all[] = {&d_mol, &d_x, &d_xnew, &d_nH2, &d_T, &d_q, &d_nmolLb, &d_cellv, &d_ke, &d_acc,
                                &d_Ibg, &d_Ibg64, &d_zero, &d_dirs, &d_steps, &d_flags, &d_R, &d_vrdv, &d_area,
                                &d_vel, &d_bD, &d_win, &d_lstart, &d_moves, &d_qlist, &d_E, &d_osteps, &d_olen64,
-                               &d_otrees, &d_oaw, &d_ostack, &d_ocounter, &d_ocell_off, &d_ocell_steps, &d_oE,
+                               &d_otrees, &d_oaw, &d_ostack, &d_ocounter, &d_ocell_off, &d_ocell_steps, &d_odir_off, &d_oE,
                                &d_1steps, &d_1off, &d_1kmin, &d_los_b, &d_los_steps, &d_los_off, &d_los_kmin,
                                &d_los_out, &d_hf, &d_ient, &d_sflags, &d_rbase, &d_spanw};
         size_t n = 0;
@@ -523,6 +523,11 @@ miloc_status build_octree_march(miloc_ctx* c, std::vector<double>& W)
     HIPCHK(c, hipMemcpy(c->d_ocell_steps.p, S.cell_steps.data(), S.cell_steps.size() * sizeof(uint32_t),
                         hipMemcpyHostToDevice));
     std::vector<uint32_t>().swap(S.cell_steps);
+    {
+        std::vector<uint32_t> doff(S.dir_off.begin(), S.dir_off.end());
+        HIPCHK(c, c->d_odir_off.ensure(doff.size() * sizeof(uint32_t)));
+        HIPCHK(c, hipMemcpy(c->d_odir_off.p, doff.data(), doff.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
     // per-step sums: as many transitions per launch as fit the budget
     {
         // a launch lasts at least as long as its longest tree, so all
@@ -1643,12 +1648,14 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
                 HIPCHK(c, ev_record(c, 4));
                 if (fp64) {
                     GatherOctArgs<double> g{c->nc, nt, t0, c->T, c->d_ocell_off.as<long long>(),
-                                            c->d_ocell_steps.as<unsigned>(), c->d_oE.as<double2>(),
+                                            c->d_ocell_steps.as<unsigned>(), c->d_odir_off.as<unsigned>(),
+                                            c->n_dir_dev, c->d_oE.as<double2>(),
                                             c->oct_estride, c->d_acc.as<double2>()};
                     HIPCHK(c, launch_gather_oct(c->stream, g));
                 } else {
                     GatherOctArgs<float> g{c->nc, nt, t0, c->T, c->d_ocell_off.as<long long>(),
-                                           c->d_ocell_steps.as<unsigned>(), c->d_oE.as<float2>(),
+                                           c->d_ocell_steps.as<unsigned>(), c->d_odir_off.as<unsigned>(),
+                                           c->n_dir_dev, c->d_oE.as<float2>(),
                                            c->oct_estride, c->d_acc.as<double2>()};
                     HIPCHK(c, launch_gather_oct(c->stream, g));
                 }
