@@ -1283,6 +1283,9 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
     double mine64 = 0.0, nx64 = 0.0, nr64 = 0.0;
     T4 mywv{}, nxwv{};
     T2 mykv{}, nxkv{};
+    // FP32: {khat, ehat} times the step length of the lane's record, formed
+    // once per chunk in the lane that loaded it and broadcast per step
+    T2 mytau{};
     auto load_rec = [&](int s0, uint2& r, double& r64) {
         const int si = s0 + lane < tr.n ? s0 + lane : s0;
         r = rec[si];
@@ -1348,11 +1351,21 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
         }
         // every group without a unit has found the counter exhausted
         if (__all(!have)) break;
+        if constexpr (sizeof(T) == 4) {
+            const T ln = __uint_as_float(mine.y);
+            mytau = T2{mykv.x * ln, mykv.y * ln};
+            // formed here, not recomputed before each broadcast
+            keep_here(mytau.x);
+            keep_here(mytau.y);
+        }
         const int s_chunk = s;
         for (int k = 0; k < LANES; ++k) {
             if (!have || s >= tr.n) continue;
             const unsigned w0 = bcast(mine.x, k);
-            T len = (T)__uint_as_float(bcast(mine.y, k));
+            // the step length enters the optical depths (formed per chunk for
+            // FP32) and, without the per-chunk weights, the step weight
+            T len = 0;
+            if (sizeof(T) == 8 || !kQuad) len = (T)__uint_as_float(bcast(mine.y, k));
             if (sizeof(T) == 8 && rec64) len = (T)__shfl(mine64, k, LANES);
             T4 wv;
             if constexpr (sizeof(T) == 4) {
@@ -1366,13 +1379,13 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
                 wv.z = __shfl(mywv.z, k, LANES);
                 wv.w = __shfl(mywv.w, k, LANES);
             }
-            T2 kv;
+            T kl, el;
             if constexpr (sizeof(T) == 4) {
-                kv.x = bcast(mykv.x, k);
-                kv.y = bcast(mykv.y, k);
+                kl = bcast(mytau.x, k);
+                el = bcast(mytau.y, k);
             } else {
-                kv.x = __shfl(mykv.x, k, LANES);
-                kv.y = __shfl(mykv.y, k, LANES);
+                kl = __shfl(mykv.x, k, LANES) * len;
+                el = __shfl(mykv.y, k, LANES) * len;
             }
             // Most steps continue their ray and save nothing (a record's word
             // is then below kOctSave): one vote over the wavefront skips the
@@ -1421,8 +1434,6 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
                 lo = clo < lo ? clo : lo;
                 hi = top > hi ? top : hi;
             }
-            const T kl = kv.x * len;
-            const T el = kv.y * len;
             T sj = 0, sl = 0;
             window_channels<LANES, T, HF>(I, lane, clo, nwin, wv.x, wv.y, kl, el, sj, sl, &hfr, p.maser, nch_reach);
             if (ACCUM) {
