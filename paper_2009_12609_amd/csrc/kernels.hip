@@ -432,14 +432,14 @@ __device__ __forceinline__ float omb_class(float tau)
 
 // The lane group's passes over the window of one step, FP32 single Gaussian:
 // the first NU passes unrolled (channel lane + i LANES, constant LDS offsets
-// from rl = I + clo + lane, profile argument xl + i hstep), any further ones
+// from rl = I + clo + lane, profile argument xl + i LANES ibs), any further ones
 // in a loop.  The NU intensities are read before any is used, whether their
 // channel is in the window or not (one wait for all of them; a value outside
 // the window is never used): every march keeps at least kVecTailPadWords
 // words of its LDS allocation after each channel vector.
 template <int LANES, int CLS>
-__device__ __forceinline__ void window_passes_f32(float* __restrict__ rl, int lane, int nwin, float xl, float hstep,
-                                                  float x0, float ibs, float kl, float el, float& sj, float& sl)
+__device__ __forceinline__ void window_passes_f32(float* __restrict__ rl, int lane, int nwin, float xl, float x0,
+                                                  float ibs, float kl, float el, float& sj, float& sl)
 {
     constexpr int NU = LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4);
     static_assert(NU * LANES <= kVecTailPadWords, "unconditional reads must stay in the LDS allocation");
@@ -449,7 +449,9 @@ __device__ __forceinline__ void window_passes_f32(float* __restrict__ rl, int la
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
         if (lane + i * LANES < nwin) {
-            const float xs = fmaf((float)i, hstep, xl);
+            // i LANES ibs is exact (LANES a power of two): no separate pass
+            // stride to form
+            const float xs = fmaf((float)(i * LANES), ibs, xl);
             const float ec = fast_exp2(-xs * xs);
             const float omb = omb_class<CLS>(kl * ec);
             const float u = fmaf(-ec, omb, ec);
@@ -467,8 +469,8 @@ __device__ __forceinline__ void window_passes_f32(float* __restrict__ rl, int la
 
 template <int LANES, int CLS, bool MASK>
 __device__ __forceinline__ void window_passes_pred(float* __restrict__ rl, int lane, int nwin, float xl,
-                                                   float hstep, float x0, float ibs, float l2len, float kh,
-                                                   float eh, float& sj, float& sl);
+                                                   float x0, float ibs, float l2len, float kh, float eh, float& sj,
+                                                   float& sl);
 
 // Channels the unrolled passes of a lane group reach from a window's start.
 template <int LANES>
@@ -488,19 +490,18 @@ __device__ __forceinline__ void window_f32(float* __restrict__ I, int lane, int 
 {
     float* __restrict__ rl = I + clo + lane;
     const float xl = fmaf((float)lane, ibs, x0);
-    const float hstep = (float)LANES * ibs;
     const float akl = fabsf(kl);
     const unsigned long long all_lanes = __builtin_amdgcn_read_exec();
     const unsigned long long thin = __builtin_amdgcn_ballot_w64(akl < 1e-3f);
     if ((thin & __builtin_amdgcn_ballot_w64(clo <= nch_reach)) == all_lanes) {
-        window_passes_pred<LANES, 0, false>(rl, lane, nwin, xl, hstep, x0, ibs, 0.0f, kl, el, sj, sl);
+        window_passes_pred<LANES, 0, false>(rl, lane, nwin, xl, x0, ibs, 0.0f, kl, el, sj, sl);
     } else if (thin == all_lanes) {
-        window_passes_f32<LANES, 0>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
+        window_passes_f32<LANES, 0>(rl, lane, nwin, xl, x0, ibs, kl, el, sj, sl);
     } else if (__all(akl < 1e-2f)) {
-        window_passes_f32<LANES, 1>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
+        window_passes_f32<LANES, 1>(rl, lane, nwin, xl, x0, ibs, kl, el, sj, sl);
     } else {
         if (kl < (float)kMaserTauMin) *maser = 1u;
-        window_passes_f32<LANES, 2>(rl, lane, nwin, xl, hstep, x0, ibs, kl, el, sj, sl);
+        window_passes_f32<LANES, 2>(rl, lane, nwin, xl, x0, ibs, kl, el, sj, sl);
     }
 }
 
@@ -680,8 +681,8 @@ namespace {
 // with their true profile values, below e^-25 of the peak past the cut.
 template <int LANES, int CLS, bool MASK>
 __device__ __forceinline__ void window_passes_pred(float* __restrict__ rl, int lane, int nwin, float xl,
-                                                   float hstep, float x0, float ibs, float l2len, float kh,
-                                                   float eh, float& sj, float& sl)
+                                                   float x0, float ibs, float l2len, float kh, float eh, float& sj,
+                                                   float& sl)
 {
     constexpr int NU = LANES >= 64 ? 1 : (LANES >= 32 ? 2 : 4);
     float Iv[NU];
@@ -689,7 +690,7 @@ __device__ __forceinline__ void window_passes_pred(float* __restrict__ rl, int l
     for (int i = 0; i < NU; ++i) Iv[i] = rl[i * LANES];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
-        const float xs = i == 0 ? xl : fmaf((float)i, hstep, xl);
+        const float xs = i == 0 ? xl : fmaf((float)(i * LANES), ibs, xl);
         const float e = fast_exp2(fmaf(-xs, xs, l2len));
         // MASK = false: every one of the NU LANES channels lies in the band,
         // and those past the window's cut take their (negligible) profile
@@ -875,7 +876,6 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
         const int nwin = as_int(wv.w);
         float* __restrict__ rl = I + (clo - base) + lane;
         const float xl = fmaf((float)lane, wv.y, wv.x);
-        const float hstep = (float)LANES * wv.y;
         const float akh = fabsf(kv.x);
         // lane masks of the class tests, combined as masks (the ballot of a
         // combined condition would be rebuilt from a lane value)
@@ -883,14 +883,14 @@ __global__ __launch_bounds__(256) void march3d_f32_kernel(March3DArgs<float> p)
         const unsigned long long in_band = __builtin_amdgcn_ballot_w64(clo <= nch_reach);
         float sj = 0.0f, sl = 0.0f;
         if ((__builtin_amdgcn_ballot_w64(akh < kthin0) & in_band) == all_lanes) {
-            window_passes_pred<LANES, 0, false>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 0, false>(rl, lane, nwin, xl, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else if (__builtin_amdgcn_ballot_w64(akh < kthin0) == all_lanes) {
-            window_passes_pred<LANES, 0, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 0, true>(rl, lane, nwin, xl, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else if (__builtin_amdgcn_ballot_w64(akh < kthin1) == all_lanes) {
-            window_passes_pred<LANES, 1, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 1, true>(rl, lane, nwin, xl, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         } else {
             if (kv.x * fast_exp2(l2len) < (float)kMaserTauMin) *p.maser = 1u;
-            window_passes_pred<LANES, 2, true>(rl, lane, nwin, xl, hstep, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
+            window_passes_pred<LANES, 2, true>(rl, lane, nwin, xl, wv.x, wv.y, l2len, kv.x, kv.y, sj, sl);
         }
         if constexpr (kT8) {
             pj = sj;
