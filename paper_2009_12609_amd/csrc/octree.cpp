@@ -418,19 +418,41 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
         total += (int64_t)P.rec.size() / 2;
     }
     if (total > (int64_t)INT32_MAX * 64) return "octree: schedule too long";
-    out.rec.clear();
-    out.rec.reserve(2 * (size_t)total);
+    // the directions' records go to their offsets in one array, the parts
+    // copied in parallel (the copy is gigabytes)
+    out.dir_off.assign(nd, 0);
+    {
+        int64_t base = 0;
+        for (int q = 0; q < nd; ++q) {
+            out.dir_off[q] = base;
+            base += (int64_t)parts[q].rec.size() / 2;
+        }
+    }
+    out.rec.alloc(2 * (size_t)total);
+    {
+        std::vector<std::thread> cp;
+        const int nc = std::max(1, std::min(n_threads, nd));
+        for (int w = 0; w < nc; ++w)
+            cp.emplace_back([&, w]() {
+                for (int q = w; q < nd; q += nc) {
+                    Part& P = parts[q];
+                    if (!P.rec.empty())
+                        std::memcpy(out.rec.data() + 2 * (size_t)out.dir_off[q], P.rec.data(),
+                                    P.rec.size() * sizeof(uint32_t));
+                    std::vector<uint32_t>().swap(P.rec);
+                }
+            });
+        for (auto& t : cp) t.join();
+    }
     out.len64.clear();
     if (want_len64) out.len64.reserve((size_t)total);
     out.trees.clear();
     out.trees.reserve((size_t)nd * nroot);
     out.max_depth = 0;
     out.n_rays = 0;
-    out.dir_off.clear();
-    for (Part& P : parts) {
-        const int64_t base = (int64_t)out.rec.size() / 2;
-        out.dir_off.push_back(base);
-        out.rec.insert(out.rec.end(), P.rec.begin(), P.rec.end());
+    for (int q = 0; q < nd; ++q) {
+        Part& P = parts[q];
+        const int64_t base = out.dir_off[q];
         out.len64.insert(out.len64.end(), P.len64.begin(), P.len64.end());
         std::vector<double>().swap(P.len64);
         for (OctTreeRec T : P.trees) {
@@ -439,7 +461,6 @@ std::string octree_schedule(const OctModel& M, const std::vector<double>& dirs, 
         }
         out.max_depth = std::max(out.max_depth, P.max_depth);
         out.n_rays += P.n_rays;
-        std::vector<uint32_t>().swap(P.rec);
     }
     out.n_steps = total;
     out.dir_off.push_back(total);

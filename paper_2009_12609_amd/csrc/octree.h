@@ -3,12 +3,29 @@
 
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "miloc_internal.h"
 
 namespace miloc {
+
+// Host array of 32-bit words allocated without initialisation, for the
+// schedule's step records (gigabytes, filled in parallel).
+struct HostWords {
+    std::unique_ptr<uint32_t[]> p;
+    size_t n = 0;
+    void alloc(size_t k)
+    {
+        p.reset(k ? new uint32_t[k] : nullptr);
+        n = k;
+    }
+    uint32_t* data() { return p.get(); }
+    const uint32_t* data() const { return p.get(); }
+    size_t size() const { return n; }
+    uint32_t operator[](size_t i) const { return p[i]; }
+};
 
 // An octree in global cell numbering: level-0 root cells (z N + y) N + x
 // first, then each level in turn; child[g] is the global index of the first
@@ -28,7 +45,7 @@ std::string octree_from_levels(int N, int n_levels, const int64_t* n_cells_per_l
                                const int32_t* const* first_child, OctModel& out);
 
 struct OctSchedule {
-    std::vector<uint32_t> rec;        // 2 words per step
+    HostWords rec;                    // 2 words per step
     std::vector<double> len64;        // FP64 step lengths (only when asked for)
     std::vector<int64_t> cell_off;    // per cell: first entry of its steps in cell_steps (+ total)
     std::vector<uint32_t> cell_steps; // step indices grouped by cell, ascending (only when asked for)
