@@ -146,8 +146,7 @@ def load_library(path: Optional[str] = None):
     if _lib is None:
         p = path or LIB_PATH
         if not os.path.exists(p):
-            raise RuntimeError(f"{p} is missing: build it with paper_2009_12609_amd/build.py "
-                               "(or __graft_entry__.build())")
+            raise RuntimeError(f"{p} is missing: build it with python paper_2009_12609_amd/build.py")
         L = ctypes.CDLL(p)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -28,7 +28,7 @@ def test_header_declares_the_boundary():
 def test_library_exports_every_declared_symbol():
     import paper_2009_12609_amd as miloc
     if not os.path.exists(miloc.LIB_PATH):
-        pytest.fail("libmiloc.so not built (run __graft_entry__.build())")
+        pytest.fail("libmiloc.so not built (run python paper_2009_12609_amd/build.py)")
     lib = ctypes.CDLL(miloc.LIB_PATH)
     for name in declared_functions():
         assert hasattr(lib, name), name
