@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # The same vector units without packed FP32 (two FP32 lanes per instruction),
-# which this build's kernels do not use: 256 CUs x 4 SIMDs x 16 lanes x 2
+# which the library's kernels do not use: 256 CUs x 4 SIMDs x 16 lanes x 2
 # (FMA) x 2.4 GHz.
 FP32_UNPACKED_TFLOPS = 78.6
 # The paper's GPU-vs-one-CPU-core speed-ups, with the hardware it states.
@@ -528,7 +528,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
+        print("bench.py: the library runs on exactly one GPU; --gpus must be 1 "
               "(the multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
 
