@@ -1081,10 +1081,12 @@ __global__ __launch_bounds__(256) void gather3d_kernel(Gather3DArgs<T> p)
     }
     const size_t idx = (size_t)ia * p.st_a + (size_t)ib * p.st_b + (size_t)cm * p.st_m;
     double2* a = p.acc + idx * p.ntr_total + p.trans_offset + t0;
+    // the first axis group's gather writes the sums (adding to the zeros it
+    // replaces would give the same bits), the others add theirs
 #pragma unroll
     for (int q = 0; q < TILE; ++q) {
         if (q < nt) {
-            double2 v = a[q];
+            double2 v = p.overwrite ? make_double2(0.0, 0.0) : a[q];
             v.x += sj[q];
             v.y += sl[q];
             a[q] = v;

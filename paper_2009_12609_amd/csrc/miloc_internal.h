@@ -125,6 +125,7 @@ struct Gather3DArgs {
     const typename V2<T>::type* E;
     size_t e_tstride;
     double2* acc;                        // [nc][ntr_total]
+    int overwrite;                       // 1: the first gather of the launch's transitions writes the sums
 };
 
 template <typename T>

@@ -1122,9 +1122,12 @@ template <typename TT>
 miloc_status launch_gathers(miloc_ctx* c, int toff, int nt)
 {
     const int64_t stride[3] = {1, c->N, (int64_t)c->N * c->N};
+    bool first = true;                    // writes every cell's sums of these transitions
     for (int g = 0; g < 3; ++g) {
         if (c->qcount[g] == 0) continue;
         Gather3DArgs<TT> a{};
+        a.overwrite = first ? 1 : 0;
+        first = false;
         a.N = c->N;
         a.ntr = nt;
         a.trans_offset = toff;
@@ -1613,7 +1616,9 @@ miloc_status miloc_run(miloc_ctx* c, int max_iter, double tol, int use_ali, int*
         HIPCHK(c, ev_record(c, 0));
         HIPCHK(c, launch_prepare(c->stream, (int)nc, c->d_mol.as<MolDev>(), c->T, c->d_x.as<double>(),
                                  c->d_nmolLb.as<double>(), nullptr, c->d_ke.p, fp64));
-        HIPCHK(c, hipMemsetAsync(c->d_acc.p, 0, c->d_acc.bytes, c->stream));
+        // the regular-grid and octree gathers write every cell's sums; the 1D
+        // march adds into zeroed accumulators
+        if (c->kind != 3 && c->kind != 4) HIPCHK(c, hipMemsetAsync(c->d_acc.p, 0, c->d_acc.bytes, c->stream));
         HIPCHK(c, ev_record(c, 1));
         float t_march = 0, t_gather = 0;
         if (c->kind == 3) {
