@@ -2094,8 +2094,11 @@ __device__ __forceinline__ void block_max_to(double v, int bs, unsigned long lon
     if (((int)threadIdx.x % width) == 0 && bits != 0ull) atomicMax(dst, bits);
 }
 
+// Up to 10 levels two wavefronts per SIMD (at 10 levels the matrix and its
+// pivoting take ~270 registers: 256 and a few spills, 17% faster than one
+// wavefront); 11 and 12 levels keep the registers of one.
 template <int L>
-__global__ __launch_bounds__(256) void se_reg_kernel(SEArgs p)
+__global__ __launch_bounds__(256, (L <= 10 ? 2 : 1)) void se_reg_kernel(SEArgs p)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const double dmax = k < p.nc ? se_cell_reg<L>(p, k) : 0.0;
