@@ -1431,8 +1431,10 @@ __global__ __launch_bounds__(256) void march_oct_kernel(OctMarchArgs<T> p)
             const int nwin = as_int(wv.w);
             if (nwin > 0) {
                 // the unmasked FP32 passes may change every channel up to the
-                // reach: the span covers them whichever passes run
-                const int top = sizeof(T) == 4 && clo <= nch_reach ? clo + pass_reach<LANES>() : clo + nwin;
+                // reach, and a longer window is finished in a loop: the span
+                // covers both whichever passes run
+                constexpr int kR = pass_reach<LANES>();
+                const int top = sizeof(T) == 4 && clo <= nch_reach ? clo + (nwin > kR ? nwin : kR) : clo + nwin;
                 lo = clo < lo ? clo : lo;
                 hi = top > hi ? top : hi;
             }
@@ -2461,8 +2463,18 @@ hipError_t do_march_oct(hipStream_t s, const OctMarchArgs<T>& a, int groups, boo
     const size_t shm = (size_t)kGroupsPerBlock * a.ich * sizeof(T) +
                        (size_t)kGroupsPerBlock * LANES * (sizeof(T) == 4 && LANES == 8 ? 2 : 1) *
                            sizeof(typename V2<T>::type);
-    if (shm > 64 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipMemsetAsync(a.counter, 0, sizeof(unsigned long long), s);
+    // up to the 160 KB of LDS a workgroup may have (wide channel grids and
+    // FP64 vectors: fewer workgroups per CU)
+    if (shm > 163840) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    if (shm > 65536) {
+        e = accum ? hipFuncSetAttribute((const void*)march_oct_kernel<T, LANES, true, HF>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)
+                  : hipFuncSetAttribute((const void*)march_oct_kernel<T, LANES, false, HF>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    e = hipMemsetAsync(a.counter, 0, sizeof(unsigned long long), s);
     if (e != hipSuccess) return e;
     if (accum)
         hipLaunchKernelGGL((march_oct_kernel<T, LANES, true, HF>), dim3(blocks), dim3(256), shm, s, a);

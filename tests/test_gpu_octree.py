@@ -63,6 +63,25 @@ def test_octree_small_iterations(fp64, tol):
     ctx.close()
 
 
+@pytest.mark.parametrize("fp64,nch,tol", [(True, 256, 1e-10), (False, 600, 1e-5)])
+def test_octree_wide_vectors(fp64, nch, tol):
+    """Channel vectors whose workgroup needs more than 64 KB of LDS (FP64 at
+    256 channels, FP32 at 600): populations, J and Lambda per leaf against
+    the oracle over two iterations."""
+    w = oct_workload(nch=nch, n_refine=2)
+    print(f"[octree] wide vectors fp64={fp64} nch={nch} cells {w.model.n_cells_per_level}", flush=True)
+    lf = leaf_rows(w)
+    ref = oracle.run_oct(w.mol, w.model, w.spec, w.T_bg, 2)
+    ctx = make_ctx(w, fp64=fp64)
+    for it in range(2):
+        ctx.run(1)
+        assert_pops(ctx.populations()[lf], ref.history[it]["x"][lf], tol, f"octree wide it {it}")
+    J, Lam = ctx.radiation()
+    assert_radiation(J[:, lf], Lam[:, lf], ref.history[1]["J"][:, lf], ref.history[1]["Lam"][:, lf], fp64,
+                     "octree wide it 1")
+    ctx.close()
+
+
 def test_unrefined_octree_matches_regular_grid_on_gpu():
     """An octree with one level is the regular grid: the two device paths
     agree (to FP32 summation order)."""
